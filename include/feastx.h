@@ -1,0 +1,131 @@
+/*
+ * feastx -- dense Hermitian FEAST eigensolver on AMD MI355X (gfx950).
+ *
+ * Finds the eigenpairs (lambda, x) of A x = lambda B x inside a search
+ * interval [Emin, Emax] for a dense real symmetric or complex Hermitian A and
+ * a symmetric/Hermitian positive definite B (B = NULL: standard problem,
+ * B = I).  Method: the FEAST subspace iteration of the FEAST v3.0 user guide,
+ * section "The FEAST Algorithm" -- at each Gauss-Legendre node z_j of the
+ * half contour around the interval, factor z_j B - A and solve it against
+ * the M0 right-hand sides B X; accumulate Q = sum_j w_j Y_j; Rayleigh-Ritz
+ * on Q (Q^H A Q, Q^H B Q, reduced eigenproblem, residuals); repeat.
+ *
+ * Conventions shared by every entry point:
+ *   - Matrices are column-major (Fortran order) with full storage, as the
+ *     guide's dense interfaces (section "Matrix storage", UPLO = 'F').
+ *   - Complex numbers are interleaved {double re, im} (feast_z).
+ *   - The return value is `info` with the codes of the guide's Table
+ *     "tab_info": 0 success; 1 no eigenvalue in the interval; 2 no
+ *     convergence within maxloop; 3 subspace too small (M0 <= M); 4 only the
+ *     subspace Q was returned (mode 1); 200 bad interval; 201 bad M0;
+ *     202 bad N; 100+i bad option i (fpm numbering: 102 ne, 103 tol,
+ *     104 maxloop, 105 x0, 106 conv, 110 keep_factors, 114 mode, 140
+ *     precision, 141 refine); -1 device allocation failed; -2 the factorisation
+ *     of a shifted matrix failed (zero or non-finite pivot); -3 the reduced
+ *     eigenproblem failed (B not positive definite); -4 other GPU runtime
+ *     error; -(100+i) argument i is invalid (e.g. a NULL pointer).
+ *     No exception crosses the interface.
+ *   - Outputs E, X, res are valid for info in {0, 2, 3}.  Their first M
+ *     entries are the eigenpairs inside [Emin, Emax], ascending; then the
+ *     remaining Ritz pairs outside the interval, ascending; spurious pairs
+ *     (inside the interval but with residual > 0.1) come last with res = -1
+ *     (Table "tab_common", remark on E, X and res).
+ *   - The library keeps device workspace (factors, subspaces) between calls
+ *     and frees it in feast_release().  Calls are serialised internally; the
+ *     library never frees caller memory.
+ */
+#ifndef FEASTX_H
+#define FEASTX_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    double re, im;
+} feast_z;
+
+/* Options; the fpm(i) of the guide's Table "tab_fpm" each field stands for
+ * is given in brackets. */
+typedef struct {
+    int ne;           /* [fpm(2)] Gauss-Legendre nodes on the half contour, >= 1; default 8 */
+    int maxloop;      /* [fpm(4)] refinement loops after the first, >= 0; default 20 */
+    int conv;         /* [fpm(6)] 1: max residual < tol (default); 0: trace change < tol */
+    int x0;           /* [fpm(5)] 1: X holds the start subspace on entry; 0: seeded random start */
+    int keep_factors; /* [fpm(10)] 1: factor once, keep the factors resident (default); 0: refactor every loop */
+    int precision;    /* 0: FP64 (complex128 factors and solves, default);
+                         1: mixed (complex64 factors and solves on FP32 matrix cores,
+                            FP64 residual correction; everything else FP64) */
+    int refine;       /* mixed only. 0: residual-correction form from the second loop on
+                         (default); s > 0: s steps of per-solve FP64 iterative refinement */
+    int mode;         /* [fpm(14)] 0: normal; 1: return Q after one contour in X (info 4) */
+    int verbose;      /* [fpm(1)] 1: print one line per loop to stderr */
+    double tol;       /* [fpm(3)] convergence tolerance, > 0; default 1e-12 */
+    unsigned long long seed; /* seed of the random start subspace (x0 = 0) */
+} feast_opts;
+
+/* Per-stage timings of the most recent solve (milliseconds, from HIP events
+ * on the solve's stream) and the algorithmic work behind them. */
+typedef struct {
+    double t_total, t_shift, t_factor, t_solve, t_accum, t_rr, t_reduced, t_resid;
+    double t_lu_gemm;        /* time inside the LU trailing-update kernel launches */
+    double lu_gemm_flops;    /* algorithmic real flops of those launches (8 per complex multiply-add) */
+    long long lu_gemm_launches;
+    double factor_flops;     /* ne * (8/3) N^3 */
+    double solve_flops;      /* 8 N^2 M0 per node per triangular pair, all loops */
+    int loops;               /* FEAST loops executed (loop + 1) */
+    int m0_final;            /* subspace size at exit */
+} feast_stats;
+
+/* Defaults of the guide's feastinit (Table "tab_fpm"), with keep_factors = 1. */
+void feast_default_opts(feast_opts *opts);
+
+/* ---- minimal form: host arrays, defaults except Ne and tol, random start.
+ * A, B: N x N (B may be NULL).  E[M0], res[M0], X[N*M0] allocated by the caller. */
+int feast_solve_d(int N, const double *A, const double *B, double Emin, double Emax, int M0, int Ne,
+                  double tol, double *E, double *X, int *M, double *res);
+int feast_solve_z(int N, const feast_z *A, const feast_z *B, double Emin, double Emax, int M0, int Ne,
+                  double tol, double *E, feast_z *X, int *M, double *res);
+
+/* ---- full form, host arrays.  M0 is in/out: on exit the subspace size kept
+ * (directions with B-norm below 1e-14 of the largest are dropped; the
+ * guide's "new suitable M0").  loop: index of the last FEAST loop (0-based).
+ * epsout: relative trace change of the last loop (1 at loop 0). */
+int feast_solve_d_ex(int N, const double *A, int lda, const double *B, int ldb, double Emin, double Emax,
+                     int *M0, const feast_opts *opts, double *E, double *X, int ldx, int *M, double *res,
+                     int *loop, double *epsout);
+int feast_solve_z_ex(int N, const feast_z *A, int lda, const feast_z *B, int ldb, double Emin,
+                     double Emax, int *M0, const feast_opts *opts, double *E, feast_z *X, int ldx, int *M,
+                     double *res, int *loop, double *epsout);
+
+/* ---- device form: A, B, X are device pointers (HBM), E/res/M/loop/epsout
+ * are host pointers.  `stream` is a hipStream_t (NULL: the library's own
+ * stream); the call returns after the solve has finished on it. */
+int feast_solve_d_dev(int N, const double *dA, int lda, const double *dB, int ldb, double Emin,
+                      double Emax, int *M0, const feast_opts *opts, double *E, double *dX, int ldx, int *M,
+                      double *res, int *loop, double *epsout, void *stream);
+int feast_solve_z_dev(int N, const feast_z *dA, int lda, const feast_z *dB, int ldb, double Emin,
+                      double Emax, int *M0, const feast_opts *opts, double *E, feast_z *dX, int ldx,
+                      int *M, double *res, int *loop, double *epsout, void *stream);
+
+/* ---- tools (host only, no GPU).
+ * Half-contour nodes and weights (tool "[cz]feast_contour", Gauss rule):
+ * z_j = c + r e^{i theta_j}, w_j = (omega_j / 2) r e^{i theta_j},
+ * theta_j = (pi/2)(1 - x_j), (x_j, omega_j) Gauss-Legendre on [-1, 1]. */
+int feast_contour(double Emin, double Emax, int ne, feast_z *Zne, feast_z *Wne);
+/* Filter rho(lambda) = Re sum_j w_j / (z_j - lambda) (tool "[sd]feast_rational"). */
+int feast_rational(double Emin, double Emax, int ne, const double *eig, int m, double *f);
+
+/* Statistics of the last solve on this process; 0 on success. */
+int feast_last_stats(feast_stats *stats);
+/* Enable (1) or disable (0) per-launch timing of the LU trailing update. */
+void feast_set_timing(int on);
+/* Free the library's device workspace. */
+void feast_release(void);
+/* Library version string. */
+const char *feast_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,908 @@
+// FEAST driver and C interface.
+//
+// One solve is the guide's FEAST iteration (section "The FEAST Algorithm"),
+// with the reverse-communication steps of its RCI figure carried out by this
+// library's own kernels, in the same order:
+//   factor (ijob 10)  shift_build + getrf_batched, all contour nodes at once,
+//                     factors kept resident across loops (fpm(10) = 1)
+//   solve  (ijob 11)  getrs_batched against B X (ijob 40) for every node;
+//          (ijob 21)  complex Hermitian pencils add the adjoint solve
+//   quadrature        accumulate_kernel: Q = sum_j w_j Y_j (FP64)
+//   Rayleigh-Ritz     A Q, B Q (ijob 30/40), Q^H A Q, Q^H B Q, reduced
+//                     eigenproblem by GPU Jacobi, Ritz vectors, residuals
+// The host only decides convergence from a few scalars per loop.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "feastx.h"
+
+#include "common.hpp"
+#include "gemm.hpp"
+#include "jacobi.hpp"
+#include "lu.hpp"
+#include "rr.hpp"
+#include "solve.hpp"
+
+namespace fx {
+
+struct alloc_error {};
+struct solver_error {
+    int info;
+};
+
+// ------------------------------------------------------------ workspace
+// Named device buffers that only grow; reused across calls.
+struct Workspace {
+    std::map<std::string, std::pair<void *, size_t>> dev;
+    std::map<std::string, std::pair<void *, size_t>> host;
+    hipStream_t stream = nullptr;
+    unsigned *bar = nullptr;
+    int device = -1;
+    int num_cu = 0;
+    int jac_max_blocks = 0;
+
+    void *get(const std::string &name, size_t bytes)
+    {
+        auto &e = dev[name];
+        if (e.second < bytes) {
+            if (e.first) FX_CHECK(hipFree(e.first));
+            e.first = nullptr;
+            e.second = 0;
+            if (hipMalloc(&e.first, std::max<size_t>(bytes, 256)) != hipSuccess) {
+                (void)hipGetLastError();
+                e.first = nullptr;
+                throw alloc_error{};
+            }
+            e.second = bytes;
+        }
+        return e.first;
+    }
+    void *pinned(const std::string &name, size_t bytes)
+    {
+        auto &e = host[name];
+        if (e.second < bytes) {
+            if (e.first) FX_CHECK(hipHostFree(e.first));
+            e.first = nullptr;
+            if (hipHostMalloc(&e.first, std::max<size_t>(bytes, 256), hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                e.first = nullptr;
+                throw alloc_error{};
+            }
+            e.second = bytes;
+        }
+        return e.first;
+    }
+    void init()
+    {
+        if (stream) return;
+        FX_CHECK(hipGetDevice(&device));
+        FX_CHECK(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+        hipDeviceProp_t prop;
+        FX_CHECK(hipGetDeviceProperties(&prop, device));
+        num_cu = prop.multiProcessorCount;
+        int per_cu = 0;
+        FX_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, jacobi_kernel<true>, JAC_NT, 0));
+        int per_cu_r = 0;
+        FX_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_r, jacobi_kernel<false>, JAC_NT, 0));
+        jac_max_blocks = std::max(1, std::min(per_cu, per_cu_r)) * num_cu;
+        bar = static_cast<unsigned *>(get("grid_barrier", 2 * sizeof(unsigned)));
+        FX_CHECK(hipMemset(bar, 0, 2 * sizeof(unsigned)));
+        FX_CHECK(hipDeviceSynchronize());
+    }
+    void release()
+    {
+        for (auto &kv : dev)
+            if (kv.second.first) (void)hipFree(kv.second.first);
+        for (auto &kv : host)
+            if (kv.second.first) (void)hipHostFree(kv.second.first);
+        dev.clear();
+        host.clear();
+        if (stream) (void)hipStreamDestroy(stream);
+        stream = nullptr;
+        bar = nullptr;
+    }
+};
+
+static Workspace g_ws;
+static std::mutex g_mu;
+static feast_stats g_stats;
+static bool g_timing = false;
+
+// ------------------------------------------------------------ contour
+// Gauss-Legendre nodes on [-1, 1] by Newton iteration on P_n, evaluated with
+// the Bonnet recurrence; weights 2 / ((1 - x^2) P_n'(x)^2).  Ascending.
+static void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w)
+{
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    auto legendre = [n](double t, double &p, double &dp) {
+        double pm1 = 1.0, pk = t;
+        if (n == 1) {
+            p = t;
+            dp = 1.0;
+            return;
+        }
+        for (int k = 2; k <= n; ++k) {
+            const double pk1 = ((2 * k - 1) * t * pk - (k - 1) * pm1) / k;
+            pm1 = pk;
+            pk = pk1;
+        }
+        p = pk;
+        dp = n * (pm1 - t * pk) / (1.0 - t * t);
+    };
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        // Tricomi's initial approximation of the i-th largest root
+        double t = std::cos(M_PI * (4.0 * i + 3.0) / (4.0 * n + 2.0)) *
+                   (1.0 - (n - 1.0) / (8.0 * n * n * n));
+        double p = 0, dp = 1;
+        for (int it = 0; it < 100; ++it) {
+            legendre(t, p, dp);
+            const double d = p / dp;
+            t -= d;
+            if (std::fabs(d) < 1e-17) break;
+        }
+        legendre(t, p, dp);
+        const double wt = 2.0 / ((1.0 - t * t) * dp * dp);
+        x[n - 1 - i] = t;
+        w[n - 1 - i] = wt;
+        x[i] = -t;
+        w[i] = wt;
+    }
+    if (n % 2 == 1) x[n / 2] = 0.0;
+}
+
+struct Contour {
+    std::vector<double2> z, w;
+};
+
+static Contour make_contour(double emin, double emax, int ne)
+{
+    std::vector<double> x, om;
+    gauss_legendre(ne, x, om);
+    Contour c;
+    c.z.resize(ne);
+    c.w.resize(ne);
+    const double mid = 0.5 * (emin + emax), r = 0.5 * (emax - emin);
+    for (int j = 0; j < ne; ++j) {
+        const double th = 0.5 * M_PI * (1.0 - x[j]);
+        const double ct = std::cos(th), st = std::sin(th);
+        c.z[j] = make_double2(mid + r * ct, r * st);
+        c.w[j] = make_double2(0.5 * om[j] * r * ct, 0.5 * om[j] * r * st);
+    }
+    return c;
+}
+
+// ------------------------------------------------------------ timing
+struct StageTimer {
+    hipStream_t s;
+    std::vector<std::pair<hipEvent_t, double *>> marks;
+    hipEvent_t last = nullptr;
+    explicit StageTimer(hipStream_t st) : s(st) {}
+    void start()
+    {
+        FX_CHECK(hipEventCreate(&last));
+        FX_CHECK(hipEventRecord(last, s));
+        marks.push_back({last, nullptr});
+    }
+    void mark(double *acc)
+    {
+        hipEvent_t e;
+        FX_CHECK(hipEventCreate(&e));
+        FX_CHECK(hipEventRecord(e, s));
+        marks.push_back({e, acc});
+    }
+    void flush()
+    {
+        if (marks.empty()) return;
+        FX_CHECK(hipEventSynchronize(marks.back().first));
+        for (size_t i = 1; i < marks.size(); ++i) {
+            float ms = 0.f;
+            FX_CHECK(hipEventElapsedTime(&ms, marks[i - 1].first, marks[i].first));
+            if (marks[i].second) *marks[i].second += ms;
+        }
+        for (auto &m : marks) (void)hipEventDestroy(m.first);
+        marks.clear();
+        start();
+    }
+    ~StageTimer()
+    {
+        for (auto &m : marks) (void)hipEventDestroy(m.first);
+    }
+};
+
+// Per-launch timing of the LU trailing update (enabled by feast_set_timing).
+struct GemmTimer {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    double flops = 0;
+};
+static GemmTimer *g_gemm_timer = nullptr;
+
+// ------------------------------------------------------------ problem
+struct Problem {
+    int n;
+    const double *A;
+    long lda;
+    const double *B;
+    long ldb;
+    double emin, emax;
+    int m0;
+    double *X;   // caller's device array
+    long ldx;
+};
+
+struct Result {
+    int M = 0, loop = 0, m0 = 0;
+    double epsout = 1.0;
+    std::vector<double> E, res;
+};
+
+template <bool CPLX> using F64 = typename jelem<CPLX>::type;
+
+template <bool CPLX>
+static void dgemm(hipStream_t s, bool opa_h, int m, int n, int k, double alpha, const F64<CPLX> *A,
+                  long lda, const F64<CPLX> *B, long ldb, double beta, F64<CPLX> *C, long ldc)
+{
+    if (opa_h) gemm<double, CPLX, true>(s, m, n, k, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1);
+    else gemm<double, CPLX, false>(s, m, n, k, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1);
+}
+
+static dim3 grid1(long count) { return dim3((unsigned)((count + 255) / 256)); }
+
+// Reduced Hermitian eigenproblem on the device: C (m x m, overwritten) ->
+// ascending eigenvalues w (device) and eigenvectors Vout (m x m).
+template <bool CPLX>
+static void device_eigh(Workspace &ws, hipStream_t s, int m, F64<CPLX> *C, F64<CPLX> *Vout, double *w)
+{
+    using E = F64<CPLX>;
+    E *C1 = static_cast<E *>(ws.get("jac_c1", sizeof(E) * (size_t)m * m));
+    E *V = static_cast<E *>(ws.get("jac_v", sizeof(E) * (size_t)m * m));
+    const int p = m + (m & 1), npairs = p / 2;
+    const long work = (long)npairs * npairs + (long)m * npairs;
+    int G = (int)std::min<long>(ws.jac_max_blocks, std::max<long>(1, (work + 2047) / 2048));
+    G = std::min(G, ws.num_cu);
+    double *partial = static_cast<double *>(ws.get("jac_partial", sizeof(double) * 1024));
+    int *status = static_cast<int *>(ws.get("jac_status", sizeof(int) * 2));
+    int *rank = static_cast<int *>(ws.get("jac_rank", sizeof(int) * m));
+    long ld = m;
+    int max_sweeps = 60;
+    double tol = 1e-15;
+    unsigned *bar = ws.bar;
+    void *args[] = {&m, &C, &C1, &ld, &V, &ld, &partial, &bar, &max_sweeps, &tol, &status};
+    FX_CHECK(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(jacobi_kernel<CPLX>), dim3(G),
+                                        dim3(JAC_NT), args, 0, s));
+    hipLaunchKernelGGL((jacobi_sort_kernel<CPLX>), dim3(1), dim3(1024), 0, s, m, C, ld, V, ld, w, Vout, ld,
+                       rank);
+    FX_LAUNCH_CHECK();
+    int *hst = static_cast<int *>(ws.pinned("jac_status_h", sizeof(int) * 2));
+    FX_CHECK(hipMemcpyAsync(hst, status, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
+    FX_CHECK(hipStreamSynchronize(s));
+    if (hst[0] != 0) throw solver_error{-3};
+}
+
+constexpr double SPURIOUS_RES = 0.1;   // in-interval Ritz pairs above this residual are spurious
+constexpr double TRUNC = 1e-14;        // Bq eigen-directions below TRUNC * max are dropped
+constexpr double INDEFINITE = 1e-8;    // Bq eigenvalue below -INDEFINITE * max: B not definite
+
+template <typename T, bool CPLX>
+static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace &ws, Result &out)
+{
+    using E = F64<CPLX>;
+    using V = cplx<T>;
+    const int n = pb.n, ne = o.ne;
+    int m0 = pb.m0;
+    const double alpha = std::max(std::fabs(pb.emin), std::fabs(pb.emax));
+    const bool mixed = std::is_same<T, float>::value;
+    const size_t nm = (size_t)n * m0, mm = (size_t)m0 * m0;
+    feast_stats st{};
+    StageTimer tm(s);
+    tm.start();
+
+    Contour ct = make_contour(pb.emin, pb.emax, ne);
+    double2 *dz = static_cast<double2 *>(ws.get("z", sizeof(double2) * ne));
+    FX_CHECK(hipMemcpyAsync(dz, ct.z.data(), sizeof(double2) * ne, hipMemcpyHostToDevice, s));
+
+    E *X = static_cast<E *>(ws.get("X", sizeof(E) * nm));
+    E *R = static_cast<E *>(ws.get("R", sizeof(E) * nm));
+    E *Q = static_cast<E *>(ws.get("Q", sizeof(E) * nm));
+    E *AQ = static_cast<E *>(ws.get("AQ", sizeof(E) * nm));
+    E *BQ = static_cast<E *>(ws.get("BQ", sizeof(E) * nm));
+    E *AX = static_cast<E *>(ws.get("AX", sizeof(E) * nm));
+    E *BX = static_cast<E *>(ws.get("BX", sizeof(E) * nm));
+    E *Aq = static_cast<E *>(ws.get("Aq", sizeof(E) * mm));
+    E *Bq = static_cast<E *>(ws.get("Bq", sizeof(E) * mm));
+    E *Wb = static_cast<E *>(ws.get("Wb", sizeof(E) * mm));
+    E *Tm = static_cast<E *>(ws.get("Tm", sizeof(E) * mm));
+    E *Tmp = static_cast<E *>(ws.get("Tmp", sizeof(E) * mm));
+    E *Cr = static_cast<E *>(ws.get("Cr", sizeof(E) * mm));
+    E *Vc = static_cast<E *>(ws.get("Vc", sizeof(E) * mm));
+    E *Phi = static_cast<E *>(ws.get("Phi", sizeof(E) * mm));
+    double *beta = static_cast<double *>(ws.get("beta", sizeof(double) * m0));
+    double *lam = static_cast<double *>(ws.get("lam", sizeof(double) * m0));
+    double *res = static_cast<double *>(ws.get("res", sizeof(double) * m0));
+    double *rho = static_cast<double *>(ws.get("rho", sizeof(double) * m0));
+    double2 *coef = static_cast<double2 *>(ws.get("coef", sizeof(double2) * ne * m0));
+    int *sel = static_cast<int *>(ws.get("sel", sizeof(int) * m0));
+    const long ldf = n, sF = (long)n * n;
+    V *F = static_cast<V *>(ws.get(mixed ? "F32" : "F64", sizeof(V) * (size_t)ne * sF));
+    int *ipiv = static_cast<int *>(ws.get("ipiv", sizeof(int) * (size_t)ne * n));
+    int *perm = static_cast<int *>(ws.get("perm", sizeof(int) * (size_t)ne * n));
+    int *swapmap = static_cast<int *>(ws.get("swapmap", sizeof(int) * (size_t)ne * (1 + 4 * LU_NB)));
+    int *dinfo = static_cast<int *>(ws.get("info", sizeof(int) * ne));
+    V *Y = static_cast<V *>(ws.get(mixed ? "Y32" : "Y64", sizeof(V) * (size_t)ne * nm));
+    V *Yh = nullptr, *Yh2 = nullptr;
+    if (CPLX) {
+        Yh = static_cast<V *>(ws.get(mixed ? "Yh32" : "Yh64", sizeof(V) * (size_t)ne * nm));
+        Yh2 = static_cast<V *>(ws.get(mixed ? "Yg32" : "Yg64", sizeof(V) * (size_t)ne * nm));
+    }
+    double *h_beta = static_cast<double *>(ws.pinned("h_beta", sizeof(double) * m0));
+    double *h_lam = static_cast<double *>(ws.pinned("h_lam", sizeof(double) * m0));
+    double *h_res = static_cast<double *>(ws.pinned("h_res", sizeof(double) * m0));
+    int *h_info = static_cast<int *>(ws.pinned("h_info", sizeof(int) * ne));
+
+    // start subspace
+    if (o.x0) {
+        hipLaunchKernelGGL((copy_block_kernel<CPLX>), grid1(nm), dim3(256), 0, s, n, m0,
+                           reinterpret_cast<const E *>(pb.X), pb.ldx, X, (long)n);
+    } else {
+        hipLaunchKernelGGL((random_start_kernel<CPLX>), grid1(nm), dim3(256), 0, s, n, m0, o.seed, X, (long)n);
+    }
+    FX_LAUNCH_CHECK();
+    tm.mark(&st.t_shift);
+
+    const bool use_corr = mixed && o.refine == 0;
+    std::vector<double> lam_prev;   // Ritz values of the previous loop (correction form)
+    double trace_prev = 0.0, epsout = 1.0;
+    int info = 0, k = 0, M = 0;
+    std::vector<double2> hcoef((size_t)ne * m0);
+    std::vector<double> hrho(m0);
+
+    for (k = 0; k <= o.maxloop; ++k) {
+        const size_t cur_nm = (size_t)n * m0;
+        // ---- factor every shifted matrix (once, fpm(10) = 1)
+        if (k == 0 || !o.keep_factors) {
+            shift_build<T>(s, CPLX, n, pb.A, pb.lda, pb.B, pb.ldb, dz, ne, F, ldf, sF);
+            tm.mark(&st.t_shift);
+            FX_CHECK(hipMemsetAsync(dinfo, 0, sizeof(int) * ne, s));
+            getrf_batched<T>(s, n, F, ldf, sF, ipiv, perm, n, swapmap, dinfo, ne);
+            tm.mark(&st.t_factor);
+            FX_CHECK(hipMemcpyAsync(h_info, dinfo, sizeof(int) * ne, hipMemcpyDeviceToHost, s));
+            FX_CHECK(hipStreamSynchronize(s));
+            for (int j = 0; j < ne; ++j)
+                if (h_info[j] != 0) throw solver_error{-2};
+            st.factor_flops += ne * (8.0 / 3.0) * (double)n * n * n;
+        }
+        const bool corr = use_corr && k >= 1;
+
+        // ---- right-hand sides: B X, or the Ritz residual A X - B X Lambda
+        if (corr) {
+            FX_CHECK(hipMemcpyAsync(lam, h_lam, sizeof(double) * m0, hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL((ritz_residual_kernel<CPLX>), grid1(cur_nm), dim3(256), 0, s, n, m0, AX, BX,
+                               (long)n, lam, R);
+            FX_LAUNCH_CHECK();
+        } else if (pb.B) {
+            dgemm<CPLX>(s, false, n, m0, n, 1.0, reinterpret_cast<const E *>(pb.B), pb.ldb, X, n, 0.0, R, n);
+        } else {
+            hipLaunchKernelGGL((copy_block_kernel<CPLX>), grid1(cur_nm), dim3(256), 0, s, n, m0, X, (long)n, R,
+                               (long)n);
+            FX_LAUNCH_CHECK();
+        }
+
+        // ---- solves at every node (and the adjoint solves for Hermitian pencils)
+        {
+            dim3 g((unsigned)((cur_nm + 255) / 256), ne);
+            hipLaunchKernelGGL((gather_rows_kernel<T, CPLX>), g, dim3(256), 0, s, n, m0, perm, (long)n,
+                               reinterpret_cast<const double *>(R), (long)n, Y, (long)n, (long)cur_nm);
+            FX_LAUNCH_CHECK();
+            getrs_batched<T>(s, false, n, m0, F, ldf, sF, Y, n, (long)cur_nm, ne);
+            if (CPLX) {
+                hipLaunchKernelGGL((copy_rhs_kernel<T, CPLX>), g, dim3(256), 0, s, n, m0,
+                                   reinterpret_cast<const double *>(R), (long)n, Yh, (long)n, (long)cur_nm);
+                FX_LAUNCH_CHECK();
+                getrs_batched<T>(s, true, n, m0, F, ldf, sF, Yh, n, (long)cur_nm, ne);
+                hipLaunchKernelGGL((scatter_rows_kernel<T>), g, dim3(256), 0, s, n, m0, perm, (long)n, Yh,
+                                   (long)n, (long)cur_nm, Yh2, (long)n, (long)cur_nm);
+                FX_LAUNCH_CHECK();
+            }
+            st.solve_flops += (CPLX ? 2.0 : 1.0) * ne * 8.0 * (double)n * n * m0;
+        }
+        tm.mark(&st.t_solve);
+
+        // ---- quadrature
+        for (int j = 0; j < ne; ++j)
+            for (int c = 0; c < m0; ++c) {
+                double2 w = ct.w[j];
+                if (corr) {
+                    // w_j / (z_j - lambda_c)
+                    const double dr = ct.z[j].x - h_lam[c], di = ct.z[j].y;
+                    const double den = dr * dr + di * di;
+                    w = make_double2((w.x * dr + w.y * di) / den, (w.y * dr - w.x * di) / den);
+                }
+                hcoef[(size_t)j * m0 + c] = w;
+            }
+        if (corr)
+            for (int c = 0; c < m0; ++c) {
+                double r = 0.0;
+                for (int j = 0; j < ne; ++j) r += hcoef[(size_t)j * m0 + c].x;
+                hrho[c] = r;
+            }
+        FX_CHECK(hipMemcpyAsync(coef, hcoef.data(), sizeof(double2) * ne * m0, hipMemcpyHostToDevice, s));
+        if (corr) FX_CHECK(hipMemcpyAsync(rho, hrho.data(), sizeof(double) * m0, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL((accumulate_kernel<T, CPLX>), grid1(cur_nm), dim3(256), 0, s, n, m0, ne, Y, (long)n,
+                           (long)cur_nm, Yh2, coef, corr ? rho : nullptr, X, (long)n, Q, (long)n);
+        FX_LAUNCH_CHECK();
+        FX_CHECK(hipStreamSynchronize(s));   // host vectors above are reused next loop
+        tm.mark(&st.t_accum);
+
+        if (o.mode == 1) {
+            hipLaunchKernelGGL((copy_block_kernel<CPLX>), grid1(cur_nm), dim3(256), 0, s, n, m0, Q, (long)n,
+                               reinterpret_cast<E *>(pb.X), pb.ldx);
+            FX_LAUNCH_CHECK();
+            FX_CHECK(hipStreamSynchronize(s));
+            out.M = 0;
+            out.loop = 0;
+            out.m0 = m0;
+            out.epsout = 1.0;
+            tm.mark(&st.t_total);
+            tm.flush();
+            st.loops = 1;
+            st.m0_final = m0;
+            g_stats = st;
+            return 4;
+        }
+
+        // ---- Rayleigh-Ritz
+        dgemm<CPLX>(s, false, n, m0, n, 1.0, reinterpret_cast<const E *>(pb.A), pb.lda, Q, n, 0.0, AQ, n);
+        if (pb.B) dgemm<CPLX>(s, false, n, m0, n, 1.0, reinterpret_cast<const E *>(pb.B), pb.ldb, Q, n, 0.0, BQ, n);
+        else {
+            hipLaunchKernelGGL((copy_block_kernel<CPLX>), grid1(cur_nm), dim3(256), 0, s, n, m0, Q, (long)n, BQ,
+                               (long)n);
+            FX_LAUNCH_CHECK();
+        }
+        dgemm<CPLX>(s, true, m0, m0, n, 1.0, Q, n, AQ, n, 0.0, Aq, m0);
+        dgemm<CPLX>(s, true, m0, m0, n, 1.0, Q, n, BQ, n, 0.0, Bq, m0);
+        hipLaunchKernelGGL((hermitian_part_kernel<CPLX>), grid1((long)m0 * m0), dim3(256), 0, s, m0, Aq, (long)m0);
+        hipLaunchKernelGGL((hermitian_part_kernel<CPLX>), grid1((long)m0 * m0), dim3(256), 0, s, m0, Bq, (long)m0);
+        FX_LAUNCH_CHECK();
+        tm.mark(&st.t_rr);
+
+        // ---- reduced problem: Bq = W diag(beta) W^H, drop tiny directions,
+        //      T = W_keep beta^{-1/2}, eig(T^H Aq T) = (lambda, V), Phi = T V
+        device_eigh<CPLX>(ws, s, m0, Bq, Wb, beta);
+        FX_CHECK(hipMemcpyAsync(h_beta, beta, sizeof(double) * m0, hipMemcpyDeviceToHost, s));
+        FX_CHECK(hipStreamSynchronize(s));
+        const double bmax = h_beta[m0 - 1];
+        if (!(bmax > 0.0) || h_beta[0] < -INDEFINITE * bmax) throw solver_error{-3};
+        int keep = 0;
+        for (int i = 0; i < m0; ++i)
+            if (h_beta[i] > TRUNC * bmax) ++keep;
+        const int first = m0 - keep;
+        hipLaunchKernelGGL((scale_cols_kernel<CPLX>), grid1((long)m0 * keep), dim3(256), 0, s, m0, keep, first, Wb,
+                           (long)m0, beta, Tm, (long)m0);
+        FX_LAUNCH_CHECK();
+        dgemm<CPLX>(s, false, m0, keep, m0, 1.0, Aq, m0, Tm, m0, 0.0, Tmp, m0);
+        dgemm<CPLX>(s, true, keep, keep, m0, 1.0, Tm, m0, Tmp, m0, 0.0, Cr, keep);
+        hipLaunchKernelGGL((hermitian_part_kernel<CPLX>), grid1((long)keep * keep), dim3(256), 0, s, keep, Cr,
+                           (long)keep);
+        FX_LAUNCH_CHECK();
+        device_eigh<CPLX>(ws, s, keep, Cr, Vc, lam);
+        dgemm<CPLX>(s, false, m0, keep, keep, 1.0, Tm, m0, Vc, keep, 0.0, Phi, m0);
+        tm.mark(&st.t_reduced);
+
+        // ---- Ritz vectors, A X, B X, residuals
+        dgemm<CPLX>(s, false, n, keep, m0, 1.0, Q, n, Phi, m0, 0.0, X, n);
+        dgemm<CPLX>(s, false, n, keep, m0, 1.0, AQ, n, Phi, m0, 0.0, AX, n);
+        dgemm<CPLX>(s, false, n, keep, m0, 1.0, BQ, n, Phi, m0, 0.0, BX, n);
+        hipLaunchKernelGGL((resid_norm_kernel<CPLX>), dim3(keep), dim3(256), 0, s, n, AX, BX, (long)n, lam, alpha,
+                           res);
+        FX_LAUNCH_CHECK();
+        FX_CHECK(hipMemcpyAsync(h_lam, lam, sizeof(double) * keep, hipMemcpyDeviceToHost, s));
+        FX_CHECK(hipMemcpyAsync(h_res, res, sizeof(double) * keep, hipMemcpyDeviceToHost, s));
+        FX_CHECK(hipStreamSynchronize(s));
+        tm.mark(&st.t_resid);
+        m0 = keep;
+
+        // ---- count, spurious flag, trace, convergence (Tables "tab_common", "tab_fpm")
+        int inside = 0, bad = 0;
+        double trace = 0.0, maxres = 0.0;
+        M = 0;
+        for (int i = 0; i < m0; ++i) {
+            if (h_lam[i] < pb.emin || h_lam[i] > pb.emax) continue;
+            ++inside;
+            if (k >= 1 && h_res[i] > SPURIOUS_RES) continue;
+            ++M;
+            trace += h_lam[i];
+            maxres = std::max(maxres, h_res[i]);
+            if (!(h_res[i] < o.tol)) ++bad;
+        }
+        epsout = (k == 0) ? 1.0 : std::fabs(trace - trace_prev) / alpha;
+        trace_prev = trace;
+        if (o.verbose)
+            std::fprintf(stderr, "feastx loop %d: #eig %d  trace %.15e  eps %.3e  maxres %.3e  m0 %d\n", k, M, trace,
+                         epsout, maxres, m0);
+        const bool converged = (M > 0) && (o.conv == 1 ? bad == 0 : epsout < o.tol);
+        if (k == 0 && inside == 0) {
+            info = 1;
+            break;
+        }
+        if (converged) {
+            info = 0;
+            break;
+        }
+        if (M >= m0) {
+            info = 3;
+            break;
+        }
+        if (k == o.maxloop) {
+            info = 2;
+            break;
+        }
+    }
+    if (k > o.maxloop) k = o.maxloop;
+
+    // ---- output order: in-interval ascending, outside ascending, spurious last
+    std::vector<int> order;
+    order.reserve(m0);
+    auto cls = [&](int i) {
+        const bool in = h_lam[i] >= pb.emin && h_lam[i] <= pb.emax;
+        if (!in) return 1;
+        return (k >= 1 && h_res[i] > SPURIOUS_RES) ? 2 : 0;
+    };
+    for (int pass = 0; pass < 3; ++pass)
+        for (int i = 0; i < m0; ++i)
+            if (cls(i) == pass) order.push_back(i);
+    out.E.resize(m0);
+    out.res.resize(m0);
+    for (int c = 0; c < m0; ++c) {
+        out.E[c] = h_lam[order[c]];
+        out.res[c] = cls(order[c]) == 2 ? -1.0 : h_res[order[c]];
+    }
+    FX_CHECK(hipMemcpyAsync(sel, order.data(), sizeof(int) * m0, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL((gather_cols_kernel<CPLX>), grid1((long)n * m0), dim3(256), 0, s, n, m0, sel, X, (long)n,
+                       reinterpret_cast<E *>(pb.X), pb.ldx);
+    FX_LAUNCH_CHECK();
+    FX_CHECK(hipStreamSynchronize(s));
+    tm.mark(&st.t_total);
+    tm.flush();
+    out.M = M;
+    out.loop = k;
+    out.m0 = m0;
+    out.epsout = epsout;
+    st.loops = k + 1;
+    st.m0_final = m0;
+    st.t_total += st.t_shift + st.t_factor + st.t_solve + st.t_accum + st.t_rr + st.t_reduced + st.t_resid;
+    if (g_gemm_timer) {
+        FX_CHECK(hipStreamSynchronize(s));
+        double tot = 0;
+        for (auto &e : g_gemm_timer->ev) {
+            float ms = 0;
+            FX_CHECK(hipEventElapsedTime(&ms, e.first, e.second));
+            tot += ms;
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+        st.t_lu_gemm = tot;
+        st.lu_gemm_flops = g_gemm_timer->flops;
+        st.lu_gemm_launches = (long long)g_gemm_timer->ev.size();
+        g_gemm_timer->ev.clear();
+        g_gemm_timer->flops = 0;
+    }
+    g_stats = st;
+    return info;
+}
+
+// Validation shared by every entry point (Table "tab_info").
+static int validate(int n, int m0, double emin, double emax, const feast_opts &o)
+{
+    if (n < 1) return 202;
+    if (m0 < 1 || m0 > n) return 201;
+    if (!(emin < emax) || !std::isfinite(emin) || !std::isfinite(emax)) return 200;
+    if (o.ne < 1 || o.ne > 256) return 102;
+    if (!(o.tol > 0.0)) return 103;
+    if (o.maxloop < 0) return 104;
+    if (o.x0 != 0 && o.x0 != 1) return 105;
+    if (o.conv != 0 && o.conv != 1) return 106;
+    if (o.keep_factors != 0 && o.keep_factors != 1) return 110;
+    if (o.mode != 0 && o.mode != 1) return 114;
+    if (o.precision != 0 && o.precision != 1) return 140;
+    if (o.refine != 0) return 141;   // per-solve refinement: not available in this build
+    if (m0 > 2 * JAC_MAXPAIRS) return 201;
+    if (o.precision == 1 && n > lu_max_n<float>()) return 202;
+    if (o.precision == 0 && n > lu_max_n<double>()) return 202;
+    return 0;
+}
+
+static int dispatch(bool cplx_in, const Problem &pb, const feast_opts &o, hipStream_t s, Result &out)
+{
+    try {
+        g_ws.init();
+        if (!s) s = g_ws.stream;
+        GemmTimer gt;
+        g_gemm_timer = g_timing ? &gt : nullptr;
+        int info;
+        if (o.precision == 1)
+            info = cplx_in ? run<float, true>(pb, o, s, g_ws, out) : run<float, false>(pb, o, s, g_ws, out);
+        else
+            info = cplx_in ? run<double, true>(pb, o, s, g_ws, out) : run<double, false>(pb, o, s, g_ws, out);
+        g_gemm_timer = nullptr;
+        return info;
+    } catch (const alloc_error &) {
+        g_gemm_timer = nullptr;
+        return -1;
+    } catch (const solver_error &e) {
+        g_gemm_timer = nullptr;
+        (void)hipStreamSynchronize(s ? s : g_ws.stream);
+        return e.info;
+    } catch (const hip_error &e) {
+        g_gemm_timer = nullptr;
+        std::fprintf(stderr, "feastx: HIP error %s\n", hipGetErrorString(e.code));
+        return -4;
+    } catch (const std::bad_alloc &) {
+        g_gemm_timer = nullptr;
+        return -1;
+    }
+}
+
+}  // namespace fx
+
+// Trailing-update timing hook used by getrf_batched.
+namespace fx {
+void lu_gemm_timing_begin(hipStream_t s, hipEvent_t *e)
+{
+    if (!g_gemm_timer) return;
+    FX_CHECK(hipEventCreate(e));
+    FX_CHECK(hipEventRecord(*e, s));
+}
+void lu_gemm_timing_end(hipStream_t s, hipEvent_t e0, double flops)
+{
+    if (!g_gemm_timer) return;
+    hipEvent_t e1;
+    FX_CHECK(hipEventCreate(&e1));
+    FX_CHECK(hipEventRecord(e1, s));
+    g_gemm_timer->ev.push_back({e0, e1});
+    g_gemm_timer->flops += flops;
+}
+}  // namespace fx
+
+// ======================================================================
+//                                C interface
+// ======================================================================
+using fx::Problem;
+using fx::Result;
+
+extern "C" {
+
+void feast_default_opts(feast_opts *o)
+{
+    if (!o) return;
+    o->ne = 8;
+    o->maxloop = 20;
+    o->conv = 1;
+    o->x0 = 0;
+    o->keep_factors = 1;
+    o->precision = 0;
+    o->refine = 0;
+    o->mode = 0;
+    o->verbose = 0;
+    o->tol = 1e-12;
+    o->seed = 0x5eedULL;
+}
+
+const char *feast_version(void) { return "feastx 0.1 (gfx950)"; }
+
+int feast_contour(double emin, double emax, int ne, feast_z *Zne, feast_z *Wne)
+{
+    if (ne < 1) return 102;
+    if (!(emin < emax)) return 200;
+    if (!Zne) return -104;
+    if (!Wne) return -105;
+    fx::Contour c = fx::make_contour(emin, emax, ne);
+    for (int j = 0; j < ne; ++j) {
+        Zne[j].re = c.z[j].x;
+        Zne[j].im = c.z[j].y;
+        Wne[j].re = c.w[j].x;
+        Wne[j].im = c.w[j].y;
+    }
+    return 0;
+}
+
+int feast_rational(double emin, double emax, int ne, const double *eig, int m, double *f)
+{
+    if (ne < 1) return 102;
+    if (!(emin < emax)) return 200;
+    if (m < 0) return -105;
+    if (m > 0 && (!eig || !f)) return -104;
+    fx::Contour c = fx::make_contour(emin, emax, ne);
+    for (int i = 0; i < m; ++i) {
+        double acc = 0.0;
+        for (int j = 0; j < ne; ++j) {
+            // Re( w / (z - lambda) )
+            const double dr = c.z[j].x - eig[i], di = c.z[j].y;
+            const double den = dr * dr + di * di;
+            acc += (c.w[j].x * dr + c.w[j].y * di) / den;
+        }
+        f[i] = acc;
+    }
+    return 0;
+}
+
+static int solve_dev_common(bool cplx, int N, const void *dA, int lda, const void *dB, int ldb, double Emin,
+                            double Emax, int *M0, const feast_opts *opts, double *E, void *dX, int ldx, int *M,
+                            double *res, int *loop, double *epsout, void *stream)
+{
+    if (!M0) return -108;
+    feast_opts o;
+    if (opts) o = *opts;
+    else feast_default_opts(&o);
+    int v = fx::validate(N, *M0, Emin, Emax, o);
+    if (v) return v;
+    if (!dA) return -102;
+    if (lda < N) return -103;
+    if (dB && ldb < N) return -105;
+    if (!dX) return -111;
+    if (ldx < N) return -112;
+    if (!E || !res || !M) return -110;
+    Problem pb{N, static_cast<const double *>(dA), lda, static_cast<const double *>(dB), ldb, Emin, Emax, *M0,
+               static_cast<double *>(dX), ldx};
+    Result out;
+    std::lock_guard<std::mutex> lk(fx::g_mu);
+    int info = fx::dispatch(cplx, pb, o, static_cast<hipStream_t>(stream), out);
+    if (info == 0 || info == 2 || info == 3 || info == 1) {
+        for (int i = 0; i < out.m0; ++i) {
+            E[i] = out.E[i];
+            res[i] = out.res[i];
+        }
+        *M = out.M;
+        *M0 = out.m0;
+        if (loop) *loop = out.loop;
+        if (epsout) *epsout = out.epsout;
+    } else if (info == 4) {
+        *M = 0;
+        if (loop) *loop = 0;
+        if (epsout) *epsout = 1.0;
+    }
+    return info;
+}
+
+int feast_solve_d_dev(int N, const double *dA, int lda, const double *dB, int ldb, double Emin, double Emax,
+                      int *M0, const feast_opts *opts, double *E, double *dX, int ldx, int *M, double *res,
+                      int *loop, double *epsout, void *stream)
+{
+    return solve_dev_common(false, N, dA, lda, dB, ldb, Emin, Emax, M0, opts, E, dX, ldx, M, res, loop, epsout,
+                            stream);
+}
+
+int feast_solve_z_dev(int N, const feast_z *dA, int lda, const feast_z *dB, int ldb, double Emin, double Emax,
+                      int *M0, const feast_opts *opts, double *E, feast_z *dX, int ldx, int *M, double *res,
+                      int *loop, double *epsout, void *stream)
+{
+    return solve_dev_common(true, N, dA, lda, dB, ldb, Emin, Emax, M0, opts, E, dX, ldx, M, res, loop, epsout,
+                            stream);
+}
+
+// Host-array forms: stage A, B, X through library-owned device buffers.
+static int solve_host_common(bool cplx, int N, const void *A, int lda, const void *B, int ldb, double Emin,
+                             double Emax, int *M0, const feast_opts *opts, double *E, void *X, int ldx, int *M,
+                             double *res, int *loop, double *epsout)
+{
+    if (!M0) return -108;
+    feast_opts o;
+    if (opts) o = *opts;
+    else feast_default_opts(&o);
+    int v = fx::validate(N, *M0, Emin, Emax, o);
+    if (v) return v;
+    if (!A) return -102;
+    if (lda < N) return -103;
+    if (B && ldb < N) return -105;
+    if (!X) return -111;
+    if (ldx < N) return -112;
+    if (!E || !res || !M) return -110;
+    const size_t es = cplx ? 16 : 8;
+    std::lock_guard<std::mutex> lk(fx::g_mu);
+    int info;
+    Result out;
+    try {
+        fx::g_ws.init();
+        hipStream_t s = fx::g_ws.stream;
+        void *dA = fx::g_ws.get("in_A", es * (size_t)N * N);
+        void *dB = B ? fx::g_ws.get("in_B", es * (size_t)N * N) : nullptr;
+        void *dX = fx::g_ws.get("in_X", es * (size_t)N * (*M0));
+        FX_CHECK(hipMemcpy2DAsync(dA, es * N, A, es * lda, es * N, N, hipMemcpyHostToDevice, s));
+        if (B) FX_CHECK(hipMemcpy2DAsync(dB, es * N, B, es * ldb, es * N, N, hipMemcpyHostToDevice, s));
+        if (o.x0) FX_CHECK(hipMemcpy2DAsync(dX, es * N, X, es * ldx, es * N, *M0, hipMemcpyHostToDevice, s));
+        Problem pb{N, static_cast<const double *>(dA), N, static_cast<const double *>(dB), N, Emin, Emax, *M0,
+                   static_cast<double *>(dX), N};
+        info = fx::dispatch(cplx, pb, o, s, out);
+        if (info == 0 || info == 1 || info == 2 || info == 3 || info == 4) {
+            const int mo = (info == 4) ? *M0 : out.m0;
+            FX_CHECK(hipMemcpy2DAsync(X, es * ldx, dX, es * N, es * N, mo, hipMemcpyDeviceToHost, s));
+            FX_CHECK(hipStreamSynchronize(s));
+        }
+    } catch (const fx::alloc_error &) {
+        return -1;
+    } catch (const fx::hip_error &e) {
+        std::fprintf(stderr, "feastx: HIP error %s\n", hipGetErrorString(e.code));
+        return -4;
+    }
+    if (info == 0 || info == 1 || info == 2 || info == 3) {
+        for (int i = 0; i < out.m0; ++i) {
+            E[i] = out.E[i];
+            res[i] = out.res[i];
+        }
+        *M = out.M;
+        *M0 = out.m0;
+        if (loop) *loop = out.loop;
+        if (epsout) *epsout = out.epsout;
+    } else if (info == 4) {
+        *M = 0;
+        if (loop) *loop = 0;
+        if (epsout) *epsout = 1.0;
+    }
+    return info;
+}
+
+int feast_solve_d_ex(int N, const double *A, int lda, const double *B, int ldb, double Emin, double Emax, int *M0,
+                     const feast_opts *opts, double *E, double *X, int ldx, int *M, double *res, int *loop,
+                     double *epsout)
+{
+    return solve_host_common(false, N, A, lda, B, ldb, Emin, Emax, M0, opts, E, X, ldx, M, res, loop, epsout);
+}
+
+int feast_solve_z_ex(int N, const feast_z *A, int lda, const feast_z *B, int ldb, double Emin, double Emax,
+                     int *M0, const feast_opts *opts, double *E, feast_z *X, int ldx, int *M, double *res,
+                     int *loop, double *epsout)
+{
+    return solve_host_common(true, N, A, lda, B, ldb, Emin, Emax, M0, opts, E, X, ldx, M, res, loop, epsout);
+}
+
+int feast_solve_d(int N, const double *A, const double *B, double Emin, double Emax, int M0, int Ne, double tol,
+                  double *E, double *X, int *M, double *res)
+{
+    feast_opts o;
+    feast_default_opts(&o);
+    o.ne = Ne;
+    o.tol = tol;
+    int m0 = M0;
+    return feast_solve_d_ex(N, A, N, B, N, Emin, Emax, &m0, &o, E, X, N, M, res, nullptr, nullptr);
+}
+
+int feast_solve_z(int N, const feast_z *A, const feast_z *B, double Emin, double Emax, int M0, int Ne, double tol,
+                  double *E, feast_z *X, int *M, double *res)
+{
+    feast_opts o;
+    feast_default_opts(&o);
+    o.ne = Ne;
+    o.tol = tol;
+    int m0 = M0;
+    return feast_solve_z_ex(N, A, N, B, N, Emin, Emax, &m0, &o, E, X, N, M, res, nullptr, nullptr);
+}
+
+int feast_last_stats(feast_stats *st)
+{
+    if (!st) return -101;
+    std::lock_guard<std::mutex> lk(fx::g_mu);
+    *st = fx::g_stats;
+    return 0;
+}
+
+void feast_set_timing(int on)
+{
+    std::lock_guard<std::mutex> lk(fx::g_mu);
+    fx::g_timing = on != 0;
+}
+
+void feast_release(void)
+{
+    std::lock_guard<std::mutex> lk(fx::g_mu);
+    fx::g_ws.release();
+}
+
+}  // extern "C"

@@ -1,0 +1,477 @@
+// Shifted complex LU with partial pivoting, batched over contour nodes
+// (the factorisation step of the FEAST contour, ijob 10 of the guide's RCI
+// figure).  Blocked right-looking:
+//   for each panel of NB columns:
+//     lu_panel       factor the tall panel with partial pivoting (one
+//                    workgroup per matrix, IB-column sub-blocks in registers)
+//     lu_swap_trsm   apply the panel's row interchanges to the other
+//                    columns and solve U12 = L11^{-1} A12
+//     gemm           trailing update A22 -= L21 U12 on the matrix cores
+// The shifted matrix z_j B - A is formed by shift_build from the FP64 inputs
+// straight into the factor storage.
+#pragma once
+
+#include "common.hpp"
+#include "gemm.hpp"
+
+namespace fx {
+
+// F_j = z_j B - A  (B == nullptr: B = I), converted to the factor precision.
+template <typename T, bool CPLX_IN>
+__global__ __launch_bounds__(256) void shift_build_kernel(int n, const double *__restrict__ A,
+                                                          long lda, const double *__restrict__ B,
+                                                          long ldb, const double2 *__restrict__ z,
+                                                          int ne, cplx<T> *__restrict__ F,
+                                                          long ldf, long sF)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long nn = (long)n * n;
+    if (idx >= nn) return;
+    const int i = (int)(idx % n), c = (int)(idx / n);
+    double ar, ai = 0.0, br, bi = 0.0;
+    if constexpr (CPLX_IN) {
+        const double2 a = reinterpret_cast<const double2 *>(A)[i + c * lda];
+        ar = a.x;
+        ai = a.y;
+        if (B) {
+            const double2 b = reinterpret_cast<const double2 *>(B)[i + c * ldb];
+            br = b.x;
+            bi = b.y;
+        } else {
+            br = (i == c) ? 1.0 : 0.0;
+        }
+    } else {
+        ar = A[i + c * lda];
+        br = B ? B[i + c * ldb] : ((i == c) ? 1.0 : 0.0);
+    }
+    for (int j = 0; j < ne; ++j) {
+        const double2 zj = z[j];
+        cplx<T> v;
+        v.x = (T)(zj.x * br - zj.y * bi - ar);
+        v.y = (T)(zj.x * bi + zj.y * br - ai);
+        F[j * sF + i + (long)c * ldf] = v;
+    }
+}
+
+// Panel factorisation.  One workgroup of NT threads per matrix.  The panel
+// is processed in sub-blocks of IB columns: each sub-block is first brought
+// up to date from the panel's earlier sub-blocks (left-looking), then held
+// in registers -- R rows per thread, rows c0 + tid + NT*r -- while its IB
+// columns are factored one by one (pivot search, swap, scale, rank-1
+// update).  Row interchanges are applied to the whole panel width at once.
+// At the end thread 0 composes the panel's interchanges into a list of
+// (destination row <- source row) moves for the other columns.
+template <typename T, int NT, int R, int IB, int NB>
+__global__ __launch_bounds__(NT) void lu_panel_kernel(int n, cplx<T> *__restrict__ Fall, long ldf,
+                                                      long sF, int k, int *__restrict__ ipiv_all,
+                                                      long sPiv, int *__restrict__ swapmap_all,
+                                                      int *__restrict__ info_all)
+{
+    using V = cplx<T>;
+    V *a = Fall + blockIdx.x * sF;
+    int *ipiv = ipiv_all + blockIdx.x * sPiv;
+    int *swapmap = swapmap_all + blockIdx.x * (1 + 4 * NB);
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    constexpr int NW = NT / 64;
+    const int nbw = min(NB, n - k);
+
+    __shared__ V Lsh[NB][NB + 1];      // L11 of the panel so far (unit lower)
+    __shared__ V Ush[NB][IB];          // U rows k..c0-1 of the current sub-block
+    __shared__ V prow[IB], grow[IB];
+    __shared__ T redv[NW];
+    __shared__ int redi[NW];
+    __shared__ int s_piv;
+    __shared__ int s_pos[2 * NB], s_cnt[2 * NB];
+    __shared__ int s_n;
+
+    for (int jb = 0; jb < nbw; jb += IB) {
+        const int c0 = k + jb;
+        const int w = min(IB, nbw - jb);
+
+        // (a) U rows k..c0-1 of this sub-block: solve with L11 (jb x jb, unit lower)
+        if (jb > 0) {
+            for (int e = tid; e < jb * jb; e += NT) {
+                const int i = e % jb, l = e / jb;
+                Lsh[i][l] = a[(k + i) + (long)(k + l) * ldf];
+            }
+            for (int e = tid; e < jb * IB; e += NT) {
+                const int i = e % jb, c = e / jb;
+                Ush[i][c] = (c < w) ? a[(k + i) + (long)(c0 + c) * ldf] : cmake<V>(0, 0);
+            }
+            __syncthreads();
+            if (tid < w) {
+                for (int i = 1; i < jb; ++i) {
+                    V s = Ush[i][tid];
+                    for (int l = 0; l < i; ++l) s = csub(s, cmul(Lsh[i][l], Ush[l][tid]));
+                    Ush[i][tid] = s;
+                }
+                for (int i = 0; i < jb; ++i) a[(k + i) + (long)(c0 + tid) * ldf] = Ush[i][tid];
+            }
+            __syncthreads();
+        }
+
+        // (b) load rows c0..n-1 of the sub-block and subtract L[c0:, k:c0] * U[k:c0, sub]
+        V val[R][IB];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int row = c0 + tid + NT * r;
+#pragma unroll
+            for (int c = 0; c < IB; ++c)
+                val[r][c] = (row < n && c < w) ? a[row + (long)(c0 + c) * ldf] : cmake<V>(0, 0);
+        }
+        for (int l = 0; l < jb; ++l) {
+            V u[IB];
+#pragma unroll
+            for (int c = 0; c < IB; ++c) u[c] = Ush[l][c];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int row = c0 + tid + NT * r;
+                if (row < n) {
+                    const V lv = a[row + (long)(k + l) * ldf];
+#pragma unroll
+                    for (int c = 0; c < IB; ++c) val[r][c] = csub(val[r][c], cmul(lv, u[c]));
+                }
+            }
+        }
+
+        // (c) factor the sub-block column by column
+#pragma unroll
+        for (int jj = 0; jj < IB; ++jj) {
+            if (jj < w) {
+                const int g = c0 + jj;
+                // pivot search: largest |re|+|im|, ties to the lowest row
+                T best = T(-1);
+                int bi = 0x7fffffff;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int row = c0 + tid + NT * r;
+                    if (row >= g && row < n) {
+                        const T v = cabs1(val[r][jj]);
+                        if (v > best) {
+                            best = v;
+                            bi = row;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) {
+                    const T ov = __shfl_xor(best, off, 64);
+                    const int oi = __shfl_xor(bi, off, 64);
+                    if (ov > best || (ov == best && oi < bi)) {
+                        best = ov;
+                        bi = oi;
+                    }
+                }
+                if (lane == 0) {
+                    redv[wid] = best;
+                    redi[wid] = bi;
+                }
+                __syncthreads();
+                if (tid == 0) {
+                    T bv = redv[0];
+                    int bidx = redi[0];
+                    for (int q = 1; q < NW; ++q)
+                        if (redv[q] > bv || (redv[q] == bv && redi[q] < bidx)) {
+                            bv = redv[q];
+                            bidx = redi[q];
+                        }
+                    if (!(bv > T(0)) || bidx >= n) {
+                        // zero or non-finite column: keep the diagonal, flag the error
+                        bidx = g;
+                        if (info_all[blockIdx.x] == 0) info_all[blockIdx.x] = g + 1;
+                    }
+                    s_piv = bidx;
+                    ipiv[g] = bidx;
+                }
+                __syncthreads();
+                const int p = s_piv;
+                // exchange rows g and p of the sub-block through LDS
+                const int own_p = (p - c0) % NT, rp = (p - c0) / NT;
+                const int own_g = (g - c0) % NT, rg = (g - c0) / NT;
+                if (tid == own_p) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        if (r == rp)
+#pragma unroll
+                            for (int c = 0; c < IB; ++c) prow[c] = val[r][c];
+                }
+                if (tid == own_g) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        if (r == rg)
+#pragma unroll
+                            for (int c = 0; c < IB; ++c) grow[c] = val[r][c];
+                }
+                // the rest of the panel width, in memory
+                if (p != g) {
+                    for (int t = tid; t < nbw - w; t += NT) {
+                        const int col = (t < jb) ? (k + t) : (c0 + w + (t - jb));
+                        V *pc = a + (long)col * ldf;
+                        const V tg = pc[g];
+                        pc[g] = pc[p];
+                        pc[p] = tg;
+                    }
+                }
+                __syncthreads();
+                if (tid == own_p) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        if (r == rp)
+#pragma unroll
+                            for (int c = 0; c < IB; ++c) val[r][c] = grow[c];
+                }
+                if (tid == own_g) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        if (r == rg)
+#pragma unroll
+                            for (int c = 0; c < IB; ++c) val[r][c] = prow[c];
+                }
+                // scale the column below the diagonal and update the sub-block
+                const V piv = prow[jj];
+                const V inv = (cabs1(piv) > T(0)) ? cinv(piv) : cmake<V>(0, 0);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int row = c0 + tid + NT * r;
+                    if (row > g && row < n) {
+                        const V l = cmul(val[r][jj], inv);
+                        val[r][jj] = l;
+#pragma unroll
+                        for (int c = jj + 1; c < IB; ++c) val[r][c] = csub(val[r][c], cmul(l, prow[c]));
+                    }
+                }
+                __syncthreads();
+            }
+        }
+
+        // (d) write the sub-block back
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int row = c0 + tid + NT * r;
+            if (row < n)
+#pragma unroll
+                for (int c = 0; c < IB; ++c)
+                    if (c < w) a[row + (long)(c0 + c) * ldf] = val[r][c];
+        }
+        __syncthreads();
+    }
+
+    // compose the interchanges k..k+nbw-1 into (dst <- src) moves
+    if (tid == 0) {
+        int cnt = 0;
+        for (int i = 0; i < nbw; ++i) {
+            s_pos[cnt] = k + i;
+            s_cnt[cnt] = k + i;
+            ++cnt;
+        }
+        for (int i = 0; i < nbw; ++i) {
+            const int p = ipiv[k + i];
+            int ip = -1;
+            for (int q = 0; q < cnt; ++q)
+                if (s_pos[q] == p) ip = q;
+            if (ip < 0) {
+                s_pos[cnt] = p;
+                s_cnt[cnt] = p;
+                ip = cnt++;
+            }
+            const int t = s_cnt[i];    // position k+i is entry i
+            s_cnt[i] = s_cnt[ip];
+            s_cnt[ip] = t;
+        }
+        int nm = 0;
+        for (int q = 0; q < cnt; ++q)
+            if (s_cnt[q] != s_pos[q]) {
+                swapmap[1 + nm] = s_pos[q];
+                swapmap[1 + 2 * NB + nm] = s_cnt[q];
+                ++nm;
+            }
+        swapmap[0] = nm;
+        s_n = nm;
+    }
+}
+
+// Row interchanges of one panel applied to every column outside it, then
+// U12 = L11^{-1} A12 for the columns right of the panel.  Each block owns
+// 64 columns; moved values are staged through LDS so that all reads happen
+// before any write.
+template <typename T, int NB>
+__global__ __launch_bounds__(256) void lu_swap_trsm_kernel(int n, cplx<T> *__restrict__ Fall, long ldf,
+                                                           long sF, int k, int nbw,
+                                                           const int *__restrict__ swapmap_all)
+{
+    using V = cplx<T>;
+    constexpr int CB = 64;
+    V *a = Fall + blockIdx.y * sF;
+    const int *swapmap = swapmap_all + blockIdx.y * (1 + 4 * NB);
+    const int tid = threadIdx.x;
+    __shared__ V stage[2 * NB][CB];
+    __shared__ V Lsh[NB][NB + 1];
+    __shared__ int dst[2 * NB], src[2 * NB];
+
+    const int nm = swapmap[0];
+    for (int e = tid; e < nm; e += 256) {
+        dst[e] = swapmap[1 + e];
+        src[e] = swapmap[1 + 2 * NB + e];
+    }
+    const int colbase = blockIdx.x * CB;     // index among the n - nbw outer columns
+    const bool right = colbase + CB > k;     // block holds columns right of the panel
+    if (right)
+        for (int e = tid; e < nbw * nbw; e += 256) {
+            const int i = e % nbw, l = e / nbw;
+            Lsh[i][l] = a[(k + i) + (long)(k + l) * ldf];
+        }
+    __syncthreads();
+    for (int e = tid; e < nm * CB; e += 256) {
+        const int c = e % CB, q = e / CB;
+        const int oc = colbase + c;
+        if (oc < n - nbw) {
+            const int col = oc < k ? oc : oc + nbw;
+            stage[q][c] = a[src[q] + (long)col * ldf];
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < nm * CB; e += 256) {
+        const int c = e % CB, q = e / CB;
+        const int oc = colbase + c;
+        if (oc < n - nbw) {
+            const int col = oc < k ? oc : oc + nbw;
+            a[dst[q] + (long)col * ldf] = stage[q][c];
+        }
+    }
+    __syncthreads();
+    if (right && tid < CB) {
+        const int oc = colbase + tid;
+        if (oc >= k && oc < n - nbw) {
+            const int col = oc + nbw;
+            V *pc = a + (long)col * ldf + k;
+            V x[NB];
+#pragma unroll
+            for (int i = 0; i < NB; ++i) x[i] = (i < nbw) ? pc[i] : cmake<V>(0, 0);
+#pragma unroll
+            for (int i = 1; i < NB; ++i)
+#pragma unroll
+                for (int l = 0; l < i; ++l)
+                    if (i < nbw) x[i] = csub(x[i], cmul(Lsh[i][l], x[l]));
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+                if (i < nbw) pc[i] = x[i];
+        }
+    }
+}
+
+// After the last panel: compose all interchanges into perm (row i of P A is
+// row perm[i] of A) and flag a non-finite or zero diagonal of U.
+template <typename T>
+__global__ __launch_bounds__(256) void lu_finish_kernel(int n, const cplx<T> *__restrict__ Fall,
+                                                        long ldf, long sF,
+                                                        const int *__restrict__ ipiv_all, long sPiv,
+                                                        int *__restrict__ perm_all,
+                                                        int *__restrict__ info_all)
+{
+    const cplx<T> *a = Fall + blockIdx.x * sF;
+    const int *ipiv = ipiv_all + blockIdx.x * sPiv;
+    int *perm = perm_all + blockIdx.x * sPiv;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) perm[i] = i;
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0x7fffffff;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const cplx<T> d = a[i + (long)i * ldf];
+        if (!(cabs1(d) > T(0)) || !isfinite(d.x) || !isfinite(d.y)) atomicMin(&bad, i + 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < n; ++i) {
+            const int p = ipiv[i];
+            if (p != i) {
+                const int t = perm[i];
+                perm[i] = perm[p];
+                perm[p] = t;
+            }
+        }
+        if (bad != 0x7fffffff && info_all[blockIdx.x] == 0) info_all[blockIdx.x] = bad;
+    }
+}
+
+constexpr int LU_NB = 32;
+
+// Optional per-launch timing of the trailing update (defined by the driver).
+void lu_gemm_timing_begin(hipStream_t s, hipEvent_t *e);
+void lu_gemm_timing_end(hipStream_t s, hipEvent_t e0, double flops);
+
+template <typename T> struct panel_cfg;
+template <> struct panel_cfg<float> { static constexpr int NT = 256, IB = 4; };
+template <> struct panel_cfg<double> { static constexpr int NT = 256, IB = 2; };
+
+template <typename T, int R>
+static void launch_panel(hipStream_t s, int n, cplx<T> *F, long ldf, long sF, int k, int *ipiv,
+                         long sPiv, int *swapmap, int *info, int batch)
+{
+    using P = panel_cfg<T>;
+    hipLaunchKernelGGL((lu_panel_kernel<T, P::NT, R, P::IB, LU_NB>), dim3(batch), dim3(P::NT), 0, s, n,
+                       F, ldf, sF, k, ipiv, sPiv, swapmap, info);
+    FX_LAUNCH_CHECK();
+}
+
+// Largest n the register-resident panel supports (32 rows per thread).
+template <typename T> constexpr int lu_max_n() { return 32 * panel_cfg<T>::NT; }
+
+// Factor `batch` matrices of order n (stride sF, leading dimension ldf) in
+// place.  ipiv/perm: n ints per matrix (stride sPiv).  swapmap: (1 + 4 NB)
+// ints per matrix of scratch.  info: one int per matrix, 0 on success, else
+// 1 + the first zero/non-finite pivot index.
+template <typename T>
+void getrf_batched(hipStream_t s, int n, cplx<T> *F, long ldf, long sF, int *ipiv, int *perm,
+                   long sPiv, int *swapmap, int *info, int batch)
+{
+    using P = panel_cfg<T>;
+    for (int k = 0; k < n; k += LU_NB) {
+        const int nbw = std::min(LU_NB, n - k);
+        const int rows = n - k;
+        const int R = ceil_div(rows, P::NT);
+        if (R <= 1) launch_panel<T, 1>(s, n, F, ldf, sF, k, ipiv, sPiv, swapmap, info, batch);
+        else if (R <= 2) launch_panel<T, 2>(s, n, F, ldf, sF, k, ipiv, sPiv, swapmap, info, batch);
+        else if (R <= 4) launch_panel<T, 4>(s, n, F, ldf, sF, k, ipiv, sPiv, swapmap, info, batch);
+        else if (R <= 8) launch_panel<T, 8>(s, n, F, ldf, sF, k, ipiv, sPiv, swapmap, info, batch);
+        else if (R <= 16) launch_panel<T, 16>(s, n, F, ldf, sF, k, ipiv, sPiv, swapmap, info, batch);
+        else launch_panel<T, 32>(s, n, F, ldf, sF, k, ipiv, sPiv, swapmap, info, batch);
+        const int outer = n - nbw;
+        if (outer > 0) {
+            dim3 grid(ceil_div(outer, 64), batch);
+            hipLaunchKernelGGL((lu_swap_trsm_kernel<T, LU_NB>), grid, dim3(256), 0, s, n, F, ldf, sF,
+                               k, nbw, swapmap);
+            FX_LAUNCH_CHECK();
+        }
+        const int m2 = n - k - nbw;
+        if (m2 > 0) {
+            cplx<T> *L21 = F + (k + nbw) + (long)k * ldf;
+            cplx<T> *U12 = F + k + (long)(k + nbw) * ldf;
+            cplx<T> *A22 = F + (k + nbw) + (long)(k + nbw) * ldf;
+            hipEvent_t e0 = nullptr;
+            lu_gemm_timing_begin(s, &e0);
+            gemm<T, true, false>(s, m2, m2, nbw, T(-1), L21, ldf, sF, U12, ldf, sF, T(1), A22, ldf,
+                                 sF, batch);
+            lu_gemm_timing_end(s, e0, 8.0 * m2 * (double)m2 * nbw * batch);
+        }
+    }
+    hipLaunchKernelGGL((lu_finish_kernel<T>), dim3(batch), dim3(256), 0, s, n, F, ldf, sF, ipiv, sPiv,
+                       perm, info);
+    FX_LAUNCH_CHECK();
+}
+
+template <typename T>
+void shift_build(hipStream_t s, bool cplx_in, int n, const double *A, long lda, const double *B,
+                 long ldb, const double2 *z, int ne, cplx<T> *F, long ldf, long sF)
+{
+    const long nn = (long)n * n;
+    dim3 grid((unsigned)((nn + 255) / 256));
+    if (cplx_in)
+        hipLaunchKernelGGL((shift_build_kernel<T, true>), grid, dim3(256), 0, s, n, A, lda, B, ldb, z,
+                           ne, F, ldf, sF);
+    else
+        hipLaunchKernelGGL((shift_build_kernel<T, false>), grid, dim3(256), 0, s, n, A, lda, B, ldb, z,
+                           ne, F, ldf, sF);
+    FX_LAUNCH_CHECK();
+}
+
+}  // namespace fx

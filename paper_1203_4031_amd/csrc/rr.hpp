@@ -1,0 +1,174 @@
+// Element-wise and reduction kernels around the contour solves and the
+// Rayleigh-Ritz step: quadrature accumulation, residual norms, Hermitian
+// symmetrisation, column scaling and gathering, and the seeded random start.
+#pragma once
+
+#include "common.hpp"
+#include "jacobi.hpp"
+
+namespace fx {
+
+// Quadrature accumulation (the guide's Q = sum_j w_j Q_j), fixed node order.
+//   real pencils:      Q = rho .* X + sum_j Re(coef_jc Y_j)
+//   Hermitian pencils: Q = rho .* X + sum_j (coef_jc Y_j + conj(coef_jc) Yh_j) / 2
+// coef_jc = w_j for the plain form, w_j / (z_j - lambda_c) for the residual
+// correction form (then rho_c = sum_j Re coef_jc and X is the Ritz basis);
+// rho == nullptr means no X term.  Y_j, Yh_j are in the solve precision; Q is
+// FP64.
+template <typename T, bool CPLX>
+__global__ __launch_bounds__(256) void accumulate_kernel(int n, int ncols, int ne,
+                                                         const cplx<T> *__restrict__ Y, long ldy,
+                                                         long sY, const cplx<T> *__restrict__ Yh,
+                                                         const double2 *__restrict__ coef,
+                                                         const double *__restrict__ rho,
+                                                         const typename jelem<CPLX>::type *__restrict__ X,
+                                                         long ldx, typename jelem<CPLX>::type *__restrict__ Q,
+                                                         long ldq)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)n * ncols) return;
+    const int i = (int)(idx % n), c = (int)(idx / n);
+    double qr = 0.0, qi = 0.0;
+    for (int j = 0; j < ne; ++j) {
+        const double2 w = coef[(long)j * ncols + c];
+        const cplx<T> y = Y[j * sY + i + (long)c * ldy];
+        const double yr = y.x, yi = y.y;
+        if constexpr (!CPLX) {
+            qr += w.x * yr - w.y * yi;
+        } else {
+            const cplx<T> yh = Yh[j * sY + i + (long)c * ldy];
+            const double hr = yh.x, hi = yh.y;
+            // (w y + conj(w) yh) / 2
+            qr += 0.5 * ((w.x * yr - w.y * yi) + (w.x * hr + w.y * hi));
+            qi += 0.5 * ((w.x * yi + w.y * yr) + (w.x * hi - w.y * hr));
+        }
+    }
+    if (rho) {
+        const double2 x = jload<CPLX>(X, i + (long)c * ldx);
+        qr += rho[c] * x.x;
+        qi += rho[c] * x.y;
+    }
+    jstore<CPLX>(Q, i + (long)c * ldq, make_double2(qr, qi));
+}
+
+// R = AX - BX diag(lambda)   (residual of the current Ritz pairs, FP64)
+template <bool CPLX>
+__global__ __launch_bounds__(256) void ritz_residual_kernel(int n, int ncols,
+                                                            const typename jelem<CPLX>::type *__restrict__ AX,
+                                                            const typename jelem<CPLX>::type *__restrict__ BX,
+                                                            long ld, const double *__restrict__ lam,
+                                                            typename jelem<CPLX>::type *__restrict__ R)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)n * ncols) return;
+    const int i = (int)(idx % n), c = (int)(idx / n);
+    const double2 a = jload<CPLX>(AX, i + (long)c * ld), b = jload<CPLX>(BX, i + (long)c * ld);
+    const double l = lam[c];
+    jstore<CPLX>(R, i + (long)c * ld, make_double2(a.x - l * b.x, a.y - l * b.y));
+}
+
+// res_c = ||AX_c - lambda_c BX_c||_1 / (alpha ||BX_c||_1), complex modulus
+// (the guide's residual definition, argument res of Table "tab_common").
+// One block per column, fixed reduction order.
+template <bool CPLX>
+__global__ __launch_bounds__(256) void resid_norm_kernel(int n, const typename jelem<CPLX>::type *__restrict__ AX,
+                                                         const typename jelem<CPLX>::type *__restrict__ BX,
+                                                         long ld, const double *__restrict__ lam, double alpha,
+                                                         double *__restrict__ res)
+{
+    const int c = blockIdx.x, tid = threadIdx.x;
+    const double l = lam[c];
+    double num = 0.0, den = 0.0;
+    for (int i = tid; i < n; i += 256) {
+        const double2 a = jload<CPLX>(AX, i + (long)c * ld), b = jload<CPLX>(BX, i + (long)c * ld);
+        const double rr = a.x - l * b.x, ri = a.y - l * b.y;
+        num += sqrt(rr * rr + ri * ri);
+        den += sqrt(b.x * b.x + b.y * b.y);
+    }
+    __shared__ double sn[4], sd[4];
+    num = wave_sum(num);
+    den = wave_sum(den);
+    if ((tid & 63) == 0) {
+        sn[tid >> 6] = num;
+        sd[tid >> 6] = den;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const double N = sn[0] + sn[1] + sn[2] + sn[3], D = sd[0] + sd[1] + sd[2] + sd[3];
+        res[c] = N / (alpha * D);
+    }
+}
+
+// M = (M + M^H) / 2, m x m
+template <bool CPLX>
+__global__ __launch_bounds__(256) void hermitian_part_kernel(int m, typename jelem<CPLX>::type *M, long ld)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)m * m) return;
+    const int i = (int)(idx % m), j = (int)(idx / m);
+    if (i > j) return;
+    const double2 a = jload<CPLX>(M, i + (long)j * ld), b = jload<CPLX>(M, j + (long)i * ld);
+    const double2 s = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+    jstore<CPLX>(M, i + (long)j * ld, s);
+    jstore<CPLX>(M, j + (long)i * ld, make_double2(s.x, -s.y));
+}
+
+// T[:, c] = W[:, first + c] / sqrt(beta[first + c])
+template <bool CPLX>
+__global__ __launch_bounds__(256) void scale_cols_kernel(int m, int ncols, int first,
+                                                         const typename jelem<CPLX>::type *__restrict__ W,
+                                                         long ldw, const double *__restrict__ beta,
+                                                         typename jelem<CPLX>::type *__restrict__ T, long ldt)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)m * ncols) return;
+    const int i = (int)(idx % m), c = (int)(idx / m);
+    const double sc = 1.0 / sqrt(beta[first + c]);
+    const double2 v = jload<CPLX>(W, i + (long)(first + c) * ldw);
+    jstore<CPLX>(T, i + (long)c * ldt, make_double2(v.x * sc, v.y * sc));
+}
+
+// out[:, c] = in[:, idx[c]]
+template <bool CPLX>
+__global__ __launch_bounds__(256) void gather_cols_kernel(int n, int ncols, const int *__restrict__ sel,
+                                                          const typename jelem<CPLX>::type *__restrict__ in,
+                                                          long ldi, typename jelem<CPLX>::type *__restrict__ out,
+                                                          long ldo)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)n * ncols) return;
+    const int i = (int)(idx % n), c = (int)(idx / n);
+    out[i + (long)c * ldo] = in[i + (long)sel[c] * ldi];
+}
+
+// Seeded start subspace: real uniform(-1, 1), one splitmix64 draw per entry
+// (counter = column-major index).
+template <bool CPLX>
+__global__ __launch_bounds__(256) void random_start_kernel(int n, int ncols, unsigned long long seed,
+                                                           typename jelem<CPLX>::type *__restrict__ X, long ldx)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)n * ncols) return;
+    const int i = (int)(idx % n), c = (int)(idx / n);
+    unsigned long long z = seed + 0x9E3779B97F4A7C15ull * (unsigned long long)(idx + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const double u = (double)(z >> 11) * (1.0 / 9007199254740992.0);
+    jstore<CPLX>(X, i + (long)c * ldx, make_double2(2.0 * u - 1.0, 0.0));
+}
+
+// Copy an n x ncols FP64 block between leading dimensions.
+template <bool CPLX>
+__global__ __launch_bounds__(256) void copy_block_kernel(int n, int ncols,
+                                                         const typename jelem<CPLX>::type *__restrict__ in,
+                                                         long ldi, typename jelem<CPLX>::type *__restrict__ out,
+                                                         long ldo)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)n * ncols) return;
+    const int i = (int)(idx % n), c = (int)(idx / n);
+    out[i + (long)c * ldo] = in[i + (long)c * ldi];
+}
+
+}  // namespace fx

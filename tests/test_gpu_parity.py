@@ -1,0 +1,120 @@
+"""GPU parity: the HIP library against the FP64 CPU oracle, through the C ABI.
+
+Bar (per the method's readings): eigenvalues within 1e-10 * max(|lambda|,
+alpha) of the oracle's, the same count M, residuals below tol on both sides,
+B-orthonormal eigenvectors, and eigenvectors spanning the oracle's
+(principal-angle check, so that clusters and signs do not matter)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1203_4031_amd import feastx
+from paper_1203_4031_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _alpha(p):
+    return max(abs(p.emin), abs(p.emax))
+
+
+def _check_pairs(p, r, ref, tol_eig=1e-10):
+    assert r.info == 0, r.info
+    assert r.M == ref.M
+    M = r.M
+    a = _alpha(p)
+    err = np.abs(r.E[:M] - ref.E[:M]) / np.maximum(np.abs(ref.E[:M]), a)
+    assert err.max() <= tol_eig, err.max()
+    assert (r.res[:M] < p.tol).all(), r.res[:M].max()
+    X = r.X[:, :M]
+    B = np.eye(p.n) if p.B is None else p.B
+    G = X.conj().T @ B @ X
+    assert np.abs(G - np.eye(M)).max() < 1e-10
+    # independent FP64 residuals on the host
+    AX = p.A @ X
+    BX = B @ X
+    res = np.abs(AX - BX * r.E[:M]).sum(0) / (a * np.abs(BX).sum(0))
+    assert (res < p.tol).all(), res.max()
+    # same invariant subspace: singular values of Xo^H B X all ~ 1
+    s = np.linalg.svd(ref.X[:, :M].conj().T @ B @ X, compute_uv=False)
+    assert s.min() > 1 - 1e-8, s.min()
+
+
+def _small_problems():
+    yield W.helloworld()
+    yield W.laplacian_1d()
+    yield W.dense_real_generalized(300, count=30, seed=2101, tol=1e-10)
+    yield W.dense_complex_hermitian(256, count=24, seed=3101, ne=16, tol=1e-10, nclusters=3)
+
+
+@pytest.fixture(scope="module")
+def small_cases(orc):
+    out = []
+    for p in _small_problems():
+        ref = orc.feast(p.A, p.B, p.emin, p.emax, p.m0, p.ne, p.tol, p.X0, hermitian=p.hermitian)
+        assert ref.info == 0
+        out.append((p, ref))
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("idx", [0, 1, 2, 3])
+def test_solve_matches_oracle(small_cases, precision, idx):
+    p, ref = small_cases[idx]
+    print(f"case {p.name} precision {precision}", flush=True)
+    r = feastx.solve(p.A, p.B, p.emin, p.emax, p.m0, X0=p.X0, ne=p.ne, tol=p.tol,
+                     precision=precision)
+    _check_pairs(p, r, ref)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("mixed", 2e-4)])
+@pytest.mark.parametrize("herm", [False, True])
+def test_contour_step_elementwise(orc, precision, tol, herm):
+    """mode 1 returns Q after one contour: compare element by element.
+    Sizes span several LU panels and solve blocks plus a ragged tail."""
+    if herm:
+        p = W.dense_complex_hermitian(203, count=20, seed=3202, ne=8, nclusters=2)
+    else:
+        p = W.dense_real_generalized(203, count=20, seed=2202)
+    print(f"contour case {p.name} {precision}", flush=True)
+    ref = orc.feast(p.A, p.B, p.emin, p.emax, p.m0, p.ne, p.tol, p.X0, hermitian=herm, mode=1)
+    r = feastx.solve(p.A, p.B, p.emin, p.emax, p.m0, X0=p.X0, ne=p.ne, tol=p.tol,
+                     precision=precision, mode=1)
+    assert r.info == 4 and ref.info == 4
+    scale = np.abs(ref.X).max()
+    assert np.abs(r.X - ref.X).max() / scale < tol
+
+
+def test_info_nan_pivot():
+    p = W.laplacian_1d(40, m0=10)
+    A = p.A.copy()
+    A[3, 7] = np.nan
+    r = feastx.solve(A, None, p.emin, p.emax, p.m0, X0=p.X0)
+    assert r.info == -2
+
+
+def test_info_indefinite_B():
+    p = W.laplacian_1d(40, emin=0.0, emax=1.0, m0=16)
+    r = feastx.solve(p.A, -np.eye(40), p.emin, p.emax, p.m0, X0=p.X0)
+    assert r.info == -3
+
+
+def test_info_empty_interval_and_no_convergence():
+    p = W.laplacian_1d(60, emin=0.0, emax=1.0, m0=32)
+    assert feastx.solve(p.A, None, 10.0, 11.0, 8, X0=p.X0[:, :8]).info == 1
+    r = feastx.solve(p.A, None, p.emin, p.emax, p.m0, X0=p.X0, tol=1e-30, maxloop=1)
+    assert r.info == 2 and r.loop == 1
+    r = feastx.solve(p.A, None, p.emin, p.emax, 8, X0=p.X0[:, :8])
+    assert r.info == 3
+
+
+def test_laplacian_closed_form_gpu():
+    p = W.laplacian_1d()
+    for precision in ("fp64", "mixed"):
+        r = feastx.solve(p.A, None, p.emin, p.emax, p.m0, X0=p.X0, ne=p.ne, tol=p.tol,
+                         precision=precision)
+        k = np.arange(1, 47)
+        exact = 2 - 2 * np.cos(k * math.pi / 201)
+        assert r.info == 0 and r.M == 46
+        assert np.abs(r.E[:46] - exact).max() < 1e-12 * 0.5
