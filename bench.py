@@ -130,6 +130,10 @@ def main():
     times, res_mixed, lu = run_steps(feastx, torch, A, B, X0, X, p, "mixed", args.steps, True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
+    st = feastx.stats()
+    stage_ms = {k: round(getattr(st, k), 3) for k in ("t_total", "t_shift", "t_factor", "t_solve", "t_accum",
+                                                      "t_rr", "t_reduced", "t_resid")}
+    stage_ms["eig_calls"], stage_ms["eig_sweeps"] = st.eig_calls, st.eig_sweeps
     check(res_mixed, p, expected)
     loops = res_mixed[-1].loop + 1
     log(f"mixed: {args.steps} solves in {wall:.3f}s, loops {loops}")
@@ -165,6 +169,7 @@ def main():
         "mixed_over_fp64": solves_per_s * float(np.mean(times64)),
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "feast_loops": loops,
+        "stage_ms_last_solve": stage_ms,
         "roofline": {"kernel": "LU trailing update (complex64 GEMM on FP32 matrix cores)",
                      "bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA, "traffic": None,

@@ -75,6 +75,8 @@ typedef struct {
     double solve_flops;      /* 8 N^2 M0 per node per triangular pair, all loops */
     int loops;               /* FEAST loops executed (loop + 1) */
     int m0_final;            /* subspace size at exit */
+    int eig_calls;           /* reduced Hermitian eigensolves */
+    int eig_sweeps;          /* Jacobi sweeps summed over those calls */
 } feast_stats;
 
 /* Defaults of the guide's feastinit (Table "tab_fpm"), with keep_factors = 1. */

@@ -111,9 +111,11 @@ struct grid_sync {
     }
     __device__ void sync()
     {
+        // __syncthreads() makes every wave's stores complete before thread 0
+        // publishes its arrival with release semantics at agent scope; the
+        // acquire on the generation word makes the other blocks' data visible.
         __syncthreads();
         if (threadIdx.x == 0) {
-            __atomic_thread_fence(__ATOMIC_SEQ_CST);
             unsigned g = local_gen;
             unsigned prev = __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
             if (prev == nblocks - 1) {
@@ -121,9 +123,8 @@ struct grid_sync {
                 __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             } else {
                 while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g)
-                    __builtin_amdgcn_s_sleep(2);
+                    __builtin_amdgcn_s_sleep(1);
             }
-            __atomic_thread_fence(__ATOMIC_SEQ_CST);
         }
         local_gen += 1;
         __syncthreads();

@@ -15,6 +15,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -45,6 +46,8 @@ struct Workspace {
     std::map<std::string, std::pair<void *, size_t>> dev;
     std::map<std::string, std::pair<void *, size_t>> host;
     hipStream_t stream = nullptr;
+    hipStream_t side = nullptr;            // look-ahead panels of the LU
+    hipEvent_t ev_a = nullptr, ev_b = nullptr;
     unsigned *bar = nullptr;
     int device = -1;
     int num_cu = 0;
@@ -86,13 +89,16 @@ struct Workspace {
         if (stream) return;
         FX_CHECK(hipGetDevice(&device));
         FX_CHECK(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+        FX_CHECK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+        FX_CHECK(hipEventCreateWithFlags(&ev_a, hipEventDisableTiming));
+        FX_CHECK(hipEventCreateWithFlags(&ev_b, hipEventDisableTiming));
         hipDeviceProp_t prop;
         FX_CHECK(hipGetDeviceProperties(&prop, device));
         num_cu = prop.multiProcessorCount;
         int per_cu = 0;
-        FX_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, jacobi_kernel<true>, JAC_NT, 0));
+        FX_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bjacobi_kernel<true>, BJ_NT, 0));
         int per_cu_r = 0;
-        FX_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_r, jacobi_kernel<false>, JAC_NT, 0));
+        FX_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_r, bjacobi_kernel<false>, BJ_NT, 0));
         jac_max_blocks = std::max(1, std::min(per_cu, per_cu_r)) * num_cu;
         bar = static_cast<unsigned *>(get("grid_barrier", 2 * sizeof(unsigned)));
         FX_CHECK(hipMemset(bar, 0, 2 * sizeof(unsigned)));
@@ -107,7 +113,11 @@ struct Workspace {
         dev.clear();
         host.clear();
         if (stream) (void)hipStreamDestroy(stream);
-        stream = nullptr;
+        if (side) (void)hipStreamDestroy(side);
+        if (ev_a) (void)hipEventDestroy(ev_a);
+        if (ev_b) (void)hipEventDestroy(ev_b);
+        stream = side = nullptr;
+        ev_a = ev_b = nullptr;
         bar = nullptr;
     }
 };
@@ -116,6 +126,7 @@ static Workspace g_ws;
 static std::mutex g_mu;
 static feast_stats g_stats;
 static bool g_timing = false;
+static const bool g_debug = std::getenv("FEASTX_DEBUG") != nullptr;
 
 // ------------------------------------------------------------ contour
 // Gauss-Legendre nodes on [-1, 1] by Newton iteration on P_n, evaluated with
@@ -260,31 +271,43 @@ static dim3 grid1(long count) { return dim3((unsigned)((count + 255) / 256)); }
 // Reduced Hermitian eigenproblem on the device: C (m x m, overwritten) ->
 // ascending eigenvalues w (device) and eigenvectors Vout (m x m).
 template <bool CPLX>
-static void device_eigh(Workspace &ws, hipStream_t s, int m, F64<CPLX> *C, F64<CPLX> *Vout, double *w)
+static void device_eigh(Workspace &ws, hipStream_t s, int m, F64<CPLX> *C, F64<CPLX> *Vout, double *w,
+                        feast_stats &st)
 {
     using E = F64<CPLX>;
-    E *C1 = static_cast<E *>(ws.get("jac_c1", sizeof(E) * (size_t)m * m));
     E *V = static_cast<E *>(ws.get("jac_v", sizeof(E) * (size_t)m * m));
-    const int p = m + (m & 1), npairs = p / 2;
-    const long work = (long)npairs * npairs + (long)m * npairs;
-    int G = (int)std::min<long>(ws.jac_max_blocks, std::max<long>(1, (work + 2047) / 2048));
-    G = std::min(G, ws.num_cu);
-    double *partial = static_cast<double *>(ws.get("jac_partial", sizeof(double) * 1024));
+    const int nb = (m + BJ_BS - 1) / BJ_BS, npairs = (nb + (nb & 1)) / 2;
+    E *Rbuf = static_cast<E *>(ws.get("jac_r", sizeof(E) * (size_t)npairs * BJ_W * BJ_W));
+    const int nrc = (m + BJ_W - 1) / BJ_W;
+    // enough blocks for the tile updates, few enough to keep grid barriers cheap
+    int G = std::max(npairs, std::min(npairs * npairs + nrc * npairs, 64));
+    G = std::min(G, ws.jac_max_blocks);
+    double *partial = static_cast<double *>(ws.get("jac_partial", sizeof(double) * 2 * 1024));
     int *status = static_cast<int *>(ws.get("jac_status", sizeof(int) * 2));
+    double *hist = static_cast<double *>(ws.get("jac_hist", sizeof(double) * 64));
     int *rank = static_cast<int *>(ws.get("jac_rank", sizeof(int) * m));
     long ld = m;
-    int max_sweeps = 60;
-    double tol = 1e-15;
+    int max_sweeps = 40, inner = 1;
+    double tol = 1e-13;
     unsigned *bar = ws.bar;
-    void *args[] = {&m, &C, &C1, &ld, &V, &ld, &partial, &bar, &max_sweeps, &tol, &status};
-    FX_CHECK(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(jacobi_kernel<CPLX>), dim3(G),
-                                        dim3(JAC_NT), args, 0, s));
+    void *args[] = {&m, &C, &ld, &V, &ld, &Rbuf, &partial, &bar, &max_sweeps, &tol, &inner, &status, &hist};
+    FX_CHECK(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(bjacobi_kernel<CPLX>), dim3(G),
+                                        dim3(BJ_NT), args, 0, s));
     hipLaunchKernelGGL((jacobi_sort_kernel<CPLX>), dim3(1), dim3(1024), 0, s, m, C, ld, V, ld, w, Vout, ld,
                        rank);
     FX_LAUNCH_CHECK();
     int *hst = static_cast<int *>(ws.pinned("jac_status_h", sizeof(int) * 2));
     FX_CHECK(hipMemcpyAsync(hst, status, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
     FX_CHECK(hipStreamSynchronize(s));
+    st.eig_calls += 1;
+    st.eig_sweeps += hst[1];
+    if (g_debug) {
+        double hh[64];
+        FX_CHECK(hipMemcpy(hh, hist, sizeof(double) * std::min(hst[1], 64), hipMemcpyDeviceToHost));
+        std::fprintf(stderr, "feastx eigh n=%d G=%d sweeps=%d off/fro:", m, G, hst[1]);
+        for (int i = 0; i < std::min(hst[1], 64); ++i) std::fprintf(stderr, " %.1e", hh[i]);
+        std::fprintf(stderr, "\n");
+    }
     if (hst[0] != 0) throw solver_error{-3};
 }
 
@@ -337,6 +360,10 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
     int *perm = static_cast<int *>(ws.get("perm", sizeof(int) * (size_t)ne * n));
     int *swapmap = static_cast<int *>(ws.get("swapmap", sizeof(int) * (size_t)ne * (1 + 4 * LU_NB)));
     int *dinfo = static_cast<int *>(ws.get("info", sizeof(int) * ne));
+    const long sInv = tri_inv_stride(n);
+    V *Linv = static_cast<V *>(ws.get(mixed ? "Linv32" : "Linv64", sizeof(V) * (size_t)ne * sInv));
+    V *Uinv = static_cast<V *>(ws.get(mixed ? "Uinv32" : "Uinv64", sizeof(V) * (size_t)ne * sInv));
+    V *Ytmp = static_cast<V *>(ws.get(mixed ? "Yt32" : "Yt64", sizeof(V) * (size_t)ne * nm));
     V *Y = static_cast<V *>(ws.get(mixed ? "Y32" : "Y64", sizeof(V) * (size_t)ne * nm));
     V *Yh = nullptr, *Yh2 = nullptr;
     if (CPLX) {
@@ -372,7 +399,8 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
             shift_build<T>(s, CPLX, n, pb.A, pb.lda, pb.B, pb.ldb, dz, ne, F, ldf, sF);
             tm.mark(&st.t_shift);
             FX_CHECK(hipMemsetAsync(dinfo, 0, sizeof(int) * ne, s));
-            getrf_batched<T>(s, n, F, ldf, sF, ipiv, perm, n, swapmap, dinfo, ne);
+            getrf_batched<T>(s, ws.side, ws.ev_a, ws.ev_b, n, F, ldf, sF, ipiv, perm, n, swapmap, dinfo, ne);
+            tri_inv_batched<T>(s, n, F, ldf, sF, Linv, Uinv, sInv, ne);
             tm.mark(&st.t_factor);
             FX_CHECK(hipMemcpyAsync(h_info, dinfo, sizeof(int) * ne, hipMemcpyDeviceToHost, s));
             FX_CHECK(hipStreamSynchronize(s));
@@ -402,12 +430,12 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
             hipLaunchKernelGGL((gather_rows_kernel<T, CPLX>), g, dim3(256), 0, s, n, m0, perm, (long)n,
                                reinterpret_cast<const double *>(R), (long)n, Y, (long)n, (long)cur_nm);
             FX_LAUNCH_CHECK();
-            getrs_batched<T>(s, false, n, m0, F, ldf, sF, Y, n, (long)cur_nm, ne);
+            getrs_batched<T>(s, false, n, m0, F, ldf, sF, Linv, Uinv, sInv, Y, Ytmp, n, (long)cur_nm, ne);
             if (CPLX) {
                 hipLaunchKernelGGL((copy_rhs_kernel<T, CPLX>), g, dim3(256), 0, s, n, m0,
                                    reinterpret_cast<const double *>(R), (long)n, Yh, (long)n, (long)cur_nm);
                 FX_LAUNCH_CHECK();
-                getrs_batched<T>(s, true, n, m0, F, ldf, sF, Yh, n, (long)cur_nm, ne);
+                getrs_batched<T>(s, true, n, m0, F, ldf, sF, Linv, Uinv, sInv, Yh, Ytmp, n, (long)cur_nm, ne);
                 hipLaunchKernelGGL((scatter_rows_kernel<T>), g, dim3(256), 0, s, n, m0, perm, (long)n, Yh,
                                    (long)n, (long)cur_nm, Yh2, (long)n, (long)cur_nm);
                 FX_LAUNCH_CHECK();
@@ -476,7 +504,7 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
 
         // ---- reduced problem: Bq = W diag(beta) W^H, drop tiny directions,
         //      T = W_keep beta^{-1/2}, eig(T^H Aq T) = (lambda, V), Phi = T V
-        device_eigh<CPLX>(ws, s, m0, Bq, Wb, beta);
+        device_eigh<CPLX>(ws, s, m0, Bq, Wb, beta, st);
         FX_CHECK(hipMemcpyAsync(h_beta, beta, sizeof(double) * m0, hipMemcpyDeviceToHost, s));
         FX_CHECK(hipStreamSynchronize(s));
         const double bmax = h_beta[m0 - 1];
@@ -493,7 +521,7 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
         hipLaunchKernelGGL((hermitian_part_kernel<CPLX>), grid1((long)keep * keep), dim3(256), 0, s, keep, Cr,
                            (long)keep);
         FX_LAUNCH_CHECK();
-        device_eigh<CPLX>(ws, s, keep, Cr, Vc, lam);
+        device_eigh<CPLX>(ws, s, keep, Cr, Vc, lam, st);
         dgemm<CPLX>(s, false, m0, keep, keep, 1.0, Tm, m0, Vc, keep, 0.0, Phi, m0);
         tm.mark(&st.t_reduced);
 
@@ -614,7 +642,7 @@ static int validate(int n, int m0, double emin, double emax, const feast_opts &o
     if (o.mode != 0 && o.mode != 1) return 114;
     if (o.precision != 0 && o.precision != 1) return 140;
     if (o.refine != 0) return 141;   // per-solve refinement: not available in this build
-    if (m0 > 2 * JAC_MAXPAIRS) return 201;
+    if (m0 > 4096) return 201;
     if (o.precision == 1 && n > lu_max_n<float>()) return 202;
     if (o.precision == 0 && n > lu_max_n<double>()) return 202;
     return 0;

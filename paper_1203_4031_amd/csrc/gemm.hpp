@@ -40,7 +40,9 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_kernel(
     constexpr int NT = WAVES_M * WAVES_N * 64;
     constexpr int FM = WM / 16, FN = WN / 16;
     constexpr int PAD = 1;
+    constexpr int LA = BM * BK / NT, LB = BN * BK / NT;   // staged elements per thread
     static_assert(BK % 4 == 0, "BK must be a multiple of 4");
+    static_assert((BM * BK) % NT == 0 && (BN * BK) % NT == 0, "tile not divisible");
 
     __shared__ E As[BK][BM + PAD];
     __shared__ E Bs[BK][BN + PAD];
@@ -57,41 +59,73 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_kernel(
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int wm = wid % WAVES_M, wn = wid / WAVES_M;
 
+    // accumulators start from beta * C / alpha so that the epilogue is a
+    // plain store of alpha * acc; the loads are issued before the k loop
     acc_t acc_re[FN][FM];
     acc_t acc_im[CPLX ? FN : 1][CPLX ? FM : 1];
+    const T cscale = (beta != T(0)) ? beta / alpha : T(0);
 #pragma unroll
     for (int a = 0; a < FN; ++a)
 #pragma unroll
-        for (int b = 0; b < FM; ++b) {
-            acc_re[a][b] = acc_t{0, 0, 0, 0};
-            if constexpr (CPLX) acc_im[a][b] = acc_t{0, 0, 0, 0};
-        }
+        for (int b = 0; b < FM; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gj = n0 + wn * WN + a * 16 + MF::acc_row(lane, r);
+                const int gi = m0 + wm * WM + b * 16 + (lane & 15);
+                E c = zero_elem<E>();
+                if (cscale != T(0) && gi < m && gj < n) c = C[gi + (long)gj * ldc];
+                if constexpr (CPLX) {
+                    acc_re[a][b][r] = cscale * c.x;
+                    acc_im[a][b][r] = cscale * c.y;
+                } else {
+                    acc_re[a][b][r] = cscale * c;
+                }
+            }
 
-    for (int k0 = 0; k0 < k; k0 += BK) {
-        // ---- stage A tile (BM x BK of op(A)) and B tile (BK x BN)
-        if constexpr (!OPA_H) {
-#pragma unroll 4
-            for (int e = tid; e < BM * BK; e += NT) {
-                const int i = e % BM, kk = e / BM;
-                const int gi = m0 + i, gk = k0 + kk;
-                As[kk][i] = (gi < m && gk < k) ? A[gi + (long)gk * lda] : zero_elem<E>();
+    E ra[LA], rb[LB];
+    auto load_tiles = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < LA; ++u) {
+            const int e = tid + u * NT;
+            int i, kk;
+            if constexpr (!OPA_H) {
+                i = e % BM;
+                kk = e / BM;
+            } else {
+                kk = e % BK;
+                i = e / BK;
             }
-        } else {
-#pragma unroll 4
-            for (int e = tid; e < BM * BK; e += NT) {
-                const int kk = e % BK, i = e / BK;
-                const int gi = m0 + i, gk = k0 + kk;
-                As[kk][i] = (gi < m && gk < k) ? conj_elem(A[gk + (long)gi * lda]) : zero_elem<E>();
-            }
+            const int gi = m0 + i, gk = k0 + kk;
+            if (gi < m && gk < k) ra[u] = OPA_H ? conj_elem(A[gk + (long)gi * lda]) : A[gi + (long)gk * lda];
+            else ra[u] = zero_elem<E>();
         }
-#pragma unroll 4
-        for (int e = tid; e < BN * BK; e += NT) {
+#pragma unroll
+        for (int u = 0; u < LB; ++u) {
+            const int e = tid + u * NT;
             const int kk = e % BK, j = e / BK;
             const int gj = n0 + j, gk = k0 + kk;
-            Bs[kk][j] = (gj < n && gk < k) ? B[gk + (long)gj * ldb] : zero_elem<E>();
+            rb[u] = (gj < n && gk < k) ? B[gk + (long)gj * ldb] : zero_elem<E>();
         }
-        __syncthreads();
+    };
+    auto store_tiles = [&]() {
+#pragma unroll
+        for (int u = 0; u < LA; ++u) {
+            const int e = tid + u * NT;
+            if constexpr (!OPA_H) As[e / BM][e % BM] = ra[u];
+            else As[e % BK][e / BK] = ra[u];
+        }
+#pragma unroll
+        for (int u = 0; u < LB; ++u) {
+            const int e = tid + u * NT;
+            Bs[e % BK][e / BK] = rb[u];
+        }
+    };
 
+    if (k > 0) load_tiles(0);
+    for (int k0 = 0; k0 < k; k0 += BK) {
+        store_tiles();
+        __syncthreads();
+        if (k0 + BK < k) load_tiles(k0 + BK);   // in flight during the MFMAs below
 #pragma unroll
         for (int k4 = 0; k4 < BK / 4; ++k4) {
             const int kr = k4 * 4 + (lane >> 4);
@@ -117,7 +151,8 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_kernel(
         __syncthreads();
     }
 
-    // ---- epilogue: acc'[row j][col i] of the transposed tile
+    // ---- epilogue: acc'[row j][col i] of the transposed tile; 16 lanes
+    //      write 16 consecutive rows of one column of C
 #pragma unroll
     for (int a = 0; a < FN; ++a)
 #pragma unroll
@@ -127,23 +162,14 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_kernel(
                 const int gj = n0 + wn * WN + a * 16 + MF::acc_row(lane, r);
                 const int gi = m0 + wm * WM + b * 16 + (lane & 15);
                 if (gi < m && gj < n) {
-                    E *p = C + gi + (long)gj * ldc;
+                    E o;
                     if constexpr (CPLX) {
-                        T vr = alpha * acc_re[a][b][r], vi = alpha * acc_im[a][b][r];
-                        if (beta != T(0)) {
-                            E c = *p;
-                            vr += beta * c.x;
-                            vi += beta * c.y;
-                        }
-                        E o;
-                        o.x = vr;
-                        o.y = vi;
-                        *p = o;
+                        o.x = alpha * acc_re[a][b][r];
+                        o.y = alpha * acc_im[a][b][r];
                     } else {
-                        T v = alpha * acc_re[a][b][r];
-                        if (beta != T(0)) v += beta * *p;
-                        *p = v;
+                        o = alpha * acc_re[a][b][r];
                     }
+                    C[gi + (long)gj * ldc] = o;
                 }
             }
 }
@@ -151,7 +177,7 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void gemm_kernel(
 // Tile shapes per element type.
 template <typename T, bool CPLX> struct gemm_cfg;
 template <> struct gemm_cfg<float, true> {
-    static constexpr int BM = 128, BN = 128, BK = 16, WM = 64, WN = 64;
+    static constexpr int BM = 128, BN = 128, BK = 32, WM = 64, WN = 64;
 };
 template <> struct gemm_cfg<double, true> {
     static constexpr int BM = 64, BN = 64, BK = 16, WM = 32, WN = 32;
@@ -169,6 +195,7 @@ void gemm(hipStream_t s, int m, int n, int k, T alpha, const typename elem<T, CP
           typename elem<T, CPLX>::type *C, long ldc, long sC, int batch)
 {
     if (m <= 0 || n <= 0 || batch <= 0) return;
+    if (alpha == T(0)) throw hip_error{hipErrorInvalidValue};   // the kernel scales C by beta / alpha
     using cfg = gemm_cfg<T, CPLX>;
     constexpr int NT = (cfg::BM / cfg::WM) * (cfg::BN / cfg::WN) * 64;
     if (k <= 0) {

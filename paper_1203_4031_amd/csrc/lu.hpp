@@ -53,14 +53,49 @@ __global__ __launch_bounds__(256) void shift_build_kernel(int n, const double *_
     }
 }
 
+// Compose the row interchanges (r0 + i <-> ipiv[r0 + i]), i = 0..cnt-1,
+// applied in order, into moves "row dst[q] receives the old row src[q]".
+// pos/val are scratch of 2 cnt entries.  Returns the number of moves.
+__device__ inline int compose_moves(const int *ipiv, int r0, int cnt, int *pos, int *val, int *dst, int *src)
+{
+    int n = 0;
+    for (int i = 0; i < cnt; ++i) {
+        pos[n] = r0 + i;
+        val[n] = r0 + i;
+        ++n;
+    }
+    for (int i = 0; i < cnt; ++i) {
+        const int p = ipiv[r0 + i];
+        int ip = -1;
+        for (int q = 0; q < n; ++q)
+            if (pos[q] == p) ip = q;
+        if (ip < 0) {
+            pos[n] = p;
+            val[n] = p;
+            ip = n++;
+        }
+        const int t = val[i];   // entry i holds position r0 + i
+        val[i] = val[ip];
+        val[ip] = t;
+    }
+    int m = 0;
+    for (int q = 0; q < n; ++q)
+        if (val[q] != pos[q]) {
+            dst[m] = pos[q];
+            src[m] = val[q];
+            ++m;
+        }
+    return m;
+}
+
 // Panel factorisation.  One workgroup of NT threads per matrix.  The panel
 // is processed in sub-blocks of IB columns: each sub-block is first brought
 // up to date from the panel's earlier sub-blocks (left-looking), then held
 // in registers -- R rows per thread, rows c0 + tid + NT*r -- while its IB
 // columns are factored one by one (pivot search, swap, scale, rank-1
-// update).  Row interchanges are applied to the whole panel width at once.
-// At the end thread 0 composes the panel's interchanges into a list of
-// (destination row <- source row) moves for the other columns.
+// update).  After each sub-block its interchanges are composed into row
+// moves and applied to the rest of the panel in one pass; at the end the
+// whole panel's interchanges are composed into moves for the other columns.
 template <typename T, int NT, int R, int IB, int NB>
 __global__ __launch_bounds__(NT) void lu_panel_kernel(int n, cplx<T> *__restrict__ Fall, long ldf,
                                                       long sF, int k, int *__restrict__ ipiv_all,
@@ -82,7 +117,9 @@ __global__ __launch_bounds__(NT) void lu_panel_kernel(int n, cplx<T> *__restrict
     __shared__ int redi[NW];
     __shared__ int s_piv;
     __shared__ int s_pos[2 * NB], s_cnt[2 * NB];
-    __shared__ int s_n;
+    __shared__ int s_mvd[2 * NB], s_mvs[2 * NB];
+    __shared__ V s_stage[2 * IB][NB];
+    __shared__ int s_n, s_nmv;
 
     for (int jb = 0; jb < nbw; jb += IB) {
         const int c0 = k + jb;
@@ -110,7 +147,8 @@ __global__ __launch_bounds__(NT) void lu_panel_kernel(int n, cplx<T> *__restrict
             __syncthreads();
         }
 
-        // (b) load rows c0..n-1 of the sub-block and subtract L[c0:, k:c0] * U[k:c0, sub]
+        // (b) load rows c0..n-1 of the sub-block and subtract L[c0:, k:c0] * U[k:c0, sub];
+        //     the L columns are fetched CW at a time so the loads overlap
         V val[R][IB];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -119,18 +157,25 @@ __global__ __launch_bounds__(NT) void lu_panel_kernel(int n, cplx<T> *__restrict
             for (int c = 0; c < IB; ++c)
                 val[r][c] = (row < n && c < w) ? a[row + (long)(c0 + c) * ldf] : cmake<V>(0, 0);
         }
-        for (int l = 0; l < jb; ++l) {
-            V u[IB];
-#pragma unroll
-            for (int c = 0; c < IB; ++c) u[c] = Ush[l][c];
+        constexpr int CW = (16 / R) < 1 ? 1 : ((16 / R) > IB ? IB : (16 / R));   // columns per fetch
+        for (int l0 = 0; l0 < jb; l0 += CW) {
+            V lv[R][CW];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int row = c0 + tid + NT * r;
-                if (row < n) {
-                    const V lv = a[row + (long)(k + l) * ldf];
 #pragma unroll
-                    for (int c = 0; c < IB; ++c) val[r][c] = csub(val[r][c], cmul(lv, u[c]));
-                }
+                for (int q = 0; q < CW; ++q)
+                    lv[r][q] = (row < n) ? a[row + (long)(k + l0 + q) * ldf] : cmake<V>(0, 0);
+            }
+#pragma unroll
+            for (int q = 0; q < CW; ++q) {
+                V u[IB];
+#pragma unroll
+                for (int c = 0; c < IB; ++c) u[c] = Ush[l0 + q][c];
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+#pragma unroll
+                    for (int c = 0; c < IB; ++c) val[r][c] = csub(val[r][c], cmul(lv[r][q], u[c]));
             }
         }
 
@@ -202,16 +247,6 @@ __global__ __launch_bounds__(NT) void lu_panel_kernel(int n, cplx<T> *__restrict
 #pragma unroll
                             for (int c = 0; c < IB; ++c) grow[c] = val[r][c];
                 }
-                // the rest of the panel width, in memory
-                if (p != g) {
-                    for (int t = tid; t < nbw - w; t += NT) {
-                        const int col = (t < jb) ? (k + t) : (c0 + w + (t - jb));
-                        V *pc = a + (long)col * ldf;
-                        const V tg = pc[g];
-                        pc[g] = pc[p];
-                        pc[p] = tg;
-                    }
-                }
                 __syncthreads();
                 if (tid == own_p) {
 #pragma unroll
@@ -253,38 +288,35 @@ __global__ __launch_bounds__(NT) void lu_panel_kernel(int n, cplx<T> *__restrict
                 for (int c = 0; c < IB; ++c)
                     if (c < w) a[row + (long)(c0 + c) * ldf] = val[r][c];
         }
+        // (e) the sub-block's interchanges, composed into row moves, applied
+        //     to the other columns of the panel (all loads before any store)
+        if (tid == 0) s_nmv = compose_moves(ipiv, c0, w, s_pos, s_cnt, s_mvd, s_mvs);
+        __syncthreads();
+        {
+            const int nmv = s_nmv, nother = nbw - w;
+            for (int e = tid; e < nmv * nother; e += NT) {
+                const int q = e % nmv, t = e / nmv;
+                const int col = (t < jb) ? (k + t) : (c0 + w + (t - jb));
+                s_stage[q][t] = a[s_mvs[q] + (long)col * ldf];
+            }
+            __syncthreads();
+            for (int e = tid; e < nmv * nother; e += NT) {
+                const int q = e % nmv, t = e / nmv;
+                const int col = (t < jb) ? (k + t) : (c0 + w + (t - jb));
+                a[s_mvd[q] + (long)col * ldf] = s_stage[q][t];
+            }
+        }
         __syncthreads();
     }
 
-    // compose the interchanges k..k+nbw-1 into (dst <- src) moves
+    // compose the interchanges k..k+nbw-1 into (dst <- src) moves for the
+    // columns outside the panel
     if (tid == 0) {
-        int cnt = 0;
-        for (int i = 0; i < nbw; ++i) {
-            s_pos[cnt] = k + i;
-            s_cnt[cnt] = k + i;
-            ++cnt;
+        const int nm = compose_moves(ipiv, k, nbw, s_pos, s_cnt, s_mvd, s_mvs);
+        for (int q = 0; q < nm; ++q) {
+            swapmap[1 + q] = s_mvd[q];
+            swapmap[1 + 2 * NB + q] = s_mvs[q];
         }
-        for (int i = 0; i < nbw; ++i) {
-            const int p = ipiv[k + i];
-            int ip = -1;
-            for (int q = 0; q < cnt; ++q)
-                if (s_pos[q] == p) ip = q;
-            if (ip < 0) {
-                s_pos[cnt] = p;
-                s_cnt[cnt] = p;
-                ip = cnt++;
-            }
-            const int t = s_cnt[i];    // position k+i is entry i
-            s_cnt[i] = s_cnt[ip];
-            s_cnt[ip] = t;
-        }
-        int nm = 0;
-        for (int q = 0; q < cnt; ++q)
-            if (s_cnt[q] != s_pos[q]) {
-                swapmap[1 + nm] = s_pos[q];
-                swapmap[1 + 2 * NB + nm] = s_cnt[q];
-                ++nm;
-            }
         swapmap[0] = nm;
         s_n = nm;
     }
@@ -400,41 +432,78 @@ void lu_gemm_timing_begin(hipStream_t s, hipEvent_t *e);
 void lu_gemm_timing_end(hipStream_t s, hipEvent_t e0, double flops);
 
 template <typename T> struct panel_cfg;
-template <> struct panel_cfg<float> { static constexpr int NT = 256, IB = 4; };
-template <> struct panel_cfg<double> { static constexpr int NT = 256, IB = 2; };
+// Register budget: R rows x IB columns of complex values per thread.  Rows
+// per thread grow with n; the sub-block narrows so that R * IB stays <= 64
+// (c64) / 32 (c128) complex values.
+template <typename T> struct panel_cfg;
+template <> struct panel_cfg<float> {
+    static constexpr int NT = 512;
+    static constexpr int ib(int R) { return R <= 4 ? 8 : 4; }
+};
+template <> struct panel_cfg<double> {
+    static constexpr int NT = 512;
+    static constexpr int ib(int R) { return R <= 4 ? 4 : 2; }
+};
 
 template <typename T, int R>
 static void launch_panel(hipStream_t s, int n, cplx<T> *F, long ldf, long sF, int k, int *ipiv,
                          long sPiv, int *swapmap, int *info, int batch)
 {
     using P = panel_cfg<T>;
-    hipLaunchKernelGGL((lu_panel_kernel<T, P::NT, R, P::IB, LU_NB>), dim3(batch), dim3(P::NT), 0, s, n,
+    constexpr int IB = P::ib(R);
+    hipLaunchKernelGGL((lu_panel_kernel<T, P::NT, R, IB, LU_NB>), dim3(batch), dim3(P::NT), 0, s, n,
                        F, ldf, sF, k, ipiv, sPiv, swapmap, info);
     FX_LAUNCH_CHECK();
 }
 
-// Largest n the register-resident panel supports (32 rows per thread).
-template <typename T> constexpr int lu_max_n() { return 32 * panel_cfg<T>::NT; }
+// Largest n the register-resident panel supports (16 rows per thread).
+template <typename T> constexpr int lu_max_n() { return 16 * panel_cfg<T>::NT; }
 
 // Factor `batch` matrices of order n (stride sF, leading dimension ldf) in
 // place.  ipiv/perm: n ints per matrix (stride sPiv).  swapmap: (1 + 4 NB)
 // ints per matrix of scratch.  info: one int per matrix, 0 on success, else
 // 1 + the first zero/non-finite pivot index.
+//
+// Look-ahead of depth one: after the interchanges and U12 of panel k, the
+// columns of panel k+1 are updated first and that panel is factored on the
+// side stream s2 while the rest of the trailing update runs on s.  ev_a and
+// ev_b order the two streams; s2 == nullptr disables the look-ahead.
 template <typename T>
-void getrf_batched(hipStream_t s, int n, cplx<T> *F, long ldf, long sF, int *ipiv, int *perm,
-                   long sPiv, int *swapmap, int *info, int batch)
+static void launch_panel_rows(hipStream_t s, int n, cplx<T> *F, long ldf, long sF, int k, int *ipiv, long sPiv,
+                              int *swapmap, int *info, int batch)
 {
     using P = panel_cfg<T>;
+    const int R = ceil_div(n - k, P::NT);
+    if (R <= 1) launch_panel<T, 1>(s, n, F, ldf, sF, k, ipiv, sPiv, swapmap, info, batch);
+    else if (R <= 2) launch_panel<T, 2>(s, n, F, ldf, sF, k, ipiv, sPiv, swapmap, info, batch);
+    else if (R <= 4) launch_panel<T, 4>(s, n, F, ldf, sF, k, ipiv, sPiv, swapmap, info, batch);
+    else if (R <= 8) launch_panel<T, 8>(s, n, F, ldf, sF, k, ipiv, sPiv, swapmap, info, batch);
+    else launch_panel<T, 16>(s, n, F, ldf, sF, k, ipiv, sPiv, swapmap, info, batch);
+}
+
+template <typename T>
+static void lu_update(hipStream_t s, int n, cplx<T> *F, long ldf, long sF, int k, int nbw, int c0, int c1,
+                      int batch)
+{
+    // A[k+nbw:, c0:c1] -= L21 U12[:, c0:c1]
+    const int m2 = n - k - nbw, nc = c1 - c0;
+    if (m2 <= 0 || nc <= 0) return;
+    cplx<T> *L21 = F + (k + nbw) + (long)k * ldf;
+    cplx<T> *U12 = F + k + (long)c0 * ldf;
+    cplx<T> *A22 = F + (k + nbw) + (long)c0 * ldf;
+    hipEvent_t e0 = nullptr;
+    lu_gemm_timing_begin(s, &e0);
+    gemm<T, true, false>(s, m2, nc, nbw, T(-1), L21, ldf, sF, U12, ldf, sF, T(1), A22, ldf, sF, batch);
+    lu_gemm_timing_end(s, e0, 8.0 * m2 * (double)nc * nbw * batch);
+}
+
+template <typename T>
+void getrf_batched(hipStream_t s, hipStream_t s2, hipEvent_t ev_a, hipEvent_t ev_b, int n, cplx<T> *F, long ldf,
+                   long sF, int *ipiv, int *perm, long sPiv, int *swapmap, int *info, int batch)
+{
+    launch_panel_rows<T>(s, n, F, ldf, sF, 0, ipiv, sPiv, swapmap, info, batch);
     for (int k = 0; k < n; k += LU_NB) {
         const int nbw = std::min(LU_NB, n - k);
-        const int rows = n - k;
-        const int R = ceil_div(rows, P::NT);
-        if (R <= 1) launch_panel<T, 1>(s, n, F, ldf, sF, k, ipiv, sPiv, swapmap, info, batch);
-        else if (R <= 2) launch_panel<T, 2>(s, n, F, ldf, sF, k, ipiv, sPiv, swapmap, info, batch);
-        else if (R <= 4) launch_panel<T, 4>(s, n, F, ldf, sF, k, ipiv, sPiv, swapmap, info, batch);
-        else if (R <= 8) launch_panel<T, 8>(s, n, F, ldf, sF, k, ipiv, sPiv, swapmap, info, batch);
-        else if (R <= 16) launch_panel<T, 16>(s, n, F, ldf, sF, k, ipiv, sPiv, swapmap, info, batch);
-        else launch_panel<T, 32>(s, n, F, ldf, sF, k, ipiv, sPiv, swapmap, info, batch);
         const int outer = n - nbw;
         if (outer > 0) {
             dim3 grid(ceil_div(outer, 64), batch);
@@ -442,16 +511,20 @@ void getrf_batched(hipStream_t s, int n, cplx<T> *F, long ldf, long sF, int *ipi
                                k, nbw, swapmap);
             FX_LAUNCH_CHECK();
         }
-        const int m2 = n - k - nbw;
-        if (m2 > 0) {
-            cplx<T> *L21 = F + (k + nbw) + (long)k * ldf;
-            cplx<T> *U12 = F + k + (long)(k + nbw) * ldf;
-            cplx<T> *A22 = F + (k + nbw) + (long)(k + nbw) * ldf;
-            hipEvent_t e0 = nullptr;
-            lu_gemm_timing_begin(s, &e0);
-            gemm<T, true, false>(s, m2, m2, nbw, T(-1), L21, ldf, sF, U12, ldf, sF, T(1), A22, ldf,
-                                 sF, batch);
-            lu_gemm_timing_end(s, e0, 8.0 * m2 * (double)m2 * nbw * batch);
+        const int kn = k + nbw;            // next panel start
+        if (kn >= n) break;
+        const int nbw2 = std::min(LU_NB, n - kn);
+        if (s2) {
+            lu_update<T>(s, n, F, ldf, sF, k, nbw, kn, kn + nbw2, batch);
+            FX_CHECK(hipEventRecord(ev_a, s));
+            FX_CHECK(hipStreamWaitEvent(s2, ev_a, 0));
+            launch_panel_rows<T>(s2, n, F, ldf, sF, kn, ipiv, sPiv, swapmap, info, batch);
+            FX_CHECK(hipEventRecord(ev_b, s2));
+            lu_update<T>(s, n, F, ldf, sF, k, nbw, kn + nbw2, n, batch);
+            FX_CHECK(hipStreamWaitEvent(s, ev_b, 0));
+        } else {
+            lu_update<T>(s, n, F, ldf, sF, k, nbw, kn, n, batch);
+            launch_panel_rows<T>(s, n, F, ldf, sF, kn, ipiv, sPiv, swapmap, info, batch);
         }
     }
     hipLaunchKernelGGL((lu_finish_kernel<T>), dim3(batch), dim3(256), 0, s, n, F, ldf, sF, ipiv, sPiv,

@@ -3,10 +3,9 @@
 // Hermitian pencils, reusing the same factors):
 //   A_z Y = R   :  Y = U^{-1} L^{-1} P R
 //   A_z^H Y = R :  Y = P^T L^{-H} U^{-H} R
-// Blocked by NBS rows: a diagonal-block triangular solve (one thread per
-// right-hand side, the block's triangle in LDS), then a matrix-core update
-// of the remaining rows.  All contour nodes are solved in one launch per
-// step (blockIdx.y / blockIdx.z = node).
+// Blocked by NBS rows, with the diagonal blocks of L and U inverted once per
+// factorisation, so every step is a matrix-core product.  All contour nodes
+// are solved in one launch per step (blockIdx.y / blockIdx.z = node).
 #pragma once
 
 #include "common.hpp"
@@ -76,112 +75,110 @@ __global__ __launch_bounds__(256) void scatter_rows_kernel(int n, int ncols,
     out[blockIdx.y * sO + dst + (long)c * ldo] = Y[blockIdx.y * sY + i + (long)c * ldy];
 }
 
-enum tri_mode { TRI_L = 0, TRI_U = 1, TRI_UH = 2, TRI_LH = 3 };
-
-// Solve the w x w diagonal block at rows kb..kb+w-1 for every right-hand
-// side.  MODE selects op(T): L (unit lower, forward), U (upper, backward),
-// U^H (lower, forward), L^H (unit upper, backward).
-template <typename T, int MODE, int NBS>
-__global__ __launch_bounds__(64) void trsm_diag_kernel(int ncols, const cplx<T> *__restrict__ Fall,
-                                                       long ldf, long sF, int kb, int w,
-                                                       cplx<T> *__restrict__ Yall, long ldy, long sY)
+// Inverses of the NBS x NBS diagonal blocks of L (unit lower) and U (upper)
+// of every factor, computed once per factorisation: the triangular solves
+// then consist of matrix products only.  One workgroup per (block, node);
+// thread c solves for column c of the identity in LDS.
+template <typename T, int NBS>
+__global__ __launch_bounds__(NBS) void tri_inv_kernel(int n, const cplx<T> *__restrict__ Fall, long ldf,
+                                                      long sF, cplx<T> *__restrict__ Linv_all,
+                                                      cplx<T> *__restrict__ Uinv_all, long sInv)
 {
     using V = cplx<T>;
+    const int blk = blockIdx.x, kb = blk * NBS, w = min(NBS, n - kb);
     const V *a = Fall + blockIdx.y * sF;
-    V *Y = Yall + blockIdx.y * sY;
-    __shared__ V Tsh[NBS][NBS + 1];   // op(T)[i][l]
-    const int tid = threadIdx.x;
-    for (int e = tid; e < w * w; e += 64) {
-        const int i = e % w, l = e / w;
-        V v;
-        if (MODE == TRI_L || MODE == TRI_U) v = a[(kb + i) + (long)(kb + l) * ldf];
-        else v = cconj(a[(kb + l) + (long)(kb + i) * ldf]);
-        Tsh[i][l] = v;
+    V *Li = Linv_all + blockIdx.y * sInv + (long)blk * NBS * NBS;
+    V *Ui = Uinv_all + blockIdx.y * sInv + (long)blk * NBS * NBS;
+    __shared__ V Tsh[NBS][NBS + 1];
+    const int c = threadIdx.x;
+    for (int e = c; e < NBS * NBS; e += NBS) {
+        const int i = e % NBS, l = e / NBS;
+        Tsh[i][l] = (i < w && l < w) ? a[(kb + i) + (long)(kb + l) * ldf] : cmake<V>(i == l ? 1 : 0, 0);
     }
     __syncthreads();
-    const int c = blockIdx.x * 64 + tid;
-    if (c >= ncols) return;
-    V *y = Y + kb + (long)c * ldy;
+    // column c of L^{-1}: forward substitution on e_c (unit diagonal)
     V x[NBS];
 #pragma unroll
-    for (int i = 0; i < NBS; ++i) x[i] = (i < w) ? y[i] : cmake<V>(0, 0);
-    if constexpr (MODE == TRI_L || MODE == TRI_UH) {
+    for (int i = 0; i < NBS; ++i) x[i] = cmake<V>(i == c ? 1 : 0, 0);
 #pragma unroll
-        for (int i = 0; i < NBS; ++i) {
-            if (i < w) {
-                V s = x[i];
+    for (int i = 1; i < NBS; ++i)
 #pragma unroll
-                for (int l = 0; l < i; ++l) s = csub(s, cmul(Tsh[i][l], x[l]));
-                if constexpr (MODE == TRI_UH) s = cmul(s, cinv(Tsh[i][i]));
-                x[i] = s;
-            }
-        }
-    } else {
+        for (int l = 0; l < i; ++l) x[i] = csub(x[i], cmul(Tsh[i][l], x[l]));
 #pragma unroll
-        for (int i = NBS - 1; i >= 0; --i) {
-            if (i < w) {
-                V s = x[i];
+    for (int i = 0; i < NBS; ++i) Li[i + c * NBS] = (i < w && c < w) ? x[i] : cmake<V>(i == c ? 1 : 0, 0);
+    // column c of U^{-1}: backward substitution on e_c
 #pragma unroll
-                for (int l = i + 1; l < NBS; ++l)
-                    if (l < w) s = csub(s, cmul(Tsh[i][l], x[l]));
-                if constexpr (MODE == TRI_U) s = cmul(s, cinv(Tsh[i][i]));
-                x[i] = s;
-            }
-        }
+    for (int i = 0; i < NBS; ++i) x[i] = cmake<V>(i == c ? 1 : 0, 0);
+#pragma unroll
+    for (int i = NBS - 1; i >= 0; --i) {
+        V s = x[i];
+#pragma unroll
+        for (int l = i + 1; l < NBS; ++l) s = csub(s, cmul(Tsh[i][l], x[l]));
+        x[i] = cmul(s, cinv(Tsh[i][i]));
     }
 #pragma unroll
-    for (int i = 0; i < NBS; ++i)
-        if (i < w) y[i] = x[i];
+    for (int i = 0; i < NBS; ++i) Ui[i + c * NBS] = (i < w && c < w) ? x[i] : cmake<V>(i == c ? 1 : 0, 0);
 }
 
-template <typename T, int MODE>
-static void trsm_diag(hipStream_t s, int ncols, const cplx<T> *F, long ldf, long sF, int kb, int w,
-                      cplx<T> *Y, long ldy, long sY, int batch)
+template <typename T>
+void tri_inv_batched(hipStream_t s, int n, const cplx<T> *F, long ldf, long sF, cplx<T> *Linv, cplx<T> *Uinv,
+                     long sInv, int batch)
 {
-    dim3 grid(ceil_div(ncols, 64), batch);
-    hipLaunchKernelGGL((trsm_diag_kernel<T, MODE, SOLVE_NB>), grid, dim3(64), 0, s, ncols, F, ldf, sF,
-                       kb, w, Y, ldy, sY);
+    dim3 grid(ceil_div(n, SOLVE_NB), batch);
+    hipLaunchKernelGGL((tri_inv_kernel<T, SOLVE_NB>), grid, dim3(SOLVE_NB), 0, s, n, F, ldf, sF, Linv, Uinv, sInv);
     FX_LAUNCH_CHECK();
 }
 
-// In place: Y_b <- A_b^{-1} Y_b (adjoint = false, Y already row-permuted) or
-// Y_b <- U^{-H} then L^{-H} (adjoint = true, permutation applied afterwards
-// by the caller).
+inline long tri_inv_stride(int n) { return (long)ceil_div(n, SOLVE_NB) * SOLVE_NB * SOLVE_NB; }
+
+// Multi-RHS solve with the stored factors using only matrix products:
+//   adjoint = false:  Y <- U^{-1} L^{-1} Y   (Y already row-permuted)
+//   adjoint = true:   Y <- L^{-H} U^{-H} Y   (row permutation applied by the caller)
+// Block k of the forward sweep: X_k = Dinv_k Y_k, then Y_rest -= T_rest,k X_k;
+// the backward sweep runs the other way with the roles of X and Y swapped,
+// so the result ends in Y with no copies.  Dinv_k are the inverted
+// diagonal blocks from tri_inv_batched.
 template <typename T>
 void getrs_batched(hipStream_t s, bool adjoint, int n, int ncols, const cplx<T> *F, long ldf, long sF,
-                   cplx<T> *Y, long ldy, long sY, int batch)
+                   const cplx<T> *Linv, const cplx<T> *Uinv, long sInv, cplx<T> *Y, cplx<T> *X, long ldy,
+                   long sY, int batch)
 {
     constexpr int NB = SOLVE_NB;
     const int nblk = ceil_div(n, NB);
+    auto inv_blk = [&](const cplx<T> *base, int b) { return base + (long)b * NB * NB; };
     if (!adjoint) {
-        for (int b = 0; b < nblk; ++b) {       // L, forward
+        for (int b = 0; b < nblk; ++b) {       // L, forward: Y -> X
             const int kb = b * NB, w = std::min(NB, n - kb);
-            trsm_diag<T, TRI_L>(s, ncols, F, ldf, sF, kb, w, Y, ldy, sY, batch);
+            gemm<T, true, false>(s, w, ncols, w, T(1), inv_blk(Linv, b), NB, sInv, Y + kb, ldy, sY, T(0), X + kb,
+                                 ldy, sY, batch);
             if (kb + w < n)
-                gemm<T, true, false>(s, n - kb - w, ncols, w, T(-1), F + (kb + w) + (long)kb * ldf, ldf,
-                                     sF, Y + kb, ldy, sY, T(1), Y + kb + w, ldy, sY, batch);
+                gemm<T, true, false>(s, n - kb - w, ncols, w, T(-1), F + (kb + w) + (long)kb * ldf, ldf, sF, X + kb,
+                                     ldy, sY, T(1), Y + kb + w, ldy, sY, batch);
         }
-        for (int b = nblk - 1; b >= 0; --b) {  // U, backward
+        for (int b = nblk - 1; b >= 0; --b) {  // U, backward: X -> Y
             const int kb = b * NB, w = std::min(NB, n - kb);
-            trsm_diag<T, TRI_U>(s, ncols, F, ldf, sF, kb, w, Y, ldy, sY, batch);
+            gemm<T, true, false>(s, w, ncols, w, T(1), inv_blk(Uinv, b), NB, sInv, X + kb, ldy, sY, T(0), Y + kb,
+                                 ldy, sY, batch);
             if (kb > 0)
-                gemm<T, true, false>(s, kb, ncols, w, T(-1), F + (long)kb * ldf, ldf, sF, Y + kb, ldy,
-                                     sY, T(1), Y, ldy, sY, batch);
+                gemm<T, true, false>(s, kb, ncols, w, T(-1), F + (long)kb * ldf, ldf, sF, Y + kb, ldy, sY, T(1), X,
+                                     ldy, sY, batch);
         }
     } else {
-        for (int b = 0; b < nblk; ++b) {       // U^H, forward
+        for (int b = 0; b < nblk; ++b) {       // U^H, forward: Y -> X
             const int kb = b * NB, w = std::min(NB, n - kb);
-            trsm_diag<T, TRI_UH>(s, ncols, F, ldf, sF, kb, w, Y, ldy, sY, batch);
+            gemm<T, true, true>(s, w, ncols, w, T(1), inv_blk(Uinv, b), NB, sInv, Y + kb, ldy, sY, T(0), X + kb,
+                                ldy, sY, batch);
             if (kb + w < n)
-                gemm<T, true, true>(s, n - kb - w, ncols, w, T(-1), F + kb + (long)(kb + w) * ldf, ldf,
-                                    sF, Y + kb, ldy, sY, T(1), Y + kb + w, ldy, sY, batch);
+                gemm<T, true, true>(s, n - kb - w, ncols, w, T(-1), F + kb + (long)(kb + w) * ldf, ldf, sF, X + kb,
+                                    ldy, sY, T(1), Y + kb + w, ldy, sY, batch);
         }
-        for (int b = nblk - 1; b >= 0; --b) {  // L^H, backward
+        for (int b = nblk - 1; b >= 0; --b) {  // L^H, backward: X -> Y
             const int kb = b * NB, w = std::min(NB, n - kb);
-            trsm_diag<T, TRI_LH>(s, ncols, F, ldf, sF, kb, w, Y, ldy, sY, batch);
+            gemm<T, true, true>(s, w, ncols, w, T(1), inv_blk(Linv, b), NB, sInv, X + kb, ldy, sY, T(0), Y + kb,
+                                ldy, sY, batch);
             if (kb > 0)
-                gemm<T, true, true>(s, kb, ncols, w, T(-1), F + kb, ldf, sF, Y + kb, ldy, sY, T(1), Y,
-                                    ldy, sY, batch);
+                gemm<T, true, true>(s, kb, ncols, w, T(-1), F + kb, ldf, sF, Y + kb, ldy, sY, T(1), X, ldy, sY,
+                                    batch);
         }
     }
 }
