@@ -32,6 +32,7 @@
 #include "lu.hpp"
 #include "rr.hpp"
 #include "solve.hpp"
+#include "bortho.hpp"
 
 namespace fx {
 
@@ -305,7 +306,7 @@ static void device_eigh(Workspace &ws, hipStream_t s, int m, F64<CPLX> *C, F64<C
         double hh[64];
         FX_CHECK(hipMemcpy(hh, hist, sizeof(double) * std::min(hst[1], 64), hipMemcpyDeviceToHost));
         std::fprintf(stderr, "feastx eigh n=%d G=%d sweeps=%d off/fro:", m, G, hst[1]);
-        for (int i = 0; i < std::min(hst[1], 64); ++i) std::fprintf(stderr, " %.1e", hh[i]);
+        for (int i = 0; i < std::min(hst[1], 40); ++i) std::fprintf(stderr, " %.1e", hh[i]);
         std::fprintf(stderr, "\n");
     }
     if (hst[0] != 0) throw solver_error{-3};
@@ -314,6 +315,103 @@ static void device_eigh(Workspace &ws, hipStream_t s, int m, F64<CPLX> *C, F64<C
 constexpr double SPURIOUS_RES = 0.1;   // in-interval Ritz pairs above this residual are spurious
 constexpr double TRUNC = 1e-14;        // Bq eigen-directions below TRUNC * max are dropped
 constexpr double INDEFINITE = 1e-8;    // Bq eigenvalue below -INDEFINITE * max: B not definite
+constexpr double CHOL_DROP = 1e-12;    // scaled Cholesky pivots at or below this are dependent columns
+
+// B-orthonormal basis by diagonal scaling and Cholesky with column dropping
+// (columns visited in order of decreasing B-norm).  Returns the rank kept;
+// Tm (m x rank) receives T.
+template <bool CPLX>
+static int bortho_cholesky(Workspace &ws, hipStream_t s, int m, F64<CPLX> *Bq, F64<CPLX> *Tm)
+{
+    using E = F64<CPLX>;
+    const size_t mm = (size_t)m * m;
+    double *d = static_cast<double *>(ws.get("bo_d", sizeof(double) * m));
+    int *status = static_cast<int *>(ws.get("bo_status", sizeof(int) * 4));
+    int *ord = static_cast<int *>(ws.get("bo_ord", sizeof(int) * m));
+    int *row_of = static_cast<int *>(ws.get("bo_rowof", sizeof(int) * m));
+    int *kidx = static_cast<int *>(ws.get("bo_kidx", sizeof(int) * m));
+    int *keepf = static_cast<int *>(ws.get("bo_keep", sizeof(int) * m));
+    E *Bt = static_cast<E *>(ws.get("bo_bt", sizeof(E) * mm));
+    E *L = static_cast<E *>(ws.get("bo_l", sizeof(E) * mm));
+    E *Lk = static_cast<E *>(ws.get("bo_lk", sizeof(E) * mm));
+    E *Ti = static_cast<E *>(ws.get("bo_ti", sizeof(E) * mm));
+    E *Xi = static_cast<E *>(ws.get("bo_xi", sizeof(E) * mm));
+    const int nblk = ceil_div(m, TRI_NB);
+    E *Dinv = static_cast<E *>(ws.get("bo_dinv", sizeof(E) * (size_t)nblk * TRI_NB * TRI_NB));
+    double *h_d = static_cast<double *>(ws.pinned("bo_hd", sizeof(double) * m));
+    int *h_i = static_cast<int *>(ws.pinned("bo_hi", sizeof(int) * (4 + 3 * (size_t)m)));
+
+    FX_CHECK(hipMemsetAsync(status, 0, sizeof(int) * 4, s));
+    hipLaunchKernelGGL((diag_rsqrt_kernel<CPLX>), dim3(ceil_div(m, 256)), dim3(256), 0, s, m, Bq, (long)m, d, status);
+    FX_LAUNCH_CHECK();
+    FX_CHECK(hipMemcpyAsync(h_d, d, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+    FX_CHECK(hipMemcpyAsync(h_i, status, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
+    FX_CHECK(hipStreamSynchronize(s));
+    if (h_i[0] != 0) throw solver_error{-3};
+    // visit columns by decreasing B-norm (increasing d), ties by index
+    std::vector<int> order(m);
+    for (int i = 0; i < m; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return h_d[a] < h_d[b]; });
+    FX_CHECK(hipMemcpyAsync(ord, order.data(), sizeof(int) * m, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL((sym_scale_kernel<CPLX>), grid1((long)mm), dim3(256), 0, s, m, Bq, (long)m, d, ord, Bt, (long)m);
+    FX_LAUNCH_CHECK();
+    hipLaunchKernelGGL((chol_drop_kernel<CPLX>), dim3(1), dim3(CHOL_MAXM), 0, s, m, Bt, (long)m, L, (long)m, keepf,
+                       CHOL_DROP, INDEFINITE, status);
+    FX_LAUNCH_CHECK();
+    FX_CHECK(hipMemcpyAsync(h_i, status, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
+    FX_CHECK(hipMemcpyAsync(h_i + 4, keepf, sizeof(int) * m, hipMemcpyDeviceToHost, s));
+    FX_CHECK(hipStreamSynchronize(s));
+    if (h_i[0] != 0) throw solver_error{-3};
+    const int r = h_i[1];
+    if (r < 1) throw solver_error{-3};
+    // kept positions in Cholesky order -> original indices
+    int *h_kidx = h_i + 4 + m, *h_rowof = h_i + 4 + 2 * (size_t)m;
+    for (int i = 0; i < m; ++i) h_rowof[i] = -1;
+    int c = 0;
+    for (int a = 0; a < m; ++a)
+        if (h_i[4 + a]) {
+            h_kidx[c] = a;
+            h_rowof[order[a]] = c;
+            ++c;
+        }
+    FX_CHECK(hipMemcpyAsync(kidx, h_kidx, sizeof(int) * r, hipMemcpyHostToDevice, s));
+    FX_CHECK(hipMemcpyAsync(row_of, h_rowof, sizeof(int) * m, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL((gather_kk_kernel<CPLX>), grid1((long)r * r), dim3(256), 0, s, r, kidx, L, (long)m, Lk, (long)r);
+    hipLaunchKernelGGL((lower_block_inv_kernel<CPLX>), dim3(ceil_div(r, TRI_NB)), dim3(TRI_NB), 0, s, r, Lk, (long)r,
+                       Dinv);
+    hipLaunchKernelGGL((set_identity_kernel<CPLX>), grid1((long)r * r), dim3(256), 0, s, r, Xi, (long)r);
+    FX_LAUNCH_CHECK();
+    lower_inv_h<CPLX>(s, r, Lk, r, Dinv, Ti, Xi, r);
+    hipLaunchKernelGGL((scatter_scale_rows_kernel<CPLX>), grid1((long)m * r), dim3(256), 0, s, m, r, d, Ti, (long)r,
+                       Tm, (long)m, row_of);
+    FX_LAUNCH_CHECK();
+    FX_CHECK(hipStreamSynchronize(s));   // host order/index vectors go out of scope
+    return r;
+}
+
+// B-orthonormal basis from the eigendecomposition Bq = W diag(beta) W^H,
+// dropping directions with beta <= TRUNC * max (for subspaces beyond the
+// one-workgroup Cholesky).  Tm = W_keep beta^{-1/2}.
+template <bool CPLX>
+static int bortho_eigen(Workspace &ws, hipStream_t s, int m0, F64<CPLX> *Bq, F64<CPLX> *Wb, double *beta,
+                        F64<CPLX> *Tm, feast_stats &st)
+{
+    double *h_beta = static_cast<double *>(ws.pinned("h_beta", sizeof(double) * m0));
+    device_eigh<CPLX>(ws, s, m0, Bq, Wb, beta, st);
+    FX_CHECK(hipMemcpyAsync(h_beta, beta, sizeof(double) * m0, hipMemcpyDeviceToHost, s));
+    FX_CHECK(hipStreamSynchronize(s));
+    const double bmax = h_beta[m0 - 1];
+    if (!(bmax > 0.0) || h_beta[0] < -INDEFINITE * bmax) throw solver_error{-3};
+    int keep = 0;
+    for (int i = 0; i < m0; ++i)
+        if (h_beta[i] > TRUNC * bmax) ++keep;
+    const int first = m0 - keep;
+    hipLaunchKernelGGL((scale_cols_kernel<CPLX>), grid1((long)m0 * keep), dim3(256), 0, s, m0, keep, first, Wb,
+                       (long)m0, beta, Tm, (long)m0);
+    FX_LAUNCH_CHECK();
+    return keep;
+}
+
 
 template <typename T, bool CPLX>
 static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace &ws, Result &out)
@@ -502,20 +600,13 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
         FX_LAUNCH_CHECK();
         tm.mark(&st.t_rr);
 
-        // ---- reduced problem: Bq = W diag(beta) W^H, drop tiny directions,
-        //      T = W_keep beta^{-1/2}, eig(T^H Aq T) = (lambda, V), Phi = T V
-        device_eigh<CPLX>(ws, s, m0, Bq, Wb, beta, st);
-        FX_CHECK(hipMemcpyAsync(h_beta, beta, sizeof(double) * m0, hipMemcpyDeviceToHost, s));
-        FX_CHECK(hipStreamSynchronize(s));
-        const double bmax = h_beta[m0 - 1];
-        if (!(bmax > 0.0) || h_beta[0] < -INDEFINITE * bmax) throw solver_error{-3};
+        // ---- reduced problem.  B-orthonormal basis T of the kept columns
+        //      (T^H Bq T = I), then eig(T^H Aq T) = (lambda, V), Phi = T V.
         int keep = 0;
-        for (int i = 0; i < m0; ++i)
-            if (h_beta[i] > TRUNC * bmax) ++keep;
-        const int first = m0 - keep;
-        hipLaunchKernelGGL((scale_cols_kernel<CPLX>), grid1((long)m0 * keep), dim3(256), 0, s, m0, keep, first, Wb,
-                           (long)m0, beta, Tm, (long)m0);
-        FX_LAUNCH_CHECK();
+        if (m0 <= CHOL_MAXM)
+            keep = bortho_cholesky<CPLX>(ws, s, m0, Bq, Tm);
+        else
+            keep = bortho_eigen<CPLX>(ws, s, m0, Bq, Wb, beta, Tm, st);
         dgemm<CPLX>(s, false, m0, keep, m0, 1.0, Aq, m0, Tm, m0, 0.0, Tmp, m0);
         dgemm<CPLX>(s, true, keep, keep, m0, 1.0, Tm, m0, Tmp, m0, 0.0, Cr, keep);
         hipLaunchKernelGGL((hermitian_part_kernel<CPLX>), grid1((long)keep * keep), dim3(256), 0, s, keep, Cr,
