@@ -110,6 +110,79 @@ int feast_solve_z_dev(int N, const feast_z *dA, int lda, const feast_z *dB, int 
                       double Emax, int *M0, const feast_opts *opts, double *E, feast_z *dX, int ldx,
                       int *M, double *res, int *loop, double *epsout, void *stream);
 
+/* ---- batched: many independent problems in one call (the guide's first
+ * level of parallelism, independent search intervals / problems).  Each job
+ * carries its problem and receives its outputs; `opts` is shared (opts.x0 =
+ * 1: every job's X holds its start subspace).  device = 1: A, B, X are device
+ * arrays; 0: host arrays.  Up to `concurrency` problems (0: 4, at most 16)
+ * run at once, each on its own stream and device workspace, so their kernels
+ * overlap on the GPU; every job runs the same kernels as a single solve and
+ * gets the result it would get alone.  Returns 0 when every job ran (its
+ * status in job.info), or an argument error (-101 njobs, -102 jobs, -104
+ * device). */
+typedef struct {
+    int n;                  /* order N */
+    const void *A;          /* double (real symmetric) or feast_z (Hermitian), N x N */
+    int lda;
+    const void *B;          /* NULL: B = I */
+    int ldb;
+    double emin, emax;
+    int m0;                 /* subspace size */
+    void *X;                /* N x M0: start subspace (opts.x0 = 1) on entry, eigenvectors on exit */
+    int ldx;
+    double *E, *res;        /* M0 entries each */
+    /* outputs */
+    int info, M, m0_out, loop;
+    double epsout;
+    double ms;              /* wall time from submission to completion */
+} feast_job;
+int feast_solve_batched_d(int njobs, feast_job *jobs, const feast_opts *opts, int device, int concurrency);
+int feast_solve_batched_z(int njobs, feast_job *jobs, const feast_opts *opts, int device, int concurrency);
+
+/* ---- serving: a request loop that admits eigenproblems of mixed size while
+ * others run.  A request is admitted when a slot is free and its device
+ * footprint (factors + subspaces + staged inputs) fits next to the running
+ * ones within hbm_budget_gb (the oldest request first); admitted requests
+ * run concurrently on separate streams with their factors and subspaces
+ * resident on the device for all their FEAST loops.  Results are those of
+ * the same request solved alone.  The request's host arrays A, B (and X0)
+ * must stay valid until the request completes. */
+typedef struct feast_server feast_server;
+typedef struct {
+    int slots;              /* concurrent requests on the device (0: 4, at most 16) */
+    double hbm_budget_gb;   /* admission limit (0: 64 GB) */
+} feast_server_cfg;
+typedef struct {
+    int hermitian;          /* 0: real symmetric (double), 1: complex Hermitian (feast_z) */
+    int n;
+    const void *A;
+    int lda;
+    const void *B;          /* NULL: B = I */
+    int ldb;
+    double emin, emax;
+    int m0;
+    const void *X0;         /* NULL: seeded random start (opts.seed) */
+    int ldx;
+    feast_opts opts;        /* opts.x0 is set from X0 */
+} feast_request;
+typedef struct {
+    int info, M, m0, loop;
+    double epsout;
+    double *E, *res;        /* caller buffers of M0 entries, filled if not NULL */
+    void *X;                /* caller buffer N x M0 (leading dimension ldx), filled if not NULL */
+    int ldx;
+    double queue_ms, run_ms, latency_ms;   /* submit->start, start->end, submit->end */
+} feast_result;
+feast_server *feast_server_create(const feast_server_cfg *cfg);   /* NULL on failure */
+/* 0 on success (id set), else the request's argument/info error code */
+int feast_server_submit(feast_server *srv, const feast_request *req, unsigned long long *id);
+/* 0: done and out filled (the request is then forgotten); 1: still pending;
+ * -102: unknown id */
+int feast_server_poll(feast_server *srv, unsigned long long id, feast_result *out);
+int feast_server_wait(feast_server *srv, unsigned long long id, feast_result *out);
+/* finishes the queued requests, then frees everything */
+void feast_server_destroy(feast_server *srv);
+
 /* ---- tools (host only, no GPU).
  * Half-contour nodes and weights (tool "[cz]feast_contour", Gauss rule):
  * z_j = c + r e^{i theta_j}, w_j = (omega_j / 2) r e^{i theta_j},

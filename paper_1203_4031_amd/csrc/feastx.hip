@@ -16,7 +16,11 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <condition_variable>
 #include <cstring>
+#include <deque>
+#include <memory>
+#include <thread>
 #include <map>
 #include <mutex>
 #include <new>
@@ -105,6 +109,22 @@ struct Workspace {
         FX_CHECK(hipMemset(bar, 0, 2 * sizeof(unsigned)));
         FX_CHECK(hipDeviceSynchronize());
     }
+    double bytes() const
+    {
+        double b = 0;
+        for (auto &kv : dev) b += (double)kv.second.second;
+        return b;
+    }
+    // free the device buffers except the grid-barrier words
+    void trim()
+    {
+        for (auto &kv : dev)
+            if (kv.first != "grid_barrier" && kv.second.first) {
+                (void)hipFree(kv.second.first);
+                kv.second.first = nullptr;
+                kv.second.second = 0;
+            }
+    }
     void release()
     {
         for (auto &kv : dev)
@@ -125,6 +145,7 @@ struct Workspace {
 
 static Workspace g_ws;
 static std::mutex g_mu;
+static std::mutex g_coop_mu;   // cooperative launches take turns (see the executor)
 static feast_stats g_stats;
 static bool g_timing = false;
 static const bool g_debug = std::getenv("FEASTX_DEBUG") != nullptr;
@@ -236,7 +257,7 @@ struct GemmTimer {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
     double flops = 0;
 };
-static GemmTimer *g_gemm_timer = nullptr;
+static thread_local GemmTimer *g_gemm_timer = nullptr;
 
 // ------------------------------------------------------------ problem
 struct Problem {
@@ -292,6 +313,7 @@ static void device_eigh(Workspace &ws, hipStream_t s, int m, F64<CPLX> *C, F64<C
     double tol = 1e-13;
     unsigned *bar = ws.bar;
     void *args[] = {&m, &C, &ld, &V, &ld, &Rbuf, &partial, &bar, &max_sweeps, &tol, &inner, &status, &hist};
+    std::lock_guard<std::mutex> coop(g_coop_mu);
     FX_CHECK(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(bjacobi_kernel<CPLX>), dim3(G),
                                         dim3(BJ_NT), args, 0, s));
     hipLaunchKernelGGL((jacobi_sort_kernel<CPLX>), dim3(1), dim3(1024), 0, s, m, C, ld, V, ld, w, Vout, ld,
@@ -414,7 +436,8 @@ static int bortho_eigen(Workspace &ws, hipStream_t s, int m0, F64<CPLX> *Bq, F64
 
 
 template <typename T, bool CPLX>
-static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace &ws, Result &out)
+static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace &ws, Result &out,
+               feast_stats &st_out)
 {
     using E = F64<CPLX>;
     using V = cplx<T>;
@@ -581,7 +604,7 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
             tm.flush();
             st.loops = 1;
             st.m0_final = m0;
-            g_stats = st;
+            st_out = st;
             return 4;
         }
 
@@ -714,7 +737,7 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
         g_gemm_timer->ev.clear();
         g_gemm_timer->flops = 0;
     }
-    g_stats = st;
+    st_out = st;
     return info;
 }
 
@@ -739,18 +762,19 @@ static int validate(int n, int m0, double emin, double emax, const feast_opts &o
     return 0;
 }
 
-static int dispatch(bool cplx_in, const Problem &pb, const feast_opts &o, hipStream_t s, Result &out)
+static int dispatch(bool cplx_in, const Problem &pb, const feast_opts &o, hipStream_t s, Workspace &ws,
+                    Result &out, feast_stats &st)
 {
+    GemmTimer gt;
     try {
-        g_ws.init();
-        if (!s) s = g_ws.stream;
-        GemmTimer gt;
+        ws.init();
+        if (!s) s = ws.stream;
         g_gemm_timer = g_timing ? &gt : nullptr;
         int info;
         if (o.precision == 1)
-            info = cplx_in ? run<float, true>(pb, o, s, g_ws, out) : run<float, false>(pb, o, s, g_ws, out);
+            info = cplx_in ? run<float, true>(pb, o, s, ws, out, st) : run<float, false>(pb, o, s, ws, out, st);
         else
-            info = cplx_in ? run<double, true>(pb, o, s, g_ws, out) : run<double, false>(pb, o, s, g_ws, out);
+            info = cplx_in ? run<double, true>(pb, o, s, ws, out, st) : run<double, false>(pb, o, s, ws, out, st);
         g_gemm_timer = nullptr;
         return info;
     } catch (const alloc_error &) {
@@ -758,7 +782,7 @@ static int dispatch(bool cplx_in, const Problem &pb, const feast_opts &o, hipStr
         return -1;
     } catch (const solver_error &e) {
         g_gemm_timer = nullptr;
-        (void)hipStreamSynchronize(s ? s : g_ws.stream);
+        (void)hipStreamSynchronize(s ? s : ws.stream);
         return e.info;
     } catch (const hip_error &e) {
         g_gemm_timer = nullptr;
@@ -768,6 +792,105 @@ static int dispatch(bool cplx_in, const Problem &pb, const feast_opts &o, hipStr
         g_gemm_timer = nullptr;
         return -1;
     }
+}
+
+// One solve with arguments already checked.  `device` says whether A, B, X
+// are device (1) or host (0) arrays; host arrays are staged through the
+// workspace.  Fills E/res/M/... on info in {0,1,2,3}.
+struct SolveArgs {
+    bool cplx;
+    int n;
+    const void *A;
+    int lda;
+    const void *B;
+    int ldb;
+    double emin, emax;
+    int m0;
+    void *X;
+    int ldx;
+    double *E, *res;
+    int device;
+    hipStream_t stream;
+};
+struct SolveOut {
+    int info = 0, M = 0, m0 = 0, loop = 0;
+    double epsout = 1.0;
+    feast_stats st{};
+};
+
+static void copy_outputs(const Result &out, int info, const SolveArgs &a, SolveOut &so)
+{
+    so.info = info;
+    if (info == 0 || info == 1 || info == 2 || info == 3) {
+        for (int i = 0; i < out.m0; ++i) {
+            a.E[i] = out.E[i];
+            a.res[i] = out.res[i];
+        }
+        so.M = out.M;
+        so.m0 = out.m0;
+        so.loop = out.loop;
+        so.epsout = out.epsout;
+    } else if (info == 4) {
+        so.M = 0;
+        so.m0 = a.m0;
+        so.loop = 0;
+        so.epsout = 1.0;
+    } else {
+        so.m0 = a.m0;
+    }
+}
+
+static void solve_in(Workspace &ws, const feast_opts &o, const SolveArgs &a, SolveOut &so)
+{
+    Result out;
+    if (a.device) {
+        Problem pb{a.n, static_cast<const double *>(a.A), a.lda, static_cast<const double *>(a.B), a.ldb, a.emin,
+                   a.emax, a.m0, static_cast<double *>(a.X), a.ldx};
+        const int info = dispatch(a.cplx, pb, o, a.stream, ws, out, so.st);
+        copy_outputs(out, info, a, so);
+        return;
+    }
+    const size_t es = a.cplx ? 16 : 8;
+    const int N = a.n;
+    int info;
+    try {
+        ws.init();
+        hipStream_t s = ws.stream;
+        void *dA = ws.get("in_A", es * (size_t)N * N);
+        void *dB = a.B ? ws.get("in_B", es * (size_t)N * N) : nullptr;
+        void *dX = ws.get("in_X", es * (size_t)N * a.m0);
+        FX_CHECK(hipMemcpy2DAsync(dA, es * N, a.A, es * a.lda, es * N, N, hipMemcpyHostToDevice, s));
+        if (a.B) FX_CHECK(hipMemcpy2DAsync(dB, es * N, a.B, es * a.ldb, es * N, N, hipMemcpyHostToDevice, s));
+        if (o.x0) FX_CHECK(hipMemcpy2DAsync(dX, es * N, a.X, es * a.ldx, es * N, a.m0, hipMemcpyHostToDevice, s));
+        Problem pb{N, static_cast<const double *>(dA), N, static_cast<const double *>(dB), N, a.emin, a.emax, a.m0,
+                   static_cast<double *>(dX), N};
+        info = dispatch(a.cplx, pb, o, s, ws, out, so.st);
+        if (info == 0 || info == 1 || info == 2 || info == 3 || info == 4) {
+            const int mo = (info == 4) ? a.m0 : out.m0;
+            FX_CHECK(hipMemcpy2DAsync(a.X, es * a.ldx, dX, es * N, es * N, mo, hipMemcpyDeviceToHost, s));
+            FX_CHECK(hipStreamSynchronize(s));
+        }
+    } catch (const alloc_error &) {
+        info = -1;
+    } catch (const hip_error &e) {
+        std::fprintf(stderr, "feastx: HIP error %s\n", hipGetErrorString(e.code));
+        info = -4;
+    }
+    copy_outputs(out, info, a, so);
+}
+
+// Bytes of device memory one solve holds (factors, solve panels, FP64
+// subspace blocks, staged inputs), for admission decisions.
+static double footprint_bytes(bool cplx, int n, int m0, const feast_opts &o, bool staged)
+{
+    const double vb = (o.precision == 1) ? 8.0 : 16.0;   // complex factor element
+    const double eb = cplx ? 16.0 : 8.0;                  // FP64 element
+    const double nn = (double)n * n, nm = (double)n * m0, mm = (double)m0 * m0;
+    double b = o.ne * nn * vb;                            // factors
+    b += o.ne * nm * vb * (cplx ? 4.0 : 2.0);             // solve panels
+    b += 7.0 * nm * eb + 16.0 * mm * eb;                  // subspace blocks, reduced problem
+    if (staged) b += 2.0 * nn * eb + nm * eb;             // copies of A, B, X
+    return b;
 }
 
 }  // namespace fx
@@ -790,6 +913,133 @@ void lu_gemm_timing_end(hipStream_t s, hipEvent_t e0, double flops)
     g_gemm_timer->flops += flops;
 }
 }  // namespace fx
+
+// ======================================================================
+//            concurrent executor: batched solves and the server
+// ======================================================================
+namespace fx {
+
+// The reduced eigensolve is a cooperative launch with grid barriers; two of
+// them in flight on different streams could each hold part of the device
+// while waiting for the rest, so slots take turns for that launch
+// (g_coop_mu, held from launch to completion in device_eigh).
+
+struct Job {
+    SolveArgs args{};
+    feast_opts opts{};
+    SolveOut out;
+    double footprint = 0;
+    std::chrono::steady_clock::time_point t_submit, t_start, t_end;
+    bool done = false;
+    unsigned long long id = 0;
+    // server-owned host buffers
+    std::vector<double> E, res;
+    std::vector<unsigned char> X;
+};
+
+class Executor {
+  public:
+    Executor(int slots, double budget_bytes) : budget_(budget_bytes)
+    {
+        FX_CHECK(hipGetDevice(&device_));
+        for (int i = 0; i < slots; ++i) ws_.emplace_back(new Workspace());
+        for (int i = 0; i < slots; ++i) threads_.emplace_back([this, i] { worker(i); });
+    }
+    ~Executor()
+    {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            stopping_ = true;
+        }
+        cv_work_.notify_all();
+        for (auto &t : threads_) t.join();
+        for (auto &w : ws_) w->release();
+    }
+    void submit(const std::shared_ptr<Job> &j)
+    {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            j->t_submit = std::chrono::steady_clock::now();
+            queue_.push_back(j);
+        }
+        cv_work_.notify_all();
+    }
+    void wait(const std::shared_ptr<Job> &j)
+    {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_done_.wait(lk, [&] { return j->done; });
+    }
+    bool is_done(const std::shared_ptr<Job> &j)
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        return j->done;
+    }
+
+  private:
+    void worker(int slot)
+    {
+        (void)hipSetDevice(device_);
+        Workspace &ws = *ws_[slot];
+        for (;;) {
+            std::shared_ptr<Job> j;
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                // FIFO admission: the oldest request runs once its footprint
+                // fits next to the running ones (or nothing else runs)
+                cv_work_.wait(lk, [&] {
+                    return stopping_ ||
+                           (!queue_.empty() && (in_use_ + queue_.front()->footprint <= budget_ || running_ == 0));
+                });
+                if (queue_.empty()) {
+                    if (stopping_) return;
+                    continue;
+                }
+                j = queue_.front();
+                queue_.pop_front();
+                in_use_ += j->footprint;
+                ++running_;
+            }
+            j->t_start = std::chrono::steady_clock::now();
+            j->args.stream = nullptr;   // the slot's own stream
+            solve_in(ws, j->opts, j->args, j->out);
+            j->t_end = std::chrono::steady_clock::now();
+            // keep a slot's workspace near the size of what it runs
+            if (ws.bytes() > 2.0 * j->footprint + 512.0 * (1 << 20)) ws.trim();
+            {
+                std::lock_guard<std::mutex> lk(mu_);
+                in_use_ -= j->footprint;
+                --running_;
+                j->done = true;
+            }
+            cv_done_.notify_all();
+            cv_work_.notify_all();
+        }
+    }
+
+    std::vector<std::unique_ptr<Workspace>> ws_;
+    std::vector<std::thread> threads_;
+    std::deque<std::shared_ptr<Job>> queue_;
+    std::mutex mu_;
+    std::condition_variable cv_work_, cv_done_;
+    bool stopping_ = false;
+    double budget_, in_use_ = 0;
+    int running_ = 0;
+    int device_ = 0;
+};
+
+static double ms_between(std::chrono::steady_clock::time_point a, std::chrono::steady_clock::time_point b)
+{
+    return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
+}  // namespace fx
+
+struct feast_server {
+    std::unique_ptr<fx::Executor> ex;
+    std::mutex mu;
+    std::map<unsigned long long, std::shared_ptr<fx::Job>> jobs;
+    unsigned long long next_id = 1;
+};
 
 // ======================================================================
 //                                C interface
@@ -853,70 +1103,12 @@ int feast_rational(double emin, double emax, int ne, const double *eig, int m, d
     return 0;
 }
 
-static int solve_dev_common(bool cplx, int N, const void *dA, int lda, const void *dB, int ldb, double Emin,
-                            double Emax, int *M0, const feast_opts *opts, double *E, void *dX, int ldx, int *M,
-                            double *res, int *loop, double *epsout, void *stream)
+// Checks shared by the single-problem entry points; 0 if the call may run.
+static int check_args(int N, int M0, double Emin, double Emax, const feast_opts &o, const void *A, int lda,
+                      const void *B, int ldb, const void *X, int ldx, const double *E, const double *res,
+                      const int *M)
 {
-    if (!M0) return -108;
-    feast_opts o;
-    if (opts) o = *opts;
-    else feast_default_opts(&o);
-    int v = fx::validate(N, *M0, Emin, Emax, o);
-    if (v) return v;
-    if (!dA) return -102;
-    if (lda < N) return -103;
-    if (dB && ldb < N) return -105;
-    if (!dX) return -111;
-    if (ldx < N) return -112;
-    if (!E || !res || !M) return -110;
-    Problem pb{N, static_cast<const double *>(dA), lda, static_cast<const double *>(dB), ldb, Emin, Emax, *M0,
-               static_cast<double *>(dX), ldx};
-    Result out;
-    std::lock_guard<std::mutex> lk(fx::g_mu);
-    int info = fx::dispatch(cplx, pb, o, static_cast<hipStream_t>(stream), out);
-    if (info == 0 || info == 2 || info == 3 || info == 1) {
-        for (int i = 0; i < out.m0; ++i) {
-            E[i] = out.E[i];
-            res[i] = out.res[i];
-        }
-        *M = out.M;
-        *M0 = out.m0;
-        if (loop) *loop = out.loop;
-        if (epsout) *epsout = out.epsout;
-    } else if (info == 4) {
-        *M = 0;
-        if (loop) *loop = 0;
-        if (epsout) *epsout = 1.0;
-    }
-    return info;
-}
-
-int feast_solve_d_dev(int N, const double *dA, int lda, const double *dB, int ldb, double Emin, double Emax,
-                      int *M0, const feast_opts *opts, double *E, double *dX, int ldx, int *M, double *res,
-                      int *loop, double *epsout, void *stream)
-{
-    return solve_dev_common(false, N, dA, lda, dB, ldb, Emin, Emax, M0, opts, E, dX, ldx, M, res, loop, epsout,
-                            stream);
-}
-
-int feast_solve_z_dev(int N, const feast_z *dA, int lda, const feast_z *dB, int ldb, double Emin, double Emax,
-                      int *M0, const feast_opts *opts, double *E, feast_z *dX, int ldx, int *M, double *res,
-                      int *loop, double *epsout, void *stream)
-{
-    return solve_dev_common(true, N, dA, lda, dB, ldb, Emin, Emax, M0, opts, E, dX, ldx, M, res, loop, epsout,
-                            stream);
-}
-
-// Host-array forms: stage A, B, X through library-owned device buffers.
-static int solve_host_common(bool cplx, int N, const void *A, int lda, const void *B, int ldb, double Emin,
-                             double Emax, int *M0, const feast_opts *opts, double *E, void *X, int ldx, int *M,
-                             double *res, int *loop, double *epsout)
-{
-    if (!M0) return -108;
-    feast_opts o;
-    if (opts) o = *opts;
-    else feast_default_opts(&o);
-    int v = fx::validate(N, *M0, Emin, Emax, o);
+    int v = fx::validate(N, M0, Emin, Emax, o);
     if (v) return v;
     if (!A) return -102;
     if (lda < N) return -103;
@@ -924,62 +1116,64 @@ static int solve_host_common(bool cplx, int N, const void *A, int lda, const voi
     if (!X) return -111;
     if (ldx < N) return -112;
     if (!E || !res || !M) return -110;
-    const size_t es = cplx ? 16 : 8;
+    return 0;
+}
+
+static int solve_single(bool cplx, int device, int N, const void *A, int lda, const void *B, int ldb, double Emin,
+                        double Emax, int *M0, const feast_opts *opts, double *E, void *X, int ldx, int *M,
+                        double *res, int *loop, double *epsout, void *stream)
+{
+    if (!M0) return -108;
+    feast_opts o;
+    if (opts) o = *opts;
+    else feast_default_opts(&o);
+    int v = check_args(N, *M0, Emin, Emax, o, A, lda, B, ldb, X, ldx, E, res, M);
+    if (v) return v;
+    fx::SolveArgs a{cplx, N, A, lda, B, ldb, Emin, Emax, *M0, X, ldx, E, res, device,
+                    static_cast<hipStream_t>(stream)};
+    fx::SolveOut so;
     std::lock_guard<std::mutex> lk(fx::g_mu);
-    int info;
-    Result out;
-    try {
-        fx::g_ws.init();
-        hipStream_t s = fx::g_ws.stream;
-        void *dA = fx::g_ws.get("in_A", es * (size_t)N * N);
-        void *dB = B ? fx::g_ws.get("in_B", es * (size_t)N * N) : nullptr;
-        void *dX = fx::g_ws.get("in_X", es * (size_t)N * (*M0));
-        FX_CHECK(hipMemcpy2DAsync(dA, es * N, A, es * lda, es * N, N, hipMemcpyHostToDevice, s));
-        if (B) FX_CHECK(hipMemcpy2DAsync(dB, es * N, B, es * ldb, es * N, N, hipMemcpyHostToDevice, s));
-        if (o.x0) FX_CHECK(hipMemcpy2DAsync(dX, es * N, X, es * ldx, es * N, *M0, hipMemcpyHostToDevice, s));
-        Problem pb{N, static_cast<const double *>(dA), N, static_cast<const double *>(dB), N, Emin, Emax, *M0,
-                   static_cast<double *>(dX), N};
-        info = fx::dispatch(cplx, pb, o, s, out);
-        if (info == 0 || info == 1 || info == 2 || info == 3 || info == 4) {
-            const int mo = (info == 4) ? *M0 : out.m0;
-            FX_CHECK(hipMemcpy2DAsync(X, es * ldx, dX, es * N, es * N, mo, hipMemcpyDeviceToHost, s));
-            FX_CHECK(hipStreamSynchronize(s));
-        }
-    } catch (const fx::alloc_error &) {
-        return -1;
-    } catch (const fx::hip_error &e) {
-        std::fprintf(stderr, "feastx: HIP error %s\n", hipGetErrorString(e.code));
-        return -4;
+    fx::solve_in(fx::g_ws, o, a, so);
+    fx::g_stats = so.st;
+    if (so.info == 0 || so.info == 1 || so.info == 2 || so.info == 3 || so.info == 4) {
+        *M = so.M;
+        *M0 = so.m0;
+        if (loop) *loop = so.loop;
+        if (epsout) *epsout = so.epsout;
     }
-    if (info == 0 || info == 1 || info == 2 || info == 3) {
-        for (int i = 0; i < out.m0; ++i) {
-            E[i] = out.E[i];
-            res[i] = out.res[i];
-        }
-        *M = out.M;
-        *M0 = out.m0;
-        if (loop) *loop = out.loop;
-        if (epsout) *epsout = out.epsout;
-    } else if (info == 4) {
-        *M = 0;
-        if (loop) *loop = 0;
-        if (epsout) *epsout = 1.0;
-    }
-    return info;
+    return so.info;
+}
+
+int feast_solve_d_dev(int N, const double *dA, int lda, const double *dB, int ldb, double Emin, double Emax,
+                      int *M0, const feast_opts *opts, double *E, double *dX, int ldx, int *M, double *res,
+                      int *loop, double *epsout, void *stream)
+{
+    return solve_single(false, 1, N, dA, lda, dB, ldb, Emin, Emax, M0, opts, E, dX, ldx, M, res, loop, epsout,
+                        stream);
+}
+
+int feast_solve_z_dev(int N, const feast_z *dA, int lda, const feast_z *dB, int ldb, double Emin, double Emax,
+                      int *M0, const feast_opts *opts, double *E, feast_z *dX, int ldx, int *M, double *res,
+                      int *loop, double *epsout, void *stream)
+{
+    return solve_single(true, 1, N, dA, lda, dB, ldb, Emin, Emax, M0, opts, E, dX, ldx, M, res, loop, epsout,
+                        stream);
 }
 
 int feast_solve_d_ex(int N, const double *A, int lda, const double *B, int ldb, double Emin, double Emax, int *M0,
                      const feast_opts *opts, double *E, double *X, int ldx, int *M, double *res, int *loop,
                      double *epsout)
 {
-    return solve_host_common(false, N, A, lda, B, ldb, Emin, Emax, M0, opts, E, X, ldx, M, res, loop, epsout);
+    return solve_single(false, 0, N, A, lda, B, ldb, Emin, Emax, M0, opts, E, X, ldx, M, res, loop, epsout,
+                        nullptr);
 }
 
 int feast_solve_z_ex(int N, const feast_z *A, int lda, const feast_z *B, int ldb, double Emin, double Emax,
                      int *M0, const feast_opts *opts, double *E, feast_z *X, int ldx, int *M, double *res,
                      int *loop, double *epsout)
 {
-    return solve_host_common(true, N, A, lda, B, ldb, Emin, Emax, M0, opts, E, X, ldx, M, res, loop, epsout);
+    return solve_single(true, 0, N, A, lda, B, ldb, Emin, Emax, M0, opts, E, X, ldx, M, res, loop, epsout,
+                        nullptr);
 }
 
 int feast_solve_d(int N, const double *A, const double *B, double Emin, double Emax, int M0, int Ne, double tol,
@@ -1002,6 +1196,175 @@ int feast_solve_z(int N, const feast_z *A, const feast_z *B, double Emin, double
     o.tol = tol;
     int m0 = M0;
     return feast_solve_z_ex(N, A, N, B, N, Emin, Emax, &m0, &o, E, X, N, M, res, nullptr, nullptr);
+}
+
+// ---------------------------------------------------------------- batched
+static int solve_batched(bool cplx, int njobs, feast_job *jobs, const feast_opts *opts, int device,
+                         int concurrency)
+{
+    if (njobs < 0) return -101;
+    if (njobs > 0 && !jobs) return -102;
+    if (device != 0 && device != 1) return -104;
+    feast_opts o;
+    if (opts) o = *opts;
+    else feast_default_opts(&o);
+    if (concurrency <= 0) concurrency = 4;
+    concurrency = std::min(concurrency, 16);
+    std::vector<std::shared_ptr<fx::Job>> js(njobs);
+    try {
+        fx::Executor ex(std::min(concurrency, std::max(njobs, 1)), 1e300);
+        for (int i = 0; i < njobs; ++i) {
+            feast_job &q = jobs[i];
+            q.info = check_args(q.n, q.m0, q.emin, q.emax, o, q.A, q.lda, q.B, q.ldb, q.X, q.ldx, q.E, q.res,
+                                &q.M);
+            if (q.info) continue;
+            auto j = std::make_shared<fx::Job>();
+            j->args = fx::SolveArgs{cplx, q.n, q.A, q.lda, q.B, q.ldb, q.emin, q.emax, q.m0, q.X, q.ldx, q.E, q.res,
+                                    device, nullptr};
+            j->opts = o;
+            j->footprint = fx::footprint_bytes(cplx, q.n, q.m0, o, device == 0);
+            js[i] = j;
+            ex.submit(j);
+        }
+        for (int i = 0; i < njobs; ++i) {
+            if (!js[i]) continue;
+            ex.wait(js[i]);
+            feast_job &q = jobs[i];
+            const fx::SolveOut &so = js[i]->out;
+            q.info = so.info;
+            q.M = so.M;
+            q.m0_out = so.m0;
+            q.loop = so.loop;
+            q.epsout = so.epsout;
+            q.ms = fx::ms_between(js[i]->t_submit, js[i]->t_end);
+        }
+    } catch (const fx::hip_error &e) {
+        std::fprintf(stderr, "feastx: HIP error %s\n", hipGetErrorString(e.code));
+        return -4;
+    }
+    return 0;
+}
+
+int feast_solve_batched_d(int njobs, feast_job *jobs, const feast_opts *opts, int device, int concurrency)
+{
+    return solve_batched(false, njobs, jobs, opts, device, concurrency);
+}
+
+int feast_solve_batched_z(int njobs, feast_job *jobs, const feast_opts *opts, int device, int concurrency)
+{
+    return solve_batched(true, njobs, jobs, opts, device, concurrency);
+}
+
+// ---------------------------------------------------------------- server
+feast_server *feast_server_create(const feast_server_cfg *cfg)
+{
+    int slots = cfg && cfg->slots > 0 ? std::min(cfg->slots, 16) : 4;
+    double budget = (cfg && cfg->hbm_budget_gb > 0 ? cfg->hbm_budget_gb : 64.0) * 1e9;
+    try {
+        auto *srv = new feast_server();
+        srv->ex.reset(new fx::Executor(slots, budget));
+        return srv;
+    } catch (...) {
+        return nullptr;
+    }
+}
+
+int feast_server_submit(feast_server *srv, const feast_request *req, unsigned long long *id)
+{
+    if (!srv) return -101;
+    if (!req) return -102;
+    if (!id) return -103;
+    const feast_request &r = *req;
+    const bool cplx = r.hermitian != 0;
+    feast_opts o = r.opts;
+    o.x0 = r.X0 ? 1 : 0;
+    auto j = std::make_shared<fx::Job>();
+    const size_t es = cplx ? 16 : 8;
+    if (r.m0 >= 1 && r.n >= 1) {
+        j->E.assign(r.m0, 0.0);
+        j->res.assign(r.m0, 0.0);
+        j->X.assign(es * (size_t)r.n * r.m0, 0);
+        if (r.X0)
+            for (int c = 0; c < r.m0; ++c)
+                std::memcpy(j->X.data() + es * (size_t)r.n * c,
+                            static_cast<const unsigned char *>(r.X0) + es * (size_t)r.ldx * c, es * r.n);
+    }
+    int v = check_args(r.n, r.m0, r.emin, r.emax, o, r.A, r.lda, r.B, r.ldb, j->X.empty() ? nullptr : j->X.data(),
+                       r.n, j->E.empty() ? nullptr : j->E.data(), j->res.empty() ? nullptr : j->res.data(),
+                       &j->out.M);
+    if (v) return v;
+    j->args = fx::SolveArgs{cplx, r.n, r.A, r.lda, r.B, r.ldb, r.emin, r.emax, r.m0, j->X.data(), r.n,
+                            j->E.data(), j->res.data(), 0, nullptr};
+    j->opts = o;
+    j->footprint = fx::footprint_bytes(cplx, r.n, r.m0, o, true);
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        j->id = srv->next_id++;
+        srv->jobs[j->id] = j;
+    }
+    *id = j->id;
+    srv->ex->submit(j);
+    return 0;
+}
+
+static void fill_result(const fx::Job &j, feast_result *out)
+{
+    const fx::SolveOut &so = j.out;
+    out->info = so.info;
+    out->M = so.M;
+    out->m0 = so.m0;
+    out->loop = so.loop;
+    out->epsout = so.epsout;
+    out->queue_ms = fx::ms_between(j.t_submit, j.t_start);
+    out->run_ms = fx::ms_between(j.t_start, j.t_end);
+    out->latency_ms = fx::ms_between(j.t_submit, j.t_end);
+    const int m = so.m0;
+    const size_t es = j.args.cplx ? 16 : 8;
+    const int n = j.args.n;
+    if (out->E)
+        for (int i = 0; i < m; ++i) out->E[i] = j.E[i];
+    if (out->res)
+        for (int i = 0; i < m; ++i) out->res[i] = j.res[i];
+    if (out->X)
+        for (int c = 0; c < m; ++c)
+            std::memcpy(static_cast<unsigned char *>(out->X) + es * (size_t)out->ldx * c,
+                        j.X.data() + es * (size_t)n * c, es * n);
+}
+
+static int server_take(feast_server *srv, unsigned long long id, feast_result *out, bool block)
+{
+    if (!srv) return -101;
+    if (!out) return -103;
+    std::shared_ptr<fx::Job> j;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        auto it = srv->jobs.find(id);
+        if (it == srv->jobs.end()) return -102;
+        j = it->second;
+    }
+    if (block) srv->ex->wait(j);
+    else if (!srv->ex->is_done(j)) return 1;
+    fill_result(*j, out);
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->jobs.erase(id);
+    return 0;
+}
+
+int feast_server_poll(feast_server *srv, unsigned long long id, feast_result *out)
+{
+    return server_take(srv, id, out, false);
+}
+
+int feast_server_wait(feast_server *srv, unsigned long long id, feast_result *out)
+{
+    return server_take(srv, id, out, true);
+}
+
+void feast_server_destroy(feast_server *srv)
+{
+    if (!srv) return;
+    srv->ex.reset();   // drains queued requests, joins the workers
+    delete srv;
 }
 
 int feast_last_stats(feast_stats *st)

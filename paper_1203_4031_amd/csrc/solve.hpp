@@ -89,35 +89,28 @@ __global__ __launch_bounds__(NBS) void tri_inv_kernel(int n, const cplx<T> *__re
     const V *a = Fall + blockIdx.y * sF;
     V *Li = Linv_all + blockIdx.y * sInv + (long)blk * NBS * NBS;
     V *Ui = Uinv_all + blockIdx.y * sInv + (long)blk * NBS * NBS;
-    __shared__ V Tsh[NBS][NBS + 1];
+    __shared__ V Tsh[NBS][NBS + 1];   // the diagonal block (L below, U on and above the diagonal)
+    __shared__ V Xs[NBS][NBS + 1];    // column c of the inverse is owned by thread c
     const int c = threadIdx.x;
     for (int e = c; e < NBS * NBS; e += NBS) {
         const int i = e % NBS, l = e / NBS;
         Tsh[i][l] = (i < w && l < w) ? a[(kb + i) + (long)(kb + l) * ldf] : cmake<V>(i == l ? 1 : 0, 0);
     }
     __syncthreads();
-    // column c of L^{-1}: forward substitution on e_c (unit diagonal)
-    V x[NBS];
-#pragma unroll
-    for (int i = 0; i < NBS; ++i) x[i] = cmake<V>(i == c ? 1 : 0, 0);
-#pragma unroll
-    for (int i = 1; i < NBS; ++i)
-#pragma unroll
-        for (int l = 0; l < i; ++l) x[i] = csub(x[i], cmul(Tsh[i][l], x[l]));
-#pragma unroll
-    for (int i = 0; i < NBS; ++i) Li[i + c * NBS] = (i < w && c < w) ? x[i] : cmake<V>(i == c ? 1 : 0, 0);
-    // column c of U^{-1}: backward substitution on e_c
-#pragma unroll
-    for (int i = 0; i < NBS; ++i) x[i] = cmake<V>(i == c ? 1 : 0, 0);
-#pragma unroll
-    for (int i = NBS - 1; i >= 0; --i) {
-        V s = x[i];
-#pragma unroll
-        for (int l = i + 1; l < NBS; ++l) s = csub(s, cmul(Tsh[i][l], x[l]));
-        x[i] = cmul(s, cinv(Tsh[i][i]));
+    // L^{-1}: forward substitution on e_c, unit diagonal
+    for (int i = 0; i < NBS; ++i) {
+        V s = cmake<V>(i == c ? 1 : 0, 0);
+        for (int l = c; l < i; ++l) s = csub(s, cmul(Tsh[i][l], Xs[l][c]));
+        Xs[i][c] = (i < c) ? cmake<V>(0, 0) : s;
     }
-#pragma unroll
-    for (int i = 0; i < NBS; ++i) Ui[i + c * NBS] = (i < w && c < w) ? x[i] : cmake<V>(i == c ? 1 : 0, 0);
+    for (int i = 0; i < NBS; ++i) Li[i + c * NBS] = Xs[i][c];
+    // U^{-1}: backward substitution on e_c
+    for (int i = NBS - 1; i >= 0; --i) {
+        V s = cmake<V>(i == c ? 1 : 0, 0);
+        for (int l = i + 1; l <= c; ++l) s = csub(s, cmul(Tsh[i][l], Xs[l][c]));
+        Xs[i][c] = (i > c) ? cmake<V>(0, 0) : cmul(s, cinv(Tsh[i][i]));
+    }
+    for (int i = 0; i < NBS; ++i) Ui[i + c * NBS] = Xs[i][c];
 }
 
 template <typename T>

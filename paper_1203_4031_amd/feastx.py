@@ -39,6 +39,31 @@ class feast_stats(C.Structure):
                 ("m0_final", C.c_int), ("eig_calls", C.c_int), ("eig_sweeps", C.c_int)]
 
 
+class feast_job(C.Structure):
+    _fields_ = [("n", C.c_int), ("A", C.c_void_p), ("lda", C.c_int), ("B", C.c_void_p), ("ldb", C.c_int),
+                ("emin", C.c_double), ("emax", C.c_double), ("m0", C.c_int), ("X", C.c_void_p),
+                ("ldx", C.c_int), ("E", C.c_void_p), ("res", C.c_void_p), ("info", C.c_int),
+                ("M", C.c_int), ("m0_out", C.c_int), ("loop", C.c_int), ("epsout", C.c_double),
+                ("ms", C.c_double)]
+
+
+class feast_server_cfg(C.Structure):
+    _fields_ = [("slots", C.c_int), ("hbm_budget_gb", C.c_double)]
+
+
+class feast_request(C.Structure):
+    _fields_ = [("hermitian", C.c_int), ("n", C.c_int), ("A", C.c_void_p), ("lda", C.c_int),
+                ("B", C.c_void_p), ("ldb", C.c_int), ("emin", C.c_double), ("emax", C.c_double),
+                ("m0", C.c_int), ("X0", C.c_void_p), ("ldx", C.c_int), ("opts", feast_opts)]
+
+
+class feast_result(C.Structure):
+    _fields_ = [("info", C.c_int), ("M", C.c_int), ("m0", C.c_int), ("loop", C.c_int),
+                ("epsout", C.c_double), ("E", C.c_void_p), ("res", C.c_void_p), ("X", C.c_void_p),
+                ("ldx", C.c_int), ("queue_ms", C.c_double), ("run_ms", C.c_double),
+                ("latency_ms", C.c_double)]
+
+
 def lib():
     """Load libfeastx.so; raises if it has not been built."""
     global _lib
@@ -71,6 +96,17 @@ def lib():
         L.feast_release.argtypes = []
         L.feast_release.restype = None
         L.feast_version.restype = C.c_char_p
+        for name in ("feast_solve_batched_d", "feast_solve_batched_z"):
+            f = getattr(L, name)
+            f.argtypes = [C.c_int, C.POINTER(feast_job), op, C.c_int, C.c_int]
+        L.feast_server_create.argtypes = [C.POINTER(feast_server_cfg)]
+        L.feast_server_create.restype = C.c_void_p
+        L.feast_server_submit.argtypes = [C.c_void_p, C.POINTER(feast_request),
+                                          C.POINTER(C.c_ulonglong)]
+        L.feast_server_poll.argtypes = [C.c_void_p, C.c_ulonglong, C.POINTER(feast_result)]
+        L.feast_server_wait.argtypes = [C.c_void_p, C.c_ulonglong, C.POINTER(feast_result)]
+        L.feast_server_destroy.argtypes = [C.c_void_p]
+        L.feast_server_destroy.restype = None
         _lib = L
     return _lib
 
@@ -205,3 +241,112 @@ def set_timing(on: bool):
 
 def release():
     lib().feast_release()
+
+
+def solve_batched(problems, concurrency=4, **kw) -> list[Result]:
+    """Solve many independent problems in one call (host arrays).  `problems`
+    is a list of (A, B, emin, emax, m0, X0) tuples of one kind (all real or
+    all complex); X0 may be None only if every X0 is None."""
+    if not problems:
+        return []
+    cplx = any(np.iscomplexobj(p[0]) or (p[1] is not None and np.iscomplexobj(p[1])) for p in problems)
+    dt = np.complex128 if cplx else np.float64
+    x0 = problems[0][5] is not None
+    o = make_opts(x0=x0, **kw)
+    keep, jobs = [], (feast_job * len(problems))()
+    for i, (A, B, emin, emax, m0, X0) in enumerate(problems):
+        A = np.asfortranarray(A, dtype=dt)
+        n = A.shape[0]
+        Bf = None if B is None else np.asfortranarray(B, dtype=dt)
+        X = np.zeros((n, m0), dtype=dt, order="F")
+        if X0 is not None:
+            X[:, :] = X0
+        E = np.zeros(m0)
+        res = np.zeros(m0)
+        keep.append((A, Bf, X, E, res))
+        j = jobs[i]
+        j.n, j.A, j.lda = n, A.ctypes.data, n
+        j.B, j.ldb = (None if Bf is None else Bf.ctypes.data), n
+        j.emin, j.emax, j.m0 = float(emin), float(emax), m0
+        j.X, j.ldx, j.E, j.res = X.ctypes.data, n, E.ctypes.data, res.ctypes.data
+    f = lib().feast_solve_batched_z if cplx else lib().feast_solve_batched_d
+    rc = f(len(problems), jobs, C.byref(o), 0, concurrency)
+    if rc:
+        raise ValueError(f"feast_solve_batched: {rc}")
+    out = []
+    for (A, Bf, X, E, res), j in zip(keep, jobs):
+        k = j.m0_out if j.info != 4 else j.m0
+        r = Result(j.info, E[:k].copy(), X[:, :k].copy(order="F"), res[:k].copy(), j.M, k, j.loop,
+                   j.epsout)
+        r.ms = j.ms
+        out.append(r)
+    return out
+
+
+class Server:
+    """The library's request loop: submit() returns an id, wait()/poll()
+    return a Result with queue/run/latency times in milliseconds."""
+
+    def __init__(self, slots=4, hbm_budget_gb=64.0):
+        cfg = feast_server_cfg(slots, hbm_budget_gb)
+        self._h = lib().feast_server_create(C.byref(cfg))
+        if not self._h:
+            raise RuntimeError("feast_server_create failed")
+        self._keep = {}
+
+    def submit(self, A, B, emin, emax, m0, X0=None, **kw):
+        cplx = np.iscomplexobj(A) or (B is not None and np.iscomplexobj(B))
+        dt = np.complex128 if cplx else np.float64
+        A = np.asfortranarray(A, dtype=dt)
+        n = A.shape[0]
+        Bf = None if B is None else np.asfortranarray(B, dtype=dt)
+        X0f = None if X0 is None else np.asfortranarray(X0, dtype=dt)
+        req = feast_request()
+        req.hermitian, req.n, req.A, req.lda = int(cplx), n, A.ctypes.data, n
+        req.B, req.ldb = (None if Bf is None else Bf.ctypes.data), n
+        req.emin, req.emax, req.m0 = float(emin), float(emax), m0
+        req.X0, req.ldx = (None if X0f is None else X0f.ctypes.data), n
+        req.opts = make_opts(**kw)
+        rid = C.c_ulonglong(0)
+        rc = lib().feast_server_submit(self._h, C.byref(req), C.byref(rid))
+        if rc:
+            raise ValueError(f"feast_server_submit: {rc}")
+        self._keep[rid.value] = (A, Bf, X0f, n, m0, dt)
+        return rid.value
+
+    def _take(self, rid, block):
+        A, Bf, X0f, n, m0, dt = self._keep[rid]
+        E = np.zeros(m0)
+        res = np.zeros(m0)
+        X = np.zeros((n, m0), dtype=dt, order="F")
+        out = feast_result()
+        out.E, out.res, out.X, out.ldx = E.ctypes.data, res.ctypes.data, X.ctypes.data, n
+        f = lib().feast_server_wait if block else lib().feast_server_poll
+        rc = f(self._h, rid, C.byref(out))
+        if rc == 1:
+            return None
+        if rc:
+            raise ValueError(f"feast_server: {rc}")
+        del self._keep[rid]
+        k = out.m0
+        r = Result(out.info, E[:k].copy(), X[:, :k].copy(order="F"), res[:k].copy(), out.M, k,
+                   out.loop, out.epsout)
+        r.queue_ms, r.run_ms, r.latency_ms = out.queue_ms, out.run_ms, out.latency_ms
+        return r
+
+    def wait(self, rid):
+        return self._take(rid, True)
+
+    def poll(self, rid):
+        return self._take(rid, False)
+
+    def close(self):
+        if self._h:
+            lib().feast_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
