@@ -68,7 +68,8 @@ typedef struct {
  * on the solve's stream) and the algorithmic work behind them. */
 typedef struct {
     double t_total, t_shift, t_factor, t_solve, t_accum, t_rr, t_reduced, t_resid;
-    double t_lu_gemm;        /* time inside the LU trailing-update kernel launches */
+    double t_lu_gemm;        /* with feast_set_timing(1): time inside the complex64 matrix-product
+                                launches (LU trailing updates and triangular-solve updates) */
     double lu_gemm_flops;    /* algorithmic real flops of those launches (8 per complex multiply-add) */
     long long lu_gemm_launches;
     double factor_flops;     /* ne * (8/3) N^3 */
@@ -193,7 +194,8 @@ int feast_rational(double Emin, double Emax, int ne, const double *eig, int m, d
 
 /* Statistics of the last solve on this process; 0 on success. */
 int feast_last_stats(feast_stats *stats);
-/* Enable (1) or disable (0) per-launch timing of the LU trailing update. */
+/* Enable (1) or disable (0) per-launch HIP-event timing of the complex64
+ * matrix-product kernel (reported in feast_stats). */
 void feast_set_timing(int on);
 /* Free the library's device workspace. */
 void feast_release(void);

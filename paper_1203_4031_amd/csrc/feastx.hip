@@ -258,6 +258,7 @@ struct GemmTimer {
     double flops = 0;
 };
 static thread_local GemmTimer *g_gemm_timer = nullptr;
+void gemm_timing_reset();
 
 // ------------------------------------------------------------ problem
 struct Problem {
@@ -728,9 +729,8 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
             float ms = 0;
             FX_CHECK(hipEventElapsedTime(&ms, e.first, e.second));
             tot += ms;
-            (void)hipEventDestroy(e.first);
-            (void)hipEventDestroy(e.second);
         }
+        gemm_timing_reset();
         st.t_lu_gemm = tot;
         st.lu_gemm_flops = g_gemm_timer->flops;
         st.lu_gemm_launches = (long long)g_gemm_timer->ev.size();
@@ -895,23 +895,35 @@ static double footprint_bytes(bool cplx, int n, int m0, const feast_opts &o, boo
 
 }  // namespace fx
 
-// Trailing-update timing hook used by getrf_batched.
+// Per-launch timing hook of the complex64 matrix product (feast_set_timing).
+// Events come from a pool created once per thread, so the hook only records.
 namespace fx {
-void lu_gemm_timing_begin(hipStream_t s, hipEvent_t *e)
+static thread_local std::vector<hipEvent_t> t_event_pool;
+static thread_local size_t t_event_next = 0;
+static hipEvent_t pooled_event()
+{
+    if (t_event_next == t_event_pool.size()) {
+        hipEvent_t e;
+        FX_CHECK(hipEventCreate(&e));
+        t_event_pool.push_back(e);
+    }
+    return t_event_pool[t_event_next++];
+}
+void gemm_timing_begin(hipStream_t s, hipEvent_t *e)
 {
     if (!g_gemm_timer) return;
-    FX_CHECK(hipEventCreate(e));
+    *e = pooled_event();
     FX_CHECK(hipEventRecord(*e, s));
 }
-void lu_gemm_timing_end(hipStream_t s, hipEvent_t e0, double flops)
+void gemm_timing_end(hipStream_t s, hipEvent_t e0, double flops)
 {
     if (!g_gemm_timer) return;
-    hipEvent_t e1;
-    FX_CHECK(hipEventCreate(&e1));
+    hipEvent_t e1 = pooled_event();
     FX_CHECK(hipEventRecord(e1, s));
     g_gemm_timer->ev.push_back({e0, e1});
     g_gemm_timer->flops += flops;
 }
+void gemm_timing_reset() { t_event_next = 0; }
 }  // namespace fx
 
 // ======================================================================

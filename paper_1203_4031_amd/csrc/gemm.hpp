@@ -10,6 +10,8 @@
 // padding per row.
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace fx {
@@ -189,6 +191,10 @@ template <> struct gemm_cfg<float, false> {
     static constexpr int BM = 128, BN = 128, BK = 16, WM = 64, WN = 64;
 };
 
+// Optional per-launch timing of the complex64 product (defined by the driver).
+void gemm_timing_begin(hipStream_t s, hipEvent_t *e);
+void gemm_timing_end(hipStream_t s, hipEvent_t e0, double flops);
+
 template <typename T, bool CPLX, bool OPA_H>
 void gemm(hipStream_t s, int m, int n, int k, T alpha, const typename elem<T, CPLX>::type *A,
           long lda, long sA, const typename elem<T, CPLX>::type *B, long ldb, long sB, T beta,
@@ -202,10 +208,14 @@ void gemm(hipStream_t s, int m, int n, int k, T alpha, const typename elem<T, CP
         // C = beta C: reuse the kernel with k = 0 (the k loop does not run)
     }
     dim3 grid(ceil_div(m, cfg::BM) * ceil_div(n, cfg::BN), 1, batch);
+    constexpr bool timed = std::is_same<T, float>::value && CPLX;
+    hipEvent_t e0 = nullptr;
+    if (timed) gemm_timing_begin(s, &e0);
     hipLaunchKernelGGL((gemm_kernel<T, CPLX, OPA_H, cfg::BM, cfg::BN, cfg::BK, cfg::WM, cfg::WN>),
                        grid, dim3(NT), 0, s, m, n, k, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc,
                        sC);
     FX_LAUNCH_CHECK();
+    if (timed) gemm_timing_end(s, e0, 8.0 * m * (double)n * (k > 0 ? k : 0) * batch);
 }
 
 }  // namespace fx

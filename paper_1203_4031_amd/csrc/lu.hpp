@@ -427,9 +427,7 @@ __global__ __launch_bounds__(256) void lu_finish_kernel(int n, const cplx<T> *__
 
 constexpr int LU_NB = 32;
 
-// Optional per-launch timing of the trailing update (defined by the driver).
-void lu_gemm_timing_begin(hipStream_t s, hipEvent_t *e);
-void lu_gemm_timing_end(hipStream_t s, hipEvent_t e0, double flops);
+
 
 template <typename T> struct panel_cfg;
 // Register budget: R rows x IB columns of complex values per thread.  Rows
@@ -491,10 +489,7 @@ static void lu_update(hipStream_t s, int n, cplx<T> *F, long ldf, long sF, int k
     cplx<T> *L21 = F + (k + nbw) + (long)k * ldf;
     cplx<T> *U12 = F + k + (long)c0 * ldf;
     cplx<T> *A22 = F + (k + nbw) + (long)c0 * ldf;
-    hipEvent_t e0 = nullptr;
-    lu_gemm_timing_begin(s, &e0);
     gemm<T, true, false>(s, m2, nc, nbw, T(-1), L21, ldf, sF, U12, ldf, sF, T(1), A22, ldf, sF, batch);
-    lu_gemm_timing_end(s, e0, 8.0 * m2 * (double)nc * nbw * batch);
 }
 
 template <typename T>
