@@ -149,6 +149,7 @@ static std::mutex g_coop_mu;   // cooperative launches take turns (see the execu
 static feast_stats g_stats;
 static bool g_timing = false;
 static const bool g_debug = std::getenv("FEASTX_DEBUG") != nullptr;
+static const bool g_no_lookahead = std::getenv("FEASTX_NO_LOOKAHEAD") != nullptr;   // tuning knob
 
 // ------------------------------------------------------------ contour
 // Gauss-Legendre nodes on [-1, 1] by Newton iteration on P_n, evaluated with
@@ -521,7 +522,8 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
             shift_build<T>(s, CPLX, n, pb.A, pb.lda, pb.B, pb.ldb, dz, ne, F, ldf, sF);
             tm.mark(&st.t_shift);
             FX_CHECK(hipMemsetAsync(dinfo, 0, sizeof(int) * ne, s));
-            getrf_batched<T>(s, ws.side, ws.ev_a, ws.ev_b, n, F, ldf, sF, ipiv, perm, n, swapmap, dinfo, ne);
+            getrf_batched<T>(s, g_no_lookahead ? nullptr : ws.side, ws.ev_a, ws.ev_b, n, F, ldf, sF, ipiv, perm, n,
+                             swapmap, dinfo, ne);
             tri_inv_batched<T>(s, n, F, ldf, sF, Linv, Uinv, sInv, ne);
             tm.mark(&st.t_factor);
             FX_CHECK(hipMemcpyAsync(h_info, dinfo, sizeof(int) * ne, hipMemcpyDeviceToHost, s));

@@ -53,39 +53,41 @@ __global__ __launch_bounds__(256) void shift_build_kernel(int n, const double *_
     }
 }
 
-// Compose the row interchanges (r0 + i <-> ipiv[r0 + i]), i = 0..cnt-1,
+// Compose the row interchanges (r0 + i <-> piv[i]), i = 0..cnt-1 (cnt <= 32),
 // applied in order, into moves "row dst[q] receives the old row src[q]".
-// pos/val are scratch of 2 cnt entries.  Returns the number of moves.
-__device__ inline int compose_moves(const int *ipiv, int r0, int cnt, int *pos, int *val, int *dst, int *src)
+// Run by one whole wave: lane q tracks one touched row position (at most
+// 2 cnt <= 64 of them) and the row it currently holds; each interchange is a
+// ballot lookup and two shuffles.  piv is in LDS.  Returns the number of
+// moves (the same in every lane); dst/src (LDS) are written by the wave.
+__device__ inline int compose_moves_wave(const int *piv, int r0, int cnt, int *dst, int *src)
 {
-    int n = 0;
+    const int lane = threadIdx.x & 63;
+    int pos = lane < cnt ? r0 + lane : -1;
+    int val = pos;
+    int n = cnt;
     for (int i = 0; i < cnt; ++i) {
-        pos[n] = r0 + i;
-        val[n] = r0 + i;
-        ++n;
-    }
-    for (int i = 0; i < cnt; ++i) {
-        const int p = ipiv[r0 + i];
-        int ip = -1;
-        for (int q = 0; q < n; ++q)
-            if (pos[q] == p) ip = q;
-        if (ip < 0) {
-            pos[n] = p;
-            val[n] = p;
-            ip = n++;
+        const int p = piv[i];
+        const unsigned long long m = __ballot(pos == p);
+        int ip;
+        if (m) {
+            ip = __ffsll((unsigned long long)m) - 1;
+        } else {
+            ip = n;
+            if (lane == n) pos = val = p;
+            ++n;
         }
-        const int t = val[i];   // entry i holds position r0 + i
-        val[i] = val[ip];
-        val[ip] = t;
+        const int vi = __shfl(val, i, 64), vip = __shfl(val, ip, 64);
+        if (lane == i) val = vip;
+        if (lane == ip) val = vi;
     }
-    int m = 0;
-    for (int q = 0; q < n; ++q)
-        if (val[q] != pos[q]) {
-            dst[m] = pos[q];
-            src[m] = val[q];
-            ++m;
-        }
-    return m;
+    const bool mv = lane < n && val != pos;
+    const unsigned long long mm = __ballot(mv);
+    if (mv) {
+        const int slot = __popcll(mm & ((1ull << lane) - 1ull));
+        dst[slot] = pos;
+        src[slot] = val;
+    }
+    return __popcll(mm);
 }
 
 // Panel factorisation.  One workgroup of NT threads per matrix.  The panel
@@ -95,16 +97,24 @@ __device__ inline int compose_moves(const int *ipiv, int r0, int cnt, int *pos, 
 // columns are factored one by one (pivot search, swap, scale, rank-1
 // update).  After each sub-block its interchanges are composed into row
 // moves and applied to the rest of the panel in one pass; at the end the
-// whole panel's interchanges are composed into moves for the other columns.
+// whole panel's interchanges are composed into moves for the other columns
+// and applied to the row permutation perm (row i of P A is row perm[i] of A).
+// The sequential parts (move composition, the small triangular solve for
+// the sub-block's U rows) run on whole waves so that no step waits on one
+// thread's chain of memory round trips.
 template <typename T, int NT, int R, int IB, int NB>
 __global__ __launch_bounds__(NT) void lu_panel_kernel(int n, cplx<T> *__restrict__ Fall, long ldf,
                                                       long sF, int k, int *__restrict__ ipiv_all,
-                                                      long sPiv, int *__restrict__ swapmap_all,
+                                                      int *__restrict__ perm_all, long sPiv,
+                                                      int *__restrict__ swapmap_all,
                                                       int *__restrict__ info_all)
 {
     using V = cplx<T>;
+    static_assert(IB <= NT / 64, "one wave per sub-block column in the U-row solve");
+    static_assert(NB <= 32, "move composition tracks at most 64 rows");
     V *a = Fall + blockIdx.x * sF;
     int *ipiv = ipiv_all + blockIdx.x * sPiv;
+    int *perm = perm_all + blockIdx.x * sPiv;
     int *swapmap = swapmap_all + blockIdx.x * (1 + 4 * NB);
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     constexpr int NW = NT / 64;
@@ -112,37 +122,42 @@ __global__ __launch_bounds__(NT) void lu_panel_kernel(int n, cplx<T> *__restrict
 
     __shared__ V Lsh[NB][NB + 1];      // L11 of the panel so far (unit lower)
     __shared__ V Ush[NB][IB];          // U rows k..c0-1 of the current sub-block
-    __shared__ V prow[IB], grow[IB];
-    __shared__ T redv[NW];
-    __shared__ int redi[NW];
-    __shared__ int s_piv;
-    __shared__ int s_pos[2 * NB], s_cnt[2 * NB];
+    __shared__ V prow[2][IB], grow[2][IB];
+    __shared__ T redv[2][NW];
+    __shared__ int redi[2][NW];
+    __shared__ int s_ipiv[NB];
     __shared__ int s_mvd[2 * NB], s_mvs[2 * NB];
     __shared__ V s_stage[2 * IB][NB];
-    __shared__ int s_n, s_nmv;
+    __shared__ int s_nmv;
+
+    if (k == 0)
+        for (int i = tid; i < n; i += NT) perm[i] = i;
 
     for (int jb = 0; jb < nbw; jb += IB) {
         const int c0 = k + jb;
         const int w = min(IB, nbw - jb);
 
-        // (a) U rows k..c0-1 of this sub-block: solve with L11 (jb x jb, unit lower)
+        // (a) U rows k..c0-1 of this sub-block: L11 (jb x jb, unit lower)
+        //     solve, one wave per column, lane i holding row k + i
         if (jb > 0) {
             for (int e = tid; e < jb * jb; e += NT) {
                 const int i = e % jb, l = e / jb;
                 Lsh[i][l] = a[(k + i) + (long)(k + l) * ldf];
             }
-            for (int e = tid; e < jb * IB; e += NT) {
-                const int i = e % jb, c = e / jb;
-                Ush[i][c] = (c < w) ? a[(k + i) + (long)(c0 + c) * ldf] : cmake<V>(0, 0);
-            }
             __syncthreads();
-            if (tid < w) {
-                for (int i = 1; i < jb; ++i) {
-                    V s = Ush[i][tid];
-                    for (int l = 0; l < i; ++l) s = csub(s, cmul(Lsh[i][l], Ush[l][tid]));
-                    Ush[i][tid] = s;
+            if (wid < IB) {
+                const int c = wid;
+                V x = (c < w && lane < jb) ? a[(k + lane) + (long)(c0 + c) * ldf] : cmake<V>(0, 0);
+                for (int l = 0; l + 1 < jb; ++l) {
+                    V xl;
+                    xl.x = __shfl(x.x, l, 64);
+                    xl.y = __shfl(x.y, l, 64);
+                    if (lane > l && lane < jb) x = csub(x, cmul(Lsh[lane][l], xl));
                 }
-                for (int i = 0; i < jb; ++i) a[(k + i) + (long)(c0 + tid) * ldf] = Ush[i][tid];
+                if (lane < jb) {
+                    Ush[lane][c] = x;
+                    if (c < w) a[(k + lane) + (long)(c0 + c) * ldf] = x;
+                }
             }
             __syncthreads();
         }
@@ -179,11 +194,15 @@ __global__ __launch_bounds__(NT) void lu_panel_kernel(int n, cplx<T> *__restrict
             }
         }
 
-        // (c) factor the sub-block column by column
+        // (c) factor the sub-block column by column.  The reduction and row
+        //     buffers alternate between two copies, so one column needs two
+        //     barriers: a thread that writes copy b for column jj + 1 has
+        //     passed the second barrier of column jj, by which time every
+        //     read of copy b (column jj - 1) is done.
 #pragma unroll
         for (int jj = 0; jj < IB; ++jj) {
             if (jj < w) {
-                const int g = c0 + jj;
+                const int g = c0 + jj, b = jj & 1;
                 // pivot search: largest |re|+|im|, ties to the lowest row
                 T best = T(-1);
                 int bi = 0x7fffffff;
@@ -208,28 +227,28 @@ __global__ __launch_bounds__(NT) void lu_panel_kernel(int n, cplx<T> *__restrict
                     }
                 }
                 if (lane == 0) {
-                    redv[wid] = best;
-                    redi[wid] = bi;
+                    redv[b][wid] = best;
+                    redi[b][wid] = bi;
                 }
                 __syncthreads();
-                if (tid == 0) {
-                    T bv = redv[0];
-                    int bidx = redi[0];
-                    for (int q = 1; q < NW; ++q)
-                        if (redv[q] > bv || (redv[q] == bv && redi[q] < bidx)) {
-                            bv = redv[q];
-                            bidx = redi[q];
-                        }
-                    if (!(bv > T(0)) || bidx >= n) {
-                        // zero or non-finite column: keep the diagonal, flag the error
-                        bidx = g;
-                        if (info_all[blockIdx.x] == 0) info_all[blockIdx.x] = g + 1;
+                // every thread reduces the NW wave results the same way
+                T bv = redv[b][0];
+                int p = redi[b][0];
+#pragma unroll
+                for (int q = 1; q < NW; ++q) {
+                    const T ov = redv[b][q];
+                    const int oi = redi[b][q];
+                    if (ov > bv || (ov == bv && oi < p)) {
+                        bv = ov;
+                        p = oi;
                     }
-                    s_piv = bidx;
-                    ipiv[g] = bidx;
                 }
-                __syncthreads();
-                const int p = s_piv;
+                if (!(bv > T(0)) || p >= n) {
+                    // zero or non-finite column: keep the diagonal, flag the error
+                    p = g;
+                    if (tid == 0 && info_all[blockIdx.x] == 0) info_all[blockIdx.x] = g + 1;
+                }
+                if (tid == 0) s_ipiv[jb + jj] = p;
                 // exchange rows g and p of the sub-block through LDS
                 const int own_p = (p - c0) % NT, rp = (p - c0) / NT;
                 const int own_g = (g - c0) % NT, rg = (g - c0) / NT;
@@ -238,14 +257,14 @@ __global__ __launch_bounds__(NT) void lu_panel_kernel(int n, cplx<T> *__restrict
                     for (int r = 0; r < R; ++r)
                         if (r == rp)
 #pragma unroll
-                            for (int c = 0; c < IB; ++c) prow[c] = val[r][c];
+                            for (int c = 0; c < IB; ++c) prow[b][c] = val[r][c];
                 }
                 if (tid == own_g) {
 #pragma unroll
                     for (int r = 0; r < R; ++r)
                         if (r == rg)
 #pragma unroll
-                            for (int c = 0; c < IB; ++c) grow[c] = val[r][c];
+                            for (int c = 0; c < IB; ++c) grow[b][c] = val[r][c];
                 }
                 __syncthreads();
                 if (tid == own_p) {
@@ -253,18 +272,20 @@ __global__ __launch_bounds__(NT) void lu_panel_kernel(int n, cplx<T> *__restrict
                     for (int r = 0; r < R; ++r)
                         if (r == rp)
 #pragma unroll
-                            for (int c = 0; c < IB; ++c) val[r][c] = grow[c];
+                            for (int c = 0; c < IB; ++c) val[r][c] = grow[b][c];
                 }
                 if (tid == own_g) {
 #pragma unroll
                     for (int r = 0; r < R; ++r)
                         if (r == rg)
 #pragma unroll
-                            for (int c = 0; c < IB; ++c) val[r][c] = prow[c];
+                            for (int c = 0; c < IB; ++c) val[r][c] = prow[b][c];
                 }
                 // scale the column below the diagonal and update the sub-block
-                const V piv = prow[jj];
-                const V inv = (cabs1(piv) > T(0)) ? cinv(piv) : cmake<V>(0, 0);
+                V pr[IB];
+#pragma unroll
+                for (int c = 0; c < IB; ++c) pr[c] = prow[b][c];
+                const V inv = (cabs1(pr[jj]) > T(0)) ? cinv(pr[jj]) : cmake<V>(0, 0);
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const int row = c0 + tid + NT * r;
@@ -272,10 +293,9 @@ __global__ __launch_bounds__(NT) void lu_panel_kernel(int n, cplx<T> *__restrict
                         const V l = cmul(val[r][jj], inv);
                         val[r][jj] = l;
 #pragma unroll
-                        for (int c = jj + 1; c < IB; ++c) val[r][c] = csub(val[r][c], cmul(l, prow[c]));
+                        for (int c = jj + 1; c < IB; ++c) val[r][c] = csub(val[r][c], cmul(l, pr[c]));
                     }
                 }
-                __syncthreads();
             }
         }
 
@@ -290,7 +310,11 @@ __global__ __launch_bounds__(NT) void lu_panel_kernel(int n, cplx<T> *__restrict
         }
         // (e) the sub-block's interchanges, composed into row moves, applied
         //     to the other columns of the panel (all loads before any store)
-        if (tid == 0) s_nmv = compose_moves(ipiv, c0, w, s_pos, s_cnt, s_mvd, s_mvs);
+        __syncthreads();
+        if (wid == 0) {
+            const int nm = compose_moves_wave(s_ipiv + jb, c0, w, s_mvd, s_mvs);
+            if (lane == 0) s_nmv = nm;
+        }
         __syncthreads();
         {
             const int nmv = s_nmv, nother = nbw - w;
@@ -309,16 +333,23 @@ __global__ __launch_bounds__(NT) void lu_panel_kernel(int n, cplx<T> *__restrict
         __syncthreads();
     }
 
-    // compose the interchanges k..k+nbw-1 into (dst <- src) moves for the
-    // columns outside the panel
-    if (tid == 0) {
-        const int nm = compose_moves(ipiv, k, nbw, s_pos, s_cnt, s_mvd, s_mvs);
-        for (int q = 0; q < nm; ++q) {
-            swapmap[1 + q] = s_mvd[q];
-            swapmap[1 + 2 * NB + q] = s_mvs[q];
+    // the panel's interchanges: pivot indices, composed moves for the
+    // columns outside the panel, and the same moves applied to perm (set to
+    // the identity above when k == 0; the loop's last barrier orders it)
+    if (tid < nbw) ipiv[k + tid] = s_ipiv[tid];
+    if (wid == 0) {
+        const int nm = compose_moves_wave(s_ipiv, k, nbw, s_mvd, s_mvs);
+        int d = 0, v = 0;
+        if (lane < nm) {
+            d = s_mvd[lane];
+            const int sr = s_mvs[lane];
+            swapmap[1 + lane] = d;
+            swapmap[1 + 2 * NB + lane] = sr;
+            v = perm[sr];
         }
-        swapmap[0] = nm;
-        s_n = nm;
+        // the wave's loads of perm all return before its store is issued
+        if (lane < nm) perm[d] = v;
+        if (lane == 0) swapmap[0] = nm;
     }
 }
 
@@ -391,19 +422,13 @@ __global__ __launch_bounds__(256) void lu_swap_trsm_kernel(int n, cplx<T> *__res
     }
 }
 
-// After the last panel: compose all interchanges into perm (row i of P A is
-// row perm[i] of A) and flag a non-finite or zero diagonal of U.
+// After the last panel: flag a non-finite or zero diagonal of U (the first
+// such index + 1, unless the panels already flagged a pivot).
 template <typename T>
 __global__ __launch_bounds__(256) void lu_finish_kernel(int n, const cplx<T> *__restrict__ Fall,
-                                                        long ldf, long sF,
-                                                        const int *__restrict__ ipiv_all, long sPiv,
-                                                        int *__restrict__ perm_all,
-                                                        int *__restrict__ info_all)
+                                                        long ldf, long sF, int *__restrict__ info_all)
 {
     const cplx<T> *a = Fall + blockIdx.x * sF;
-    const int *ipiv = ipiv_all + blockIdx.x * sPiv;
-    int *perm = perm_all + blockIdx.x * sPiv;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) perm[i] = i;
     __shared__ int bad;
     if (threadIdx.x == 0) bad = 0x7fffffff;
     __syncthreads();
@@ -412,17 +437,7 @@ __global__ __launch_bounds__(256) void lu_finish_kernel(int n, const cplx<T> *__
         if (!(cabs1(d) > T(0)) || !isfinite(d.x) || !isfinite(d.y)) atomicMin(&bad, i + 1);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int i = 0; i < n; ++i) {
-            const int p = ipiv[i];
-            if (p != i) {
-                const int t = perm[i];
-                perm[i] = perm[p];
-                perm[p] = t;
-            }
-        }
-        if (bad != 0x7fffffff && info_all[blockIdx.x] == 0) info_all[blockIdx.x] = bad;
-    }
+    if (threadIdx.x == 0 && bad != 0x7fffffff && info_all[blockIdx.x] == 0) info_all[blockIdx.x] = bad;
 }
 
 constexpr int LU_NB = 32;
@@ -444,13 +459,13 @@ template <> struct panel_cfg<double> {
 };
 
 template <typename T, int R>
-static void launch_panel(hipStream_t s, int n, cplx<T> *F, long ldf, long sF, int k, int *ipiv,
+static void launch_panel(hipStream_t s, int n, cplx<T> *F, long ldf, long sF, int k, int *ipiv, int *perm,
                          long sPiv, int *swapmap, int *info, int batch)
 {
     using P = panel_cfg<T>;
     constexpr int IB = P::ib(R);
     hipLaunchKernelGGL((lu_panel_kernel<T, P::NT, R, IB, LU_NB>), dim3(batch), dim3(P::NT), 0, s, n,
-                       F, ldf, sF, k, ipiv, sPiv, swapmap, info);
+                       F, ldf, sF, k, ipiv, perm, sPiv, swapmap, info);
     FX_LAUNCH_CHECK();
 }
 
@@ -467,16 +482,16 @@ template <typename T> constexpr int lu_max_n() { return 16 * panel_cfg<T>::NT; }
 // side stream s2 while the rest of the trailing update runs on s.  ev_a and
 // ev_b order the two streams; s2 == nullptr disables the look-ahead.
 template <typename T>
-static void launch_panel_rows(hipStream_t s, int n, cplx<T> *F, long ldf, long sF, int k, int *ipiv, long sPiv,
-                              int *swapmap, int *info, int batch)
+static void launch_panel_rows(hipStream_t s, int n, cplx<T> *F, long ldf, long sF, int k, int *ipiv, int *perm,
+                              long sPiv, int *swapmap, int *info, int batch)
 {
     using P = panel_cfg<T>;
     const int R = ceil_div(n - k, P::NT);
-    if (R <= 1) launch_panel<T, 1>(s, n, F, ldf, sF, k, ipiv, sPiv, swapmap, info, batch);
-    else if (R <= 2) launch_panel<T, 2>(s, n, F, ldf, sF, k, ipiv, sPiv, swapmap, info, batch);
-    else if (R <= 4) launch_panel<T, 4>(s, n, F, ldf, sF, k, ipiv, sPiv, swapmap, info, batch);
-    else if (R <= 8) launch_panel<T, 8>(s, n, F, ldf, sF, k, ipiv, sPiv, swapmap, info, batch);
-    else launch_panel<T, 16>(s, n, F, ldf, sF, k, ipiv, sPiv, swapmap, info, batch);
+    if (R <= 1) launch_panel<T, 1>(s, n, F, ldf, sF, k, ipiv, perm, sPiv, swapmap, info, batch);
+    else if (R <= 2) launch_panel<T, 2>(s, n, F, ldf, sF, k, ipiv, perm, sPiv, swapmap, info, batch);
+    else if (R <= 4) launch_panel<T, 4>(s, n, F, ldf, sF, k, ipiv, perm, sPiv, swapmap, info, batch);
+    else if (R <= 8) launch_panel<T, 8>(s, n, F, ldf, sF, k, ipiv, perm, sPiv, swapmap, info, batch);
+    else launch_panel<T, 16>(s, n, F, ldf, sF, k, ipiv, perm, sPiv, swapmap, info, batch);
 }
 
 template <typename T>
@@ -496,7 +511,7 @@ template <typename T>
 void getrf_batched(hipStream_t s, hipStream_t s2, hipEvent_t ev_a, hipEvent_t ev_b, int n, cplx<T> *F, long ldf,
                    long sF, int *ipiv, int *perm, long sPiv, int *swapmap, int *info, int batch)
 {
-    launch_panel_rows<T>(s, n, F, ldf, sF, 0, ipiv, sPiv, swapmap, info, batch);
+    launch_panel_rows<T>(s, n, F, ldf, sF, 0, ipiv, perm, sPiv, swapmap, info, batch);
     for (int k = 0; k < n; k += LU_NB) {
         const int nbw = std::min(LU_NB, n - k);
         const int outer = n - nbw;
@@ -513,17 +528,16 @@ void getrf_batched(hipStream_t s, hipStream_t s2, hipEvent_t ev_a, hipEvent_t ev
             lu_update<T>(s, n, F, ldf, sF, k, nbw, kn, kn + nbw2, batch);
             FX_CHECK(hipEventRecord(ev_a, s));
             FX_CHECK(hipStreamWaitEvent(s2, ev_a, 0));
-            launch_panel_rows<T>(s2, n, F, ldf, sF, kn, ipiv, sPiv, swapmap, info, batch);
+            launch_panel_rows<T>(s2, n, F, ldf, sF, kn, ipiv, perm, sPiv, swapmap, info, batch);
             FX_CHECK(hipEventRecord(ev_b, s2));
             lu_update<T>(s, n, F, ldf, sF, k, nbw, kn + nbw2, n, batch);
             FX_CHECK(hipStreamWaitEvent(s, ev_b, 0));
         } else {
             lu_update<T>(s, n, F, ldf, sF, k, nbw, kn, n, batch);
-            launch_panel_rows<T>(s, n, F, ldf, sF, kn, ipiv, sPiv, swapmap, info, batch);
+            launch_panel_rows<T>(s, n, F, ldf, sF, kn, ipiv, perm, sPiv, swapmap, info, batch);
         }
     }
-    hipLaunchKernelGGL((lu_finish_kernel<T>), dim3(batch), dim3(256), 0, s, n, F, ldf, sF, ipiv, sPiv,
-                       perm, info);
+    hipLaunchKernelGGL((lu_finish_kernel<T>), dim3(batch), dim3(256), 0, s, n, F, ldf, sF, info);
     FX_LAUNCH_CHECK();
 }
 
