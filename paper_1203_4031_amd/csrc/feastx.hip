@@ -53,6 +53,15 @@ struct Workspace {
     hipStream_t stream = nullptr;
     hipStream_t side = nullptr;            // look-ahead panels of the LU
     hipEvent_t ev_a = nullptr, ev_b = nullptr;
+    // Factorisation on a split of the CUs: the trailing updates on `fmain`,
+    // the look-ahead panels on `fside`, which owns `fres` CUs per XCD that
+    // `fmain` never uses, so a panel starts at once instead of waiting for
+    // the trailing update to drain the device.  Created on first use, only
+    // for workspaces that ask for it (want_split).
+    bool want_split = false;
+    int fres = 0;
+    hipStream_t fmain = nullptr, fside = nullptr;
+    hipEvent_t ev_c = nullptr, ev_d = nullptr;
     unsigned *bar = nullptr;
     int device = -1;
     int num_cu = 0;
@@ -109,6 +118,44 @@ struct Workspace {
         FX_CHECK(hipMemset(bar, 0, 2 * sizeof(unsigned)));
         FX_CHECK(hipDeviceSynchronize());
     }
+    void drop_split()
+    {
+        if (fmain) (void)hipStreamDestroy(fmain);
+        if (fside) (void)hipStreamDestroy(fside);
+        if (ev_c) (void)hipEventDestroy(ev_c);
+        if (ev_d) (void)hipEventDestroy(ev_d);
+        fmain = fside = nullptr;
+        ev_c = ev_d = nullptr;
+        fres = 0;
+    }
+    // Streams for a factorisation of `batch` matrices with the CU split, or
+    // false when the split is not used.  The panel launch has one workgroup
+    // per matrix and workgroups go to the 8 XCDs in turn, so ceil(batch / 8)
+    // CUs per XCD are reserved.  Mask bit 33 x + 8 j (x = XCD, j < reserve)
+    // lands on XCD x both when the driver interleaves mask bits over the
+    // XCDs (bit i -> XCD i mod 8) and when it gives each XCD 32 consecutive
+    // bits, so no XCD is ever left without a CU on either stream.
+    bool split(int batch)
+    {
+        static const bool off = std::getenv("FEASTX_NO_CU_SPLIT") != nullptr;   // tuning knob
+        if (!want_split || off || num_cu != 256) return false;
+        const int r = std::min(4, std::max(1, (batch + 7) / 8));
+        if (fres == r) return true;
+        drop_split();
+        uint32_t pm[8] = {0}, mm[8];
+        for (int x = 0; x < 8; ++x)
+            for (int j = 0; j < r; ++j) {
+                const int b = 33 * x + 8 * j;
+                pm[b / 32] |= 1u << (b % 32);
+            }
+        for (int w = 0; w < 8; ++w) mm[w] = ~pm[w];
+        FX_CHECK(hipExtStreamCreateWithCUMask(&fmain, 8, mm));
+        FX_CHECK(hipExtStreamCreateWithCUMask(&fside, 8, pm));
+        FX_CHECK(hipEventCreateWithFlags(&ev_c, hipEventDisableTiming));
+        FX_CHECK(hipEventCreateWithFlags(&ev_d, hipEventDisableTiming));
+        fres = r;
+        return true;
+    }
     double bytes() const
     {
         double b = 0;
@@ -137,6 +184,7 @@ struct Workspace {
         if (side) (void)hipStreamDestroy(side);
         if (ev_a) (void)hipEventDestroy(ev_a);
         if (ev_b) (void)hipEventDestroy(ev_b);
+        drop_split();
         stream = side = nullptr;
         ev_a = ev_b = nullptr;
         bar = nullptr;
@@ -522,8 +570,17 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
             shift_build<T>(s, CPLX, n, pb.A, pb.lda, pb.B, pb.ldb, dz, ne, F, ldf, sF);
             tm.mark(&st.t_shift);
             FX_CHECK(hipMemsetAsync(dinfo, 0, sizeof(int) * ne, s));
-            getrf_batched<T>(s, g_no_lookahead ? nullptr : ws.side, ws.ev_a, ws.ev_b, n, F, ldf, sF, ipiv, perm, n,
-                             swapmap, dinfo, ne);
+            if (!g_no_lookahead && ws.split(ne)) {
+                FX_CHECK(hipEventRecord(ws.ev_c, s));
+                FX_CHECK(hipStreamWaitEvent(ws.fmain, ws.ev_c, 0));
+                getrf_batched<T>(ws.fmain, ws.fside, ws.ev_a, ws.ev_b, n, F, ldf, sF, ipiv, perm, n, swapmap,
+                                 dinfo, ne);
+                FX_CHECK(hipEventRecord(ws.ev_d, ws.fmain));
+                FX_CHECK(hipStreamWaitEvent(s, ws.ev_d, 0));
+            } else {
+                getrf_batched<T>(s, g_no_lookahead ? nullptr : ws.side, ws.ev_a, ws.ev_b, n, F, ldf, sF, ipiv,
+                                 perm, n, swapmap, dinfo, ne);
+            }
             tri_inv_batched<T>(s, n, F, ldf, sF, Linv, Uinv, sInv, ne);
             tm.mark(&st.t_factor);
             FX_CHECK(hipMemcpyAsync(h_info, dinfo, sizeof(int) * ne, hipMemcpyDeviceToHost, s));
@@ -1147,6 +1204,7 @@ static int solve_single(bool cplx, int device, int N, const void *A, int lda, co
                     static_cast<hipStream_t>(stream)};
     fx::SolveOut so;
     std::lock_guard<std::mutex> lk(fx::g_mu);
+    fx::g_ws.want_split = true;
     fx::solve_in(fx::g_ws, o, a, so);
     fx::g_stats = so.st;
     if (so.info == 0 || so.info == 1 || so.info == 2 || so.info == 3 || so.info == 4) {
