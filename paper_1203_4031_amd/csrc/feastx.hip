@@ -348,26 +348,30 @@ static void device_eigh(Workspace &ws, hipStream_t s, int m, F64<CPLX> *C, F64<C
 {
     using E = F64<CPLX>;
     E *V = static_cast<E *>(ws.get("jac_v", sizeof(E) * (size_t)m * m));
-    const int nb = (m + BJ_BS - 1) / BJ_BS, npairs = (nb + (nb & 1)) / 2;
-    E *Rbuf = static_cast<E *>(ws.get("jac_r", sizeof(E) * (size_t)npairs * BJ_W * BJ_W));
+    E *C1 = static_cast<E *>(ws.get("jac_c1", sizeof(E) * (size_t)m * m));
+    const int nb = (m + BJ_BS - 1) / BJ_BS, nbp = nb + (nb & 1), npairs = nbp / 2;
+    E *Rbuf = static_cast<E *>(ws.get("jac_r", sizeof(E) * 2 * (size_t)npairs * BJ_W * BJ_W));
+    E *Dbuf = static_cast<E *>(ws.get("jac_d", sizeof(E) * (size_t)nbp * BJ_BS * BJ_BS));
+    double *dout = static_cast<double *>(ws.get("jac_diag", sizeof(double) * m));
     const int nrc = (m + BJ_W - 1) / BJ_W;
-    // enough blocks for the tile updates, few enough to keep grid barriers cheap
-    int G = std::max(npairs, std::min(npairs * npairs + nrc * npairs, 64));
+    const int nitems = npairs * (npairs + 1) / 2 + nrc * npairs;
+    // one workgroup per block pair plus about two tile updates per other
+    // workgroup, few enough to keep grid barriers cheap
+    int G = std::max(npairs + 1, std::min(npairs + (nitems + 1) / 2, 96));
     G = std::min(G, ws.jac_max_blocks);
     double *partial = static_cast<double *>(ws.get("jac_partial", sizeof(double) * 2 * 1024));
     int *status = static_cast<int *>(ws.get("jac_status", sizeof(int) * 2));
     double *hist = static_cast<double *>(ws.get("jac_hist", sizeof(double) * 64));
     int *rank = static_cast<int *>(ws.get("jac_rank", sizeof(int) * m));
     long ld = m;
-    int max_sweeps = 40, inner = 1;
+    int max_sweeps = 40;
     double tol = 1e-13;
     unsigned *bar = ws.bar;
-    void *args[] = {&m, &C, &ld, &V, &ld, &Rbuf, &partial, &bar, &max_sweeps, &tol, &inner, &status, &hist};
+    void *args[] = {&m, &C, &C1, &ld, &V, &ld, &Rbuf, &Dbuf, &partial, &bar, &max_sweeps, &tol, &status, &hist, &dout};
     std::lock_guard<std::mutex> coop(g_coop_mu);
     FX_CHECK(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(bjacobi_kernel<CPLX>), dim3(G),
                                         dim3(BJ_NT), args, 0, s));
-    hipLaunchKernelGGL((jacobi_sort_kernel<CPLX>), dim3(1), dim3(1024), 0, s, m, C, ld, V, ld, w, Vout, ld,
-                       rank);
+    hipLaunchKernelGGL((jacobi_sort_kernel<CPLX>), dim3(1), dim3(1024), 0, s, m, dout, V, ld, w, Vout, ld, rank);
     FX_LAUNCH_CHECK();
     int *hst = static_cast<int *>(ws.pinned("jac_status_h", sizeof(int) * 2));
     FX_CHECK(hipMemcpyAsync(hst, status, sizeof(int) * 2, hipMemcpyDeviceToHost, s));

@@ -37,31 +37,38 @@ template <bool CPLX> __device__ inline void jstore(typename jelem<CPLX>::type *p
 
 __device__ inline void rr_pair(int s, int i, int p, int &a, int &b)
 {
-    // circle method: index p-1 is fixed, the others rotate
-    if (i == 0) {
-        a = p - 1;
-        b = s;
-    } else {
-        a = (s + i) % (p - 1);
-        b = (s - i + (p - 1)) % (p - 1);
-    }
-    if (a > b) {
-        const int t = a;
-        a = b;
-        b = t;
-    }
+    // circle method: index p-1 is fixed, the others rotate (branch-free)
+    const int x = (s + i) % (p - 1), y = (s - i + (p - 1)) % (p - 1);
+    const int a0 = (i == 0) ? p - 1 : x, b0 = (i == 0) ? s : y;
+    a = min(a0, b0);
+    b = max(a0, b0);
 }
 
 // ------------------------------------------------------------------------
 // Two-level (block) parallel Jacobi.  The index set is split into blocks of
-// BJ_BS; each round of a sweep pairs the blocks (circle method) and, for
-// every block pair P = (I, J), one workgroup runs inner Jacobi sweeps on the
-// 2*BJ_BS principal submatrix in LDS and accumulates its rotations into a
-// unitary R_P.  After a grid barrier every 2BS x 2BS tile of the matrix is
-// replaced by R_P^H C_PQ R_Q and the eigenvector columns by V_Q R_Q.  Each
-// outer sweep applies every scalar rotation pair at least once, so the
-// convergence is that of cyclic Jacobi, with two grid barriers per round
-// instead of one per scalar round.
+// BJ_BS; round t of the iteration pairs the blocks by the circle method
+// (pairing t mod (nbp - 1)), and for every block pair P = (I, J) one
+// workgroup runs an inner Jacobi sweep on the 2 BS x 2 BS principal
+// submatrix of C_t in LDS, accumulating its rotations into a unitary R_t,P.
+// Then C_{t+1} = R_t^H C_t R_t (tile by tile: C'_PQ = R_P^H C_PQ R_Q) and
+// V_{t+1} = V_t R_t.  One outer sweep (nbp - 1 rounds) applies every scalar
+// rotation pair at least once, so the convergence is that of cyclic Jacobi.
+//
+// Pipelining: the pair submatrix that round t needs is built from round
+// t-1's results directly -- its diagonal blocks are the diagonal blocks of
+// round t-1's rotated pair submatrices (kept in Dbuf), its off-diagonal
+// block is R_{t-1,P1}^H C_{t-1}[P1, P2] R_{t-1,P2} restricted to blocks I
+// and J (P1, P2 the round t-1 pairs holding I and J) -- so the inner sweeps
+// of round t run while other workgroups form C_t, and each round costs one
+// grid barrier.  C is double-buffered (C_t read, C_{t+1} written) and so is
+// R; only the tiles P <= Q are formed (C is Hermitian), the others are
+// written as their mirror.  The off-diagonal norm is summed from
+// per-workgroup partials in a fixed order, so every workgroup takes the
+// same stopping decision.
+//
+// Rotation for a pair (a < b), c_ab = |c_ab| e^{i phi}, d = c_bb - c_aa:
+//   t = sign(d) 2|c_ab| / (|d| + sqrt(d^2 + 4 |c_ab|^2))  (tan of the angle),
+//   c = 1/sqrt(1 + t^2), s = t c,  J = [[c, s e^{i phi}], [-s e^{-i phi}, c]].
 constexpr int BJ_BS = 16;
 constexpr int BJ_W = 2 * BJ_BS;
 constexpr int BJ_NT = 256;
@@ -72,6 +79,8 @@ __device__ inline double jconj(double a) { return a; }
 __device__ inline double2 jconj(double2 a) { return make_double2(a.x, -a.y); }
 __device__ inline double jadd(double a, double b) { return a + b; }
 __device__ inline double2 jadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ inline double jsub(double a, double b) { return a - b; }
+__device__ inline double2 jsub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ inline double jabs2(double a) { return a * a; }
 __device__ inline double jabs2(double2 a) { return a.x * a.x + a.y * a.y; }
 template <typename E> __device__ inline E jzero();
@@ -82,38 +91,85 @@ template <> __device__ inline double jreal<double>(double v) { return v; }
 template <> __device__ inline double2 jreal<double2>(double v) { return make_double2(v, 0.0); }
 __device__ inline double jre(double a) { return a; }
 __device__ inline double jre(double2 a) { return a.x; }
-// s e^{+i phi} (sign = +1) or s e^{-i phi} (sign = -1) as an element
-template <typename E> __device__ inline E jphase(double s, double2 ph, double sign);
-template <> __device__ inline double jphase<double>(double s, double2 ph, double) { return s * ph.x; }
-template <> __device__ inline double2 jphase<double2>(double s, double2 ph, double sign)
+__device__ inline double jscale(double a, double c) { return a * c; }
+__device__ inline double2 jscale(double2 a, double c) { return make_double2(a.x * c, a.y * c); }
+// which pair of the circle-method pairing `s` (p indices) holds index I, and
+// whether I is its first (0) or second (1) member
+__device__ inline void rr_locate(int s, int I, int p, int &pair, int &half)
 {
-    return make_double2(s * ph.x, sign * s * ph.y);
+    int i;
+    if (I == p - 1 || I == s) {
+        i = 0;
+    } else {
+        const int d = ((I - s) % (p - 1) + (p - 1)) % (p - 1);
+        i = (d <= p / 2 - 1) ? d : (p - 1) - d;
+    }
+    int a, b;
+    rr_pair(s, i, p, a, b);
+    pair = i;
+    half = (I == a) ? 0 : 1;
+}
+
+// Rotation annihilating c_ab of the 2x2 Hermitian block [[aa, c_ab], [c_ab^*, bb]]:
+// with d = bb - aa, r = sqrt(d^2 + 4|c_ab|^2), u = r + |d|, k = 1/sqrt(2 r u),
+//   c = u k,  s e^{i phi} = 2 sign(d) c_ab k,
+// which equals the t = tan(theta) form above (c^2 + |s|^2 = (u^2 + 4|c_ab|^2) k^2
+// = 1).  se = s e^{+i phi}, sc = s e^{-i phi}.  Contraction is off, so every
+// inlined copy rounds identically and a rotation formed by different
+// threads is the same to the bit.
+template <bool CPLX>
+__device__ __forceinline__ void jrot(typename jelem<CPLX>::type cab, double aa, double bb, bool valid, double &c,
+                                     typename jelem<CPLX>::type &se, typename jelem<CPLX>::type &sc)
+{
+#pragma clang fp contract(off)
+    using E = typename jelem<CPLX>::type;
+    const double h2 = jabs2(cab);
+    const double d = bb - aa;
+    const double r = sqrt(d * d + 4.0 * h2);
+    const double u = r + fabs(d);
+    const double ru2 = 2.0 * r * u;
+    // branch-free, so that the two rotations a thread forms interleave
+    const bool ok = valid && h2 > 0.0 && ru2 > 1e-300;
+    const double k = rsqrt(ok ? ru2 : 1.0);
+    c = ok ? u * k : 1.0;
+    const double f = ok ? copysign(2.0 * k, d) : 0.0;
+    if constexpr (CPLX) {
+        se = make_double2(f * cab.x, f * cab.y);
+        sc = make_double2(f * cab.x, -f * cab.y);
+    } else {
+        se = f * cab;
+        sc = f * cab;
+    }
 }
 
 template <bool CPLX>
-__global__ __launch_bounds__(BJ_NT) void bjacobi_kernel(int n, typename jelem<CPLX>::type *C, long ldc,
+__global__ __launch_bounds__(BJ_NT) void bjacobi_kernel(int n, typename jelem<CPLX>::type *C0,
+                                                        typename jelem<CPLX>::type *C1, long ldc,
                                                         typename jelem<CPLX>::type *V, long ldv,
-                                                        typename jelem<CPLX>::type *Rbuf, double *partial,
-                                                        unsigned *bar, int max_sweeps, double tol,
-                                                        int inner_sweeps, int *status, double *hist)
+                                                        typename jelem<CPLX>::type *Rbuf,
+                                                        typename jelem<CPLX>::type *Dbuf, double *partial,
+                                                        unsigned *bar, int max_sweeps, double tol, int *status,
+                                                        double *hist, double *dout)
 {
     using E = typename jelem<CPLX>::type;
+    static_assert(BJ_NT == BJ_BS * BJ_BS, "one thread per 2x2 block of rotation pairs");
     __shared__ E L0[BJ_W][BJ_W + 1];
+    __shared__ E L0b[BJ_W][BJ_W + 1];
     __shared__ E L1[BJ_W][BJ_W + 1];
-    __shared__ double s_c[BJ_BS], s_s[BJ_BS];
-    __shared__ double2 s_ph[BJ_BS];
-    __shared__ int s_ia[BJ_BS], s_ib[BJ_BS];
+    __shared__ E Ys[BJ_W][BJ_BS + 1];
     __shared__ int s_iP[BJ_W], s_iQ[BJ_W];
     __shared__ double s_red[BJ_NT / 64];
 
     grid_sync gs;
     gs.init(bar, bar + 1, gridDim.x);
-    const int G = gridDim.x, tid = threadIdx.x, bid = blockIdx.x;
+    const int G = gridDim.x, tid = threadIdx.x, bid = blockIdx.x, lane = tid & 63;
     const long gtid = (long)bid * BJ_NT + tid, gthreads = (long)G * BJ_NT;
     const int nb = (n + BJ_BS - 1) / BJ_BS;
     const int nbp = nb + (nb & 1), npairs = nbp / 2, rounds = nbp - 1;
     const int nrc = (n + BJ_W - 1) / BJ_W;   // row chunks of V
-    E *Rall = Rbuf;
+    const long RS = (long)npairs * BJ_W * BJ_W;
+    const int n_ctiles = npairs * (npairs + 1) / 2, nitems = n_ctiles + nrc * npairs;
+    E *Cb[2] = {C0, C1};
 
     auto block_reduce = [&](double v) {
         v = wave_sum(v);
@@ -124,7 +180,7 @@ __global__ __launch_bounds__(BJ_NT) void bjacobi_kernel(int n, typename jelem<CP
         __syncthreads();
         return t;
     };
-    // indices of the 2 * BS rows of block pair P in round s (-1 = padding)
+    // indices of the 2 BS rows of block pair P of pairing s (-1 = padding)
     auto pair_idx = [&](int s, int P, int *dst) {
         int I, J;
         rr_pair(s, P, nbp, I, J);
@@ -138,7 +194,7 @@ __global__ __launch_bounds__(BJ_NT) void bjacobi_kernel(int n, typename jelem<CP
     for (long e = gtid; e < (long)n * n; e += gthreads) {
         const int i = (int)(e % n), j = (int)(e / n);
         V[i + j * ldv] = jreal<E>(i == j ? 1.0 : 0.0);
-        acc += jabs2(C[i + j * ldc]);
+        acc += jabs2(C0[i + j * ldc]);
     }
     double bs = block_reduce(acc);
     if (tid == 0) partial[G + bid] = bs;
@@ -147,110 +203,185 @@ __global__ __launch_bounds__(BJ_NT) void bjacobi_kernel(int n, typename jelem<CP
     for (int q = 0; q < G; ++q) fro2 += partial[G + q];
     const double fro = sqrt(fro2);
 
-    int sweep = 0, conv = 0;
+    int sweep = 0, conv = 0, t = 0;
     double off_prev = 1e300;
-    for (sweep = 0; sweep < max_sweeps && !conv; ++sweep) {
-        double offacc = 0.0;
-        for (int s = 0; s < rounds; ++s) {
-            const bool last = (s == rounds - 1);
-            // ---------------- phase 1: inner Jacobi on each block pair
-            for (int P = bid; P < npairs; P += G) {
-                pair_idx(s, P, s_iP);
-                __syncthreads();
+    for (;; ++t) {
+        const int s = t % rounds;
+        E *Rcur = Rbuf + (long)(t & 1) * RS;
+        const E *Rprev = Rbuf + (long)((t + 1) & 1) * RS;
+        const E *Cprev = Cb[(t + 1) & 1];
+        // ---------------- phase 1 of round t: inner Jacobi on each block pair
+        for (int P = bid; P < npairs; P += G) {
+            int I, J;
+            rr_pair(s, P, nbp, I, J);
+            pair_idx(s, P, s_iP);
+            __syncthreads();
+            if (t == 0) {
                 for (int e = tid; e < BJ_W * BJ_W; e += BJ_NT) {
                     const int a = e % BJ_W, b = e / BJ_W;
                     const int ia = s_iP[a], ib = s_iP[b];
-                    L0[a][b] = (ia >= 0 && ib >= 0) ? C[ia + (long)ib * ldc] : jzero<E>();
-                    L1[a][b] = jreal<E>(a == b ? 1.0 : 0.0);
+                    L0[a][b] = (ia >= 0 && ib >= 0) ? C0[ia + (long)ib * ldc] : jzero<E>();
                 }
+            } else {
+                // off-diagonal block C_t[I, J] from round t-1
+                const int sp = (t - 1) % rounds;
+                int P1, h1, P2, h2;
+                rr_locate(sp, I, nbp, P1, h1);
+                rr_locate(sp, J, nbp, P2, h2);
+                pair_idx(sp, P1, s_iQ);        // rows: pair P1 of round t-1
+                pair_idx(sp, P2, s_iP);        // columns: pair P2 (s_iP rebuilt below)
                 __syncthreads();
-                for (int isw = 0; isw < inner_sweeps; ++isw)
-                    for (int r = 0; r < BJ_W - 1; ++r) {
-                        if (tid < BJ_BS) {
-                            int a, b;
-                            rr_pair(r, tid, BJ_W, a, b);
-                            double c = 1.0, sn = 0.0;
-                            double2 ph = make_double2(1.0, 0.0);
-                            if (s_iP[a] >= 0 && s_iP[b] >= 0) {
-                                const E sab = L0[a][b];
-                                const double babs = sqrt(jabs2(sab));
-                                if (babs > 1e-300) {
-                                    const double tau = (jre(L0[b][b]) - jre(L0[a][a])) / (2.0 * babs);
-                                    const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                                    c = 1.0 / sqrt(1.0 + t * t);
-                                    sn = t * c;
-                                    if constexpr (CPLX) ph = make_double2(sab.x / babs, sab.y / babs);
-                                    else ph = make_double2(sab / babs, 0.0);
-                                }
-                            }
-                            s_c[tid] = c;
-                            s_s[tid] = sn;
-                            s_ph[tid] = ph;
-                            s_ia[tid] = a;
-                            s_ib[tid] = b;
-                        }
-                        __syncthreads();
-                        for (int e = tid; e < BJ_BS * BJ_BS; e += BJ_NT) {
-                            const int p = e % BJ_BS, q = e / BJ_BS;
-                            const int ra = s_ia[p], rb = s_ib[p], ca = s_ia[q], cb = s_ib[q];
-                            const E x00 = L0[ra][ca], x01 = L0[ra][cb], x10 = L0[rb][ca], x11 = L0[rb][cb];
-                            const double cq = s_c[q], cp = s_c[p];
-                            const E sqe = jphase<E>(s_s[q], s_ph[q], 1.0), sqc = jphase<E>(s_s[q], s_ph[q], -1.0);
-                            const E spe = jphase<E>(s_s[p], s_ph[p], 1.0), spc = jphase<E>(s_s[p], s_ph[p], -1.0);
-                            // M = X J_q,  J = [[c, s e^{i phi}], [-s e^{-i phi}, c]]
-                            const E m00 = jadd(jmul(jreal<E>(cq), x00), jmul(jreal<E>(-1.0), jmul(sqc, x01)));
-                            const E m01 = jadd(jmul(sqe, x00), jmul(jreal<E>(cq), x01));
-                            const E m10 = jadd(jmul(jreal<E>(cq), x10), jmul(jreal<E>(-1.0), jmul(sqc, x11)));
-                            const E m11 = jadd(jmul(sqe, x10), jmul(jreal<E>(cq), x11));
-                            // C' = J_p^H M
-                            E y00 = jadd(jmul(jreal<E>(cp), m00), jmul(jreal<E>(-1.0), jmul(spe, m10)));
-                            E y01 = jadd(jmul(jreal<E>(cp), m01), jmul(jreal<E>(-1.0), jmul(spe, m11)));
-                            E y10 = jadd(jmul(spc, m00), jmul(jreal<E>(cp), m10));
-                            E y11 = jadd(jmul(spc, m01), jmul(jreal<E>(cp), m11));
-                            if (p == q) {
-                                y01 = jzero<E>();
-                                y10 = jzero<E>();
-                                y00 = jreal<E>(jre(y00));
-                                y11 = jreal<E>(jre(y11));
-                            }
-                            L0[ra][ca] = y00;
-                            L0[ra][cb] = y01;
-                            L0[rb][ca] = y10;
-                            L0[rb][cb] = y11;
-                        }
-                        for (int e = tid; e < BJ_W * BJ_BS; e += BJ_NT) {
-                            const int x = e % BJ_W, q = e / BJ_W;
-                            const int ca = s_ia[q], cb = s_ib[q];
-                            const E va = L1[x][ca], vb = L1[x][cb];
-                            const double cq = s_c[q];
-                            const E sqe = jphase<E>(s_s[q], s_ph[q], 1.0), sqc = jphase<E>(s_s[q], s_ph[q], -1.0);
-                            L1[x][ca] = jadd(jmul(jreal<E>(cq), va), jmul(jreal<E>(-1.0), jmul(sqc, vb)));
-                            L1[x][cb] = jadd(jmul(sqe, va), jmul(jreal<E>(cq), vb));
-                        }
-                        __syncthreads();
-                    }
-                E *R = Rall + (long)P * BJ_W * BJ_W;
+                const E *R2 = Rprev + (long)P2 * BJ_W * BJ_W;
                 for (int e = tid; e < BJ_W * BJ_W; e += BJ_NT) {
                     const int a = e % BJ_W, b = e / BJ_W;
-                    R[a + b * BJ_W] = L1[a][b];
+                    const int ia = s_iQ[a], ib = s_iP[b];
+                    L0[a][b] = (ia >= 0 && ib >= 0) ? Cprev[ia + (long)ib * ldc] : jzero<E>();
+                    L1[a][b] = R2[a + b * BJ_W];
                 }
                 __syncthreads();
-            }
-            gs.sync();
-            // ---------------- phase 2: C_PQ <- R_P^H C_PQ R_Q,  V_Q <- V_Q R_Q
-            const int nc_items = npairs * npairs, nitems = nc_items + nrc * npairs;
-            for (int it = bid; it < nitems; it += G) {
-                const bool is_c = it < nc_items;
-                const int Q = is_c ? it / npairs : (it - nc_items) / nrc;
-                const int P = is_c ? it % npairs : 0;
-                const int rc = is_c ? 0 : (it - nc_items) % nrc;
-                pair_idx(s, Q, s_iQ);
-                if (is_c) pair_idx(s, P, s_iP);
-                else
-                    for (int t = tid; t < BJ_W; t += BJ_NT) s_iP[t] = (rc * BJ_W + t < n) ? rc * BJ_W + t : -1;
+                // Y = C_{t-1}[P1, P2] R_{t-1,P2}[:, J part]   (W x BS)
+                for (int e = tid; e < BJ_W * BJ_BS; e += BJ_NT) {
+                    const int a = e % BJ_W, j = e / BJ_W;
+                    E sum = jzero<E>();
+#pragma unroll 8
+                    for (int k = 0; k < BJ_W; ++k) sum = jadd(sum, jmul(L0[a][k], L1[k][h2 * BJ_BS + j]));
+                    Ys[a][j] = sum;
+                }
                 __syncthreads();
-                const E *RQ = Rall + (long)Q * BJ_W * BJ_W;
-                const E *src = is_c ? C : V;
+                const E *R1 = Rprev + (long)P1 * BJ_W * BJ_W;
+                for (int e = tid; e < BJ_W * BJ_W; e += BJ_NT) {
+                    const int a = e % BJ_W, b = e / BJ_W;
+                    L1[a][b] = R1[a + b * BJ_W];
+                }
+                __syncthreads();
+                // X = R_{t-1,P1}[:, I part]^H Y   (BS x BS, one entry per thread)
+                E xv = jzero<E>();
+                const int xi = tid % BJ_BS, xj = tid / BJ_BS;
+#pragma unroll 8
+                for (int k = 0; k < BJ_W; ++k) xv = jadd(xv, jmul(jconj(L1[k][h1 * BJ_BS + xi]), Ys[k][xj]));
+                pair_idx(s, P, s_iP);
+                __syncthreads();
+                // diagonal blocks from round t-1's rotated pairs
+                const E *DI = Dbuf + (long)I * BJ_BS * BJ_BS, *DJ = Dbuf + (long)J * BJ_BS * BJ_BS;
+                for (int e = tid; e < BJ_BS * BJ_BS; e += BJ_NT) {
+                    const int a = e % BJ_BS, b = e / BJ_BS;
+                    L0[a][b] = DI[a + b * BJ_BS];
+                    L0[BJ_BS + a][BJ_BS + b] = DJ[a + b * BJ_BS];
+                }
+                L0[xi][BJ_BS + xj] = xv;
+                L0[BJ_BS + xj][xi] = jconj(xv);
+            }
+            for (int e = tid; e < BJ_W * BJ_W; e += BJ_NT) {
+                const int a = e % BJ_W, b = e / BJ_W;
+                L1[a][b] = jreal<E>(a == b ? 1.0 : 0.0);
+            }
+            __syncthreads();
+            // one inner sweep: thread (p, q) = (tid mod BS, tid / BS) owns the
+            // 2x2 block of rotation pairs p and q and rows p, p + BS of the
+            // accumulated rotation's column pair q.  Every thread forms the
+            // two rotations it needs itself from the current matrix; the
+            // matrix alternates between two LDS copies, so an inner round
+            // takes one barrier.
+            {
+                const int p = tid % BJ_BS, q = tid / BJ_BS;
+                unsigned vmask = 0;
+                for (int u = 0; u < BJ_W; ++u) vmask |= (s_iP[u] >= 0 ? 1u : 0u) << u;
+                E(*A)[BJ_W + 1] = L0;
+                E(*B)[BJ_W + 1] = L0b;
+                for (int r = 0; r < BJ_W - 1; ++r) {
+                    int ra, rb, ca, cb;
+                    rr_pair(r, p, BJ_W, ra, rb);
+                    rr_pair(r, q, BJ_W, ca, cb);
+                    // accumulated-rotation entries first: their loads overlap the rotation math
+                    E va[2], vb[2];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        va[h] = L1[p + h * BJ_BS][ca];
+                        vb[h] = L1[p + h * BJ_BS][cb];
+                    }
+                    double cp, cq;
+                    E spe, spc, sqe, sqc;
+                    jrot<CPLX>(A[ra][rb], jre(A[ra][ra]), jre(A[rb][rb]), ((vmask >> ra) & (vmask >> rb) & 1u) != 0,
+                               cp, spe, spc);
+                    jrot<CPLX>(A[ca][cb], jre(A[ca][ca]), jre(A[cb][cb]), ((vmask >> ca) & (vmask >> cb) & 1u) != 0,
+                               cq, sqe, sqc);
+                    const E x00 = A[ra][ca], x01 = A[ra][cb], x10 = A[rb][ca], x11 = A[rb][cb];
+                    // M = X J_q,  J = [[c, s e^{i phi}], [-s e^{-i phi}, c]]
+                    const E m00 = jsub(jscale(x00, cq), jmul(sqc, x01));
+                    const E m01 = jadd(jmul(sqe, x00), jscale(x01, cq));
+                    const E m10 = jsub(jscale(x10, cq), jmul(sqc, x11));
+                    const E m11 = jadd(jmul(sqe, x10), jscale(x11, cq));
+                    // C' = J_p^H M
+                    E y00 = jsub(jscale(m00, cp), jmul(spe, m10));
+                    E y01 = jsub(jscale(m01, cp), jmul(spe, m11));
+                    E y10 = jadd(jmul(spc, m00), jscale(m10, cp));
+                    E y11 = jadd(jmul(spc, m01), jscale(m11, cp));
+                    if (p == q) {
+                        y01 = jzero<E>();
+                        y10 = jzero<E>();
+                        y00 = jreal<E>(jre(y00));
+                        y11 = jreal<E>(jre(y11));
+                    }
+                    B[ra][ca] = y00;
+                    B[ra][cb] = y01;
+                    B[rb][ca] = y10;
+                    B[rb][cb] = y11;
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int x = p + h * BJ_BS;
+                        L1[x][ca] = jsub(jscale(va[h], cq), jmul(sqc, vb[h]));
+                        L1[x][cb] = jadd(jmul(sqe, va[h]), jscale(vb[h], cq));
+                    }
+                    __syncthreads();
+                    E(*T)[BJ_W + 1] = A;
+                    A = B;
+                    B = T;
+                }
+                // the rotated pair matrix is in A
+                if (A != L0)
+                    for (int e = tid; e < BJ_W * BJ_W; e += BJ_NT) L0[e % BJ_W][e / BJ_W] = A[e % BJ_W][e / BJ_W];
+            }
+            __syncthreads();
+            E *R = Rcur + (long)P * BJ_W * BJ_W;
+            for (int e = tid; e < BJ_W * BJ_W; e += BJ_NT) {
+                const int a = e % BJ_W, b = e / BJ_W;
+                R[a + b * BJ_W] = L1[a][b];
+            }
+            E *DI = Dbuf + (long)I * BJ_BS * BJ_BS, *DJ = Dbuf + (long)J * BJ_BS * BJ_BS;
+            for (int e = tid; e < BJ_BS * BJ_BS; e += BJ_NT) {
+                const int a = e % BJ_BS, b = e / BJ_BS;
+                DI[a + b * BJ_BS] = L0[a][b];
+                DJ[a + b * BJ_BS] = L0[BJ_BS + a][BJ_BS + b];
+            }
+            __syncthreads();
+        }
+        // ---------------- phase 2 of round t-1: C_t = R^H C_{t-1} R, V_t = V_{t-1} R
+        const bool have2 = t > 0;
+        const int sp = have2 ? (t - 1) % rounds : 0;
+        const bool lastp = have2 && sp == rounds - 1;
+        double offacc = 0.0;
+        if (have2) {
+            E *Cnext = Cb[t & 1];
+            const int start = (bid + G - (npairs % G)) % G;
+            for (int it = start; it < nitems; it += G) {
+                const bool is_c = it < n_ctiles;
+                int P = 0, Q = 0, rc = 0;
+                if (is_c) {
+                    Q = (int)((sqrt(8.0 * it + 1.0) - 1.0) * 0.5);
+                    while ((Q + 1) * (Q + 2) / 2 <= it) ++Q;
+                    while (Q * (Q + 1) / 2 > it) --Q;
+                    P = it - Q * (Q + 1) / 2;
+                } else {
+                    Q = (it - n_ctiles) / nrc;
+                    rc = (it - n_ctiles) % nrc;
+                }
+                pair_idx(sp, Q, s_iQ);
+                if (is_c) pair_idx(sp, P, s_iP);
+                else
+                    for (int u = tid; u < BJ_W; u += BJ_NT) s_iP[u] = (rc * BJ_W + u < n) ? rc * BJ_W + u : -1;
+                __syncthreads();
+                const E *RQ = Rprev + (long)Q * BJ_W * BJ_W;
+                const E *src = is_c ? Cprev : V;
                 const long lds = is_c ? ldc : ldv;
                 for (int e = tid; e < BJ_W * BJ_W; e += BJ_NT) {
                     const int a = e % BJ_W, b = e / BJ_W;
@@ -259,19 +390,20 @@ __global__ __launch_bounds__(BJ_NT) void bjacobi_kernel(int n, typename jelem<CP
                     L1[a][b] = RQ[a + b * BJ_W];
                 }
                 __syncthreads();
-                // T = X R_Q, 16 entries per thread
+                // T = X R_Q, 4 entries per thread
                 E tv[BJ_W * BJ_W / BJ_NT];
 #pragma unroll
                 for (int u = 0; u < BJ_W * BJ_W / BJ_NT; ++u) {
                     const int e = tid + u * BJ_NT;
                     const int a = e % BJ_W, b = e / BJ_W;
                     E sum = jzero<E>();
+#pragma unroll 8
                     for (int k = 0; k < BJ_W; ++k) sum = jadd(sum, jmul(L0[a][k], L1[k][b]));
                     tv[u] = sum;
                 }
                 __syncthreads();
                 if (is_c) {
-                    const E *RP = Rall + (long)P * BJ_W * BJ_W;
+                    const E *RP = Rprev + (long)P * BJ_W * BJ_W;
 #pragma unroll
                     for (int u = 0; u < BJ_W * BJ_W / BJ_NT; ++u) {
                         const int e = tid + u * BJ_NT;
@@ -287,12 +419,14 @@ __global__ __launch_bounds__(BJ_NT) void bjacobi_kernel(int n, typename jelem<CP
                         const int e = tid + u * BJ_NT;
                         const int a = e % BJ_W, b = e / BJ_W;
                         E sum = jzero<E>();
+#pragma unroll 8
                         for (int k = 0; k < BJ_W; ++k) sum = jadd(sum, jmul(jconj(L1[k][a]), L0[k][b]));
                         const int ia = s_iP[a], ib = s_iQ[b];
                         if (ia >= 0 && ib >= 0) {
                             if (ia == ib) sum = jreal<E>(jre(sum));
-                            C[ia + (long)ib * ldc] = sum;
-                            if (last && ia != ib) offacc += jabs2(sum);
+                            Cnext[ia + (long)ib * ldc] = sum;
+                            if (P != Q) Cnext[ib + (long)ia * ldc] = jconj(sum);
+                            if (lastp && ia != ib) offacc += (P != Q ? 2.0 : 1.0) * jabs2(sum);
                         }
                     }
                 } else {
@@ -306,43 +440,50 @@ __global__ __launch_bounds__(BJ_NT) void bjacobi_kernel(int n, typename jelem<CP
                 }
                 __syncthreads();
             }
-            if (last) {
-                const double b2 = block_reduce(offacc);
-                if (tid == 0) partial[bid] = b2;
-            }
-            gs.sync();
         }
-        double off2 = 0.0;
-        for (int q = 0; q < G; ++q) off2 += partial[q];
-        const double off = sqrt(off2);
-        if (gtid == 0 && sweep < 64) hist[sweep] = fro > 0.0 ? off / fro : 0.0;
-        // Stop once the off-diagonal norm is below tol * ||C||_F (a Ritz vector
-        // error of size off mixes only pairs whose eigenvalues differ by about
-        // off / error, so its residual contribution is ~off), or once rounding
-        // noise stops the decrease.
-        if (off <= tol * fro || fro == 0.0) conv = 1;
-        else if (off <= 1e-11 * fro && off >= 0.5 * off_prev) conv = 1;
-        off_prev = off;
+        if (lastp) {
+            const double b2 = block_reduce(offacc);
+            if (tid == 0) partial[bid] = b2;
+        }
+        gs.sync();
+        if (lastp) {
+            // C_t is the matrix after a whole sweep
+            double off2 = 0.0;
+            for (int q = 0; q < G; ++q) off2 += partial[q];
+            const double off = sqrt(off2);
+            if (gtid == 0 && sweep < 64) hist[sweep] = fro > 0.0 ? off / fro : 0.0;
+            ++sweep;
+            // Stop once the off-diagonal norm is below tol * ||C||_F (a Ritz
+            // vector error of size off mixes only pairs whose eigenvalues differ
+            // by about off / error, so its residual contribution is ~off), or
+            // once rounding noise stops the decrease.
+            if (off <= tol * fro || fro == 0.0) conv = 1;
+            else if (off <= 1e-11 * fro && off >= 0.5 * off_prev) conv = 1;
+            off_prev = off;
+            if (conv || sweep >= max_sweeps) break;
+        }
     }
+    const E *Cfin = Cb[t & 1];
+    for (long i = gtid; i < n; i += gthreads) dout[i] = jre(Cfin[i + i * ldc]);
     if (gtid == 0) {
         status[0] = conv ? 0 : -1;
         status[1] = sweep;
     }
 }
 
-// Eigenvalues from the diagonal of the converged matrix, sorted ascending
+// Eigenvalues (the diagonal d of the converged matrix) sorted ascending
 // (stable by index); eigenvector columns follow.  One block.
 template <bool CPLX>
-__global__ __launch_bounds__(1024) void jacobi_sort_kernel(int m, const typename jelem<CPLX>::type *C,
-                                                           long ldc, const typename jelem<CPLX>::type *V,
-                                                           long ldv, double *w, typename jelem<CPLX>::type *Vout,
+__global__ __launch_bounds__(1024) void jacobi_sort_kernel(int m, const double *__restrict__ d,
+                                                           const typename jelem<CPLX>::type *V, long ldv,
+                                                           double *w, typename jelem<CPLX>::type *Vout,
                                                            long ldo, int *rank)
 {
     for (int i = threadIdx.x; i < m; i += blockDim.x) {
-        const double di = jload<CPLX>(C, i + (long)i * ldc).x;
+        const double di = d[i];
         int r = 0;
         for (int j = 0; j < m; ++j) {
-            const double dj = jload<CPLX>(C, j + (long)j * ldc).x;
+            const double dj = d[j];
             r += (dj < di) || (dj == di && j < i);
         }
         rank[i] = r;
