@@ -83,11 +83,15 @@ __global__ __launch_bounds__(CHOL_MAXM) void chol_drop_kernel(int m, const typen
         s_rank = 0;
     }
     __syncthreads();
+    // rows of L are fetched this many columns at a time, all loads issued
+    // before the multiply-adds, so the left-looking sum is not bound by one
+    // memory round trip per column
+    constexpr int CH = CPLX ? 8 : 32;
     for (int k0 = 0; k0 < m; k0 += CHOL_CB) {
         const int cb = min(CHOL_CB, m - k0);
-        for (int e = i; e < cb * k0; e += CHOL_MAXM) {
-            const int c = e % cb, j = e / cb;
-            Lrow[c][j] = L[(k0 + c) + (long)j * ldl];
+        for (int e = i; e < CHOL_CB * k0; e += CHOL_MAXM) {
+            const int c = e % CHOL_CB, j = e / CHOL_CB;
+            Lrow[c][j] = (c < cb) ? L[(k0 + c) + (long)j * ldl] : jzero<E>();   // zero rows past the end
         }
         __syncthreads();
         E w[CHOL_CB];
@@ -95,13 +99,23 @@ __global__ __launch_bounds__(CHOL_MAXM) void chol_drop_kernel(int m, const typen
 #pragma unroll
         for (int c = 0; c < CHOL_CB; ++c)
             w[c] = (mine && c < cb) ? Bt[i + (long)(k0 + c) * ldb] : jzero<E>();
-        if (mine)
-            for (int j = 0; j < k0; ++j) {
+        if (mine) {
+            int j = 0;
+            for (; j + CH <= k0; j += CH) {
+                E lv[CH];
+#pragma unroll
+                for (int u = 0; u < CH; ++u) lv[u] = L[i + (long)(j + u) * ldl];
+#pragma unroll
+                for (int u = 0; u < CH; ++u)
+#pragma unroll
+                    for (int c = 0; c < CHOL_CB; ++c) w[c] = jsub(w[c], jmul(lv[u], jconj(Lrow[c][j + u])));
+            }
+            for (; j < k0; ++j) {
                 const E lij = L[i + (long)j * ldl];
 #pragma unroll
-                for (int c = 0; c < CHOL_CB; ++c)
-                    if (c < cb) w[c] = jadd(w[c], jmul(jreal<E>(-1.0), jmul(lij, jconj(Lrow[c][j]))));
+                for (int c = 0; c < CHOL_CB; ++c) w[c] = jsub(w[c], jmul(lij, jconj(Lrow[c][j])));
             }
+        }
 #pragma unroll
         for (int c = 0; c < CHOL_CB; ++c) {
             if (c < cb) {
@@ -133,8 +147,9 @@ __global__ __launch_bounds__(CHOL_MAXM) void chol_drop_kernel(int m, const typen
             }
         }
         // column block k0..k0+cb of L: rows above the diagonal are zero
-        for (int c = 0; c < cb; ++c) {
-            if (i < m) L[i + (long)(k0 + c) * ldl] = (i >= k0 + c) ? w[c] : jzero<E>();
+#pragma unroll
+        for (int c = 0; c < CHOL_CB; ++c) {
+            if (c < cb && i < m) L[i + (long)(k0 + c) * ldl] = (i >= k0 + c) ? w[c] : jzero<E>();
         }
         __syncthreads();
     }

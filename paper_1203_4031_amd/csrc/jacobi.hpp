@@ -471,6 +471,8 @@ __global__ __launch_bounds__(BJ_NT) void bjacobi_kernel(int n, typename jelem<CP
     }
 }
 
+constexpr int JSORT_MAXM = 4096;   // largest reduced problem (M0 limit)
+
 // Eigenvalues (the diagonal d of the converged matrix) sorted ascending
 // (stable by index); eigenvector columns follow.  One block.
 template <bool CPLX>
@@ -479,11 +481,14 @@ __global__ __launch_bounds__(1024) void jacobi_sort_kernel(int m, const double *
                                                            double *w, typename jelem<CPLX>::type *Vout,
                                                            long ldo, int *rank)
 {
+    __shared__ double sd[JSORT_MAXM];
+    for (int i = threadIdx.x; i < m; i += blockDim.x) sd[i] = d[i];
+    __syncthreads();
     for (int i = threadIdx.x; i < m; i += blockDim.x) {
-        const double di = d[i];
+        const double di = sd[i];
         int r = 0;
         for (int j = 0; j < m; ++j) {
-            const double dj = d[j];
+            const double dj = sd[j];
             r += (dj < di) || (dj == di && j < i);
         }
         rank[i] = r;
