@@ -533,7 +533,7 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
     V *F = static_cast<V *>(ws.get(mixed ? "F32" : "F64", sizeof(V) * (size_t)ne * sF));
     int *ipiv = static_cast<int *>(ws.get("ipiv", sizeof(int) * (size_t)ne * n));
     int *perm = static_cast<int *>(ws.get("perm", sizeof(int) * (size_t)ne * n));
-    int *swapmap = static_cast<int *>(ws.get("swapmap", sizeof(int) * (size_t)ne * (1 + 4 * LU_NB)));
+    int *swapmap = static_cast<int *>(ws.get("swapmap", sizeof(int) * 2 * (size_t)ne * (1 + 4 * LU_NB)));
     int *dinfo = static_cast<int *>(ws.get("info", sizeof(int) * ne));
     const long sInv = tri_inv_stride(n);
     V *Linv = static_cast<V *>(ws.get(mixed ? "Linv32" : "Linv64", sizeof(V) * (size_t)ne * sInv));

@@ -90,6 +90,64 @@ __device__ inline int compose_moves_wave(const int *piv, int r0, int cnt, int *d
     return __popcll(mm);
 }
 
+// Bit moves for the DPP lane permutations (32-bit lanes).
+__device__ inline int as_bits(float v) { return __float_as_int(v); }
+__device__ inline float from_bits(int b, float) { return __int_as_float(b); }
+template <int CTRL> __device__ inline float dpp_mov(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL> __device__ inline double dpp_mov(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+template <int CTRL> __device__ inline int dpp_mov(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+__device__ inline float lane_read(float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); }
+__device__ inline double lane_read(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+// (v, i) <- the better of (v, i) and (ov, oi): larger v, ties to the lower i
+template <typename T> __device__ inline void amax_take(T &v, int &i, T ov, int oi)
+{
+    const bool take = (ov > v) | ((ov == v) & (oi < i));   // branch-free
+    v = take ? ov : v;
+    i = take ? oi : i;
+}
+// Argmax over the 64 lanes of a wave with DPP row permutations (quad xor 1
+// and 2, half-row and row mirror) and one read of each 16-lane row; the
+// result is uniform over the wave.  All lanes must be active.
+template <typename T> __device__ inline void wave_argmax(T &v, int &i)
+{
+    amax_take(v, i, dpp_mov<0xB1>(v), dpp_mov<0xB1>(i));    // quad_perm [1,0,3,2]
+    amax_take(v, i, dpp_mov<0x4E>(v), dpp_mov<0x4E>(i));    // quad_perm [2,3,0,1]
+    amax_take(v, i, dpp_mov<0x141>(v), dpp_mov<0x141>(i));  // row_half_mirror
+    amax_take(v, i, dpp_mov<0x140>(v), dpp_mov<0x140>(i));  // row_mirror
+    T bv = lane_read(v, 0);
+    int bi = __builtin_amdgcn_readlane(i, 0);
+#pragma unroll
+    for (int r = 1; r < 4; ++r) amax_take(bv, bi, lane_read(v, 16 * r), __builtin_amdgcn_readlane(i, 16 * r));
+    v = bv;
+    i = bi;
+}
+// 1 / p for a pivot: hardware reciprocal in FP32 (the factors are an
+// FP32 preconditioner), correctly rounded division in FP64.
+__device__ inline float2 pivot_inv(float2 p)
+{
+    const float rn = __builtin_amdgcn_rcpf(p.x * p.x + p.y * p.y);
+    return make_float2(p.x * rn, -p.y * rn);
+}
+__device__ inline double2 pivot_inv(double2 p) { return cinv(p); }
+
 // Panel factorisation.  One workgroup of NT threads per matrix.  The panel
 // is processed in sub-blocks of IB columns: each sub-block is first brought
 // up to date from the panel's earlier sub-blocks (left-looking), then held
@@ -122,9 +180,10 @@ __global__ __launch_bounds__(NT) void lu_panel_kernel(int n, cplx<T> *__restrict
 
     __shared__ V Lsh[NB][NB + 1];      // L11 of the panel so far (unit lower)
     __shared__ V Ush[NB][IB];          // U rows k..c0-1 of the current sub-block
-    __shared__ V prow[2][IB], grow[2][IB];
-    __shared__ T redv[2][NW];
-    __shared__ int redi[2][NW];
+    __shared__ V cand_row[2][NW][IB];  // each wave's best row (pivot candidate)
+    __shared__ V grow[2][IB];          // row g before the exchange
+    __shared__ T cand_v[2][NW];
+    __shared__ int cand_i[2][NW];
     __shared__ int s_ipiv[NB];
     __shared__ int s_mvd[2 * NB], s_mvs[2 * NB];
     __shared__ V s_stage[2 * IB][NB];
@@ -150,8 +209,8 @@ __global__ __launch_bounds__(NT) void lu_panel_kernel(int n, cplx<T> *__restrict
                 V x = (c < w && lane < jb) ? a[(k + lane) + (long)(c0 + c) * ldf] : cmake<V>(0, 0);
                 for (int l = 0; l + 1 < jb; ++l) {
                     V xl;
-                    xl.x = __shfl(x.x, l, 64);
-                    xl.y = __shfl(x.y, l, 64);
+                    xl.x = lane_read(x.x, l);
+                    xl.y = lane_read(x.y, l);
                     if (lane > l && lane < jb) x = csub(x, cmul(Lsh[lane][l], xl));
                 }
                 if (lane < jb) {
@@ -194,11 +253,13 @@ __global__ __launch_bounds__(NT) void lu_panel_kernel(int n, cplx<T> *__restrict
             }
         }
 
-        // (c) factor the sub-block column by column.  The reduction and row
-        //     buffers alternate between two copies, so one column needs two
-        //     barriers: a thread that writes copy b for column jj + 1 has
-        //     passed the second barrier of column jj, by which time every
-        //     read of copy b (column jj - 1) is done.
+        // (c) factor the sub-block column by column, one barrier per column:
+        //     every wave publishes its best pivot candidate together with
+        //     that row's IB values, and the owner of row g publishes row g;
+        //     after the barrier every thread picks the winner the same way.
+        //     The buffers alternate between two copies: a thread writing
+        //     copy b for column jj + 1 has passed the barrier of column jj,
+        //     by which time every read of copy b (column jj - 1) is done.
 #pragma unroll
         for (int jj = 0; jj < IB; ++jj) {
             if (jj < w) {
@@ -217,48 +278,20 @@ __global__ __launch_bounds__(NT) void lu_panel_kernel(int n, cplx<T> *__restrict
                         }
                     }
                 }
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) {
-                    const T ov = __shfl_xor(best, off, 64);
-                    const int oi = __shfl_xor(bi, off, 64);
-                    if (ov > best || (ov == best && oi < bi)) {
-                        best = ov;
-                        bi = oi;
-                    }
-                }
+                wave_argmax(best, bi);
                 if (lane == 0) {
-                    redv[b][wid] = best;
-                    redi[b][wid] = bi;
+                    cand_v[b][wid] = best;
+                    cand_i[b][wid] = bi;
                 }
-                __syncthreads();
-                // every thread reduces the NW wave results the same way
-                T bv = redv[b][0];
-                int p = redi[b][0];
-#pragma unroll
-                for (int q = 1; q < NW; ++q) {
-                    const T ov = redv[b][q];
-                    const int oi = redi[b][q];
-                    if (ov > bv || (ov == bv && oi < p)) {
-                        bv = ov;
-                        p = oi;
-                    }
-                }
-                if (!(bv > T(0)) || p >= n) {
-                    // zero or non-finite column: keep the diagonal, flag the error
-                    p = g;
-                    if (tid == 0 && info_all[blockIdx.x] == 0) info_all[blockIdx.x] = g + 1;
-                }
-                if (tid == 0) s_ipiv[jb + jj] = p;
-                // exchange rows g and p of the sub-block through LDS
-                const int own_p = (p - c0) % NT, rp = (p - c0) / NT;
-                const int own_g = (g - c0) % NT, rg = (g - c0) / NT;
-                if (tid == own_p) {
+                if (bi < n && tid == (bi - c0) % NT) {
+                    const int rr = (bi - c0) / NT;
 #pragma unroll
                     for (int r = 0; r < R; ++r)
-                        if (r == rp)
+                        if (r == rr)
 #pragma unroll
-                            for (int c = 0; c < IB; ++c) prow[b][c] = val[r][c];
+                            for (int c = 0; c < IB; ++c) cand_row[b][wid][c] = val[r][c];
                 }
+                const int own_g = (g - c0) % NT, rg = (g - c0) / NT;
                 if (tid == own_g) {
 #pragma unroll
                     for (int r = 0; r < R; ++r)
@@ -267,6 +300,37 @@ __global__ __launch_bounds__(NT) void lu_panel_kernel(int n, cplx<T> *__restrict
                             for (int c = 0; c < IB; ++c) grow[b][c] = val[r][c];
                 }
                 __syncthreads();
+                // all candidates are loaded before any comparison
+                T cv[NW];
+                int ci[NW];
+#pragma unroll
+                for (int q = 0; q < NW; ++q) {
+                    cv[q] = cand_v[b][q];
+                    ci[q] = cand_i[b][q];
+                }
+                T bv = cv[0];
+                int p = ci[0], ww = 0;
+#pragma unroll
+                for (int q = 1; q < NW; ++q) {
+                    const bool take = (cv[q] > bv) | ((cv[q] == bv) & (ci[q] < p));
+                    bv = take ? cv[q] : bv;
+                    p = take ? ci[q] : p;
+                    ww = take ? q : ww;
+                }
+                V pr[IB];
+                if (!(bv > T(0)) || p >= n) {
+                    // zero or non-finite column: keep the diagonal, flag the error
+                    p = g;
+#pragma unroll
+                    for (int c = 0; c < IB; ++c) pr[c] = grow[b][c];
+                    if (tid == 0 && info_all[blockIdx.x] == 0) info_all[blockIdx.x] = g + 1;
+                } else {
+#pragma unroll
+                    for (int c = 0; c < IB; ++c) pr[c] = cand_row[b][ww][c];
+                }
+                if (tid == 0) s_ipiv[jb + jj] = p;
+                // exchange rows g and p
+                const int own_p = (p - c0) % NT, rp = (p - c0) / NT;
                 if (tid == own_p) {
 #pragma unroll
                     for (int r = 0; r < R; ++r)
@@ -279,13 +343,10 @@ __global__ __launch_bounds__(NT) void lu_panel_kernel(int n, cplx<T> *__restrict
                     for (int r = 0; r < R; ++r)
                         if (r == rg)
 #pragma unroll
-                            for (int c = 0; c < IB; ++c) val[r][c] = prow[b][c];
+                            for (int c = 0; c < IB; ++c) val[r][c] = pr[c];
                 }
                 // scale the column below the diagonal and update the sub-block
-                V pr[IB];
-#pragma unroll
-                for (int c = 0; c < IB; ++c) pr[c] = prow[b][c];
-                const V inv = (cabs1(pr[jj]) > T(0)) ? cinv(pr[jj]) : cmake<V>(0, 0);
+                const V inv = (cabs1(pr[jj]) > T(0)) ? pivot_inv(pr[jj]) : cmake<V>(0, 0);
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const int row = c0 + tid + NT * r;
@@ -353,14 +414,15 @@ __global__ __launch_bounds__(NT) void lu_panel_kernel(int n, cplx<T> *__restrict
     }
 }
 
-// Row interchanges of one panel applied to every column outside it, then
-// U12 = L11^{-1} A12 for the columns right of the panel.  Each block owns
-// 64 columns; moved values are staged through LDS so that all reads happen
-// before any write.
+// Row interchanges of one panel (columns k..k+nbw-1) applied to a set of
+// columns outside it -- the concatenation of [c0, c1) and [c2, c3) -- and
+// U12 = L11^{-1} A12 for those of them right of the panel.  Each block owns
+// 64 columns of that set; moved values are staged through LDS so that all
+// reads happen before any write.
 template <typename T, int NB>
 __global__ __launch_bounds__(256) void lu_swap_trsm_kernel(int n, cplx<T> *__restrict__ Fall, long ldf,
-                                                           long sF, int k, int nbw,
-                                                           const int *__restrict__ swapmap_all)
+                                                           long sF, int k, int nbw, int c0, int c1, int c2,
+                                                           int c3, const int *__restrict__ swapmap_all)
 {
     using V = cplx<T>;
     constexpr int CB = 64;
@@ -376,8 +438,12 @@ __global__ __launch_bounds__(256) void lu_swap_trsm_kernel(int n, cplx<T> *__res
         dst[e] = swapmap[1 + e];
         src[e] = swapmap[1 + 2 * NB + e];
     }
-    const int colbase = blockIdx.x * CB;     // index among the n - nbw outer columns
-    const bool right = colbase + CB > k;     // block holds columns right of the panel
+    const int w1 = c1 - c0, ncols = w1 + (c3 - c2);
+    auto col_of = [&](int oc) { return oc < w1 ? c0 + oc : c2 + (oc - w1); };
+    const int colbase = blockIdx.x * CB;
+    bool right = false;   // block holds a column right of the panel
+    for (int c = 0; c < CB; ++c)
+        if (colbase + c < ncols && col_of(colbase + c) >= k + nbw) right = true;
     if (right)
         for (int e = tid; e < nbw * nbw; e += 256) {
             const int i = e % nbw, l = e / nbw;
@@ -387,26 +453,19 @@ __global__ __launch_bounds__(256) void lu_swap_trsm_kernel(int n, cplx<T> *__res
     for (int e = tid; e < nm * CB; e += 256) {
         const int c = e % CB, q = e / CB;
         const int oc = colbase + c;
-        if (oc < n - nbw) {
-            const int col = oc < k ? oc : oc + nbw;
-            stage[q][c] = a[src[q] + (long)col * ldf];
-        }
+        if (oc < ncols) stage[q][c] = a[src[q] + (long)col_of(oc) * ldf];
     }
     __syncthreads();
     for (int e = tid; e < nm * CB; e += 256) {
         const int c = e % CB, q = e / CB;
         const int oc = colbase + c;
-        if (oc < n - nbw) {
-            const int col = oc < k ? oc : oc + nbw;
-            a[dst[q] + (long)col * ldf] = stage[q][c];
-        }
+        if (oc < ncols) a[dst[q] + (long)col_of(oc) * ldf] = stage[q][c];
     }
     __syncthreads();
     if (right && tid < CB) {
         const int oc = colbase + tid;
-        if (oc >= k && oc < n - nbw) {
-            const int col = oc + nbw;
-            V *pc = a + (long)col * ldf + k;
+        if (oc < ncols && col_of(oc) >= k + nbw) {
+            V *pc = a + (long)col_of(oc) * ldf + k;
             V x[NB];
 #pragma unroll
             for (int i = 0; i < NB; ++i) x[i] = (i < nbw) ? pc[i] : cmake<V>(0, 0);
@@ -472,15 +531,7 @@ static void launch_panel(hipStream_t s, int n, cplx<T> *F, long ldf, long sF, in
 // Largest n the register-resident panel supports (16 rows per thread).
 template <typename T> constexpr int lu_max_n() { return 16 * panel_cfg<T>::NT; }
 
-// Factor `batch` matrices of order n (stride sF, leading dimension ldf) in
-// place.  ipiv/perm: n ints per matrix (stride sPiv).  swapmap: (1 + 4 NB)
-// ints per matrix of scratch.  info: one int per matrix, 0 on success, else
-// 1 + the first zero/non-finite pivot index.
-//
-// Look-ahead of depth one: after the interchanges and U12 of panel k, the
-// columns of panel k+1 are updated first and that panel is factored on the
-// side stream s2 while the rest of the trailing update runs on s.  ev_a and
-// ev_b order the two streams; s2 == nullptr disables the look-ahead.
+// The panel kernel instance for the rows left at column k.
 template <typename T>
 static void launch_panel_rows(hipStream_t s, int n, cplx<T> *F, long ldf, long sF, int k, int *ipiv, int *perm,
                               long sPiv, int *swapmap, int *info, int batch)
@@ -508,34 +559,59 @@ static void lu_update(hipStream_t s, int n, cplx<T> *F, long ldf, long sF, int k
 }
 
 template <typename T>
+static void swap_trsm(hipStream_t s, int n, cplx<T> *F, long ldf, long sF, int k, int nbw, int c0, int c1, int c2,
+                      int c3, const int *swapmap, int batch)
+{
+    const int ncols = (c1 - c0) + (c3 - c2);
+    if (ncols <= 0) return;
+    dim3 grid(ceil_div(ncols, 64), batch);
+    hipLaunchKernelGGL((lu_swap_trsm_kernel<T, LU_NB>), grid, dim3(256), 0, s, n, F, ldf, sF, k, nbw, c0, c1, c2, c3,
+                       swapmap);
+    FX_LAUNCH_CHECK();
+}
+
+// Factor `batch` matrices of order n (stride sF, leading dimension ldf) in
+// place.  ipiv/perm: n ints per matrix (stride sPiv).  swapmap: 2 (1 + 4 NB)
+// ints per matrix of scratch.  info: one int per matrix, 0 on success, else
+// 1 + the first zero/non-finite pivot index.
+//
+// Look-ahead of depth one: panel k+1 is factored on the side stream s2
+// while the rest of step k's work runs on s (ev_a and ev_b order the two
+// streams; s2 == nullptr runs everything on s, in the same order).
+// Per step, the critical chain is: panel k -> its interchanges and U12 on
+// the next panel's columns -> the next panel's update -> panel k+1.  The
+// interchanges on every other column (left of panel k and right of the
+// next panel) and the rest of the trailing update go after panel k+1 is
+// launched, on s, while it runs on s2.  swapmap holds two move lists per
+// matrix (panels alternate), so panel k+1 can write its own while panel
+// k's is still being applied.
+template <typename T>
 void getrf_batched(hipStream_t s, hipStream_t s2, hipEvent_t ev_a, hipEvent_t ev_b, int n, cplx<T> *F, long ldf,
                    long sF, int *ipiv, int *perm, long sPiv, int *swapmap, int *info, int batch)
 {
-    launch_panel_rows<T>(s, n, F, ldf, sF, 0, ipiv, perm, sPiv, swapmap, info, batch);
+    const long smap = (long)batch * (1 + 4 * LU_NB);   // one move list per matrix
+    auto sm = [&](int k) { return swapmap + ((k / LU_NB) & 1) * smap; };
+    launch_panel_rows<T>(s, n, F, ldf, sF, 0, ipiv, perm, sPiv, sm(0), info, batch);
     for (int k = 0; k < n; k += LU_NB) {
         const int nbw = std::min(LU_NB, n - k);
-        const int outer = n - nbw;
-        if (outer > 0) {
-            dim3 grid(ceil_div(outer, 64), batch);
-            hipLaunchKernelGGL((lu_swap_trsm_kernel<T, LU_NB>), grid, dim3(256), 0, s, n, F, ldf, sF,
-                               k, nbw, swapmap);
-            FX_LAUNCH_CHECK();
-        }
         const int kn = k + nbw;            // next panel start
-        if (kn >= n) break;
+        if (kn >= n) {
+            swap_trsm<T>(s, n, F, ldf, sF, k, nbw, 0, k, 0, 0, sm(k), batch);   // left columns only
+            break;
+        }
         const int nbw2 = std::min(LU_NB, n - kn);
+        hipStream_t sp = s2 ? s2 : s;
+        swap_trsm<T>(s, n, F, ldf, sF, k, nbw, kn, kn + nbw2, 0, 0, sm(k), batch);
+        lu_update<T>(s, n, F, ldf, sF, k, nbw, kn, kn + nbw2, batch);
         if (s2) {
-            lu_update<T>(s, n, F, ldf, sF, k, nbw, kn, kn + nbw2, batch);
             FX_CHECK(hipEventRecord(ev_a, s));
             FX_CHECK(hipStreamWaitEvent(s2, ev_a, 0));
-            launch_panel_rows<T>(s2, n, F, ldf, sF, kn, ipiv, perm, sPiv, swapmap, info, batch);
-            FX_CHECK(hipEventRecord(ev_b, s2));
-            lu_update<T>(s, n, F, ldf, sF, k, nbw, kn + nbw2, n, batch);
-            FX_CHECK(hipStreamWaitEvent(s, ev_b, 0));
-        } else {
-            lu_update<T>(s, n, F, ldf, sF, k, nbw, kn, n, batch);
-            launch_panel_rows<T>(s, n, F, ldf, sF, kn, ipiv, perm, sPiv, swapmap, info, batch);
         }
+        launch_panel_rows<T>(sp, n, F, ldf, sF, kn, ipiv, perm, sPiv, sm(kn), info, batch);
+        if (s2) FX_CHECK(hipEventRecord(ev_b, s2));
+        swap_trsm<T>(s, n, F, ldf, sF, k, nbw, 0, k, kn + nbw2, n, sm(k), batch);
+        lu_update<T>(s, n, F, ldf, sF, k, nbw, kn + nbw2, n, batch);
+        if (s2) FX_CHECK(hipStreamWaitEvent(s, ev_b, 0));
     }
     hipLaunchKernelGGL((lu_finish_kernel<T>), dim3(batch), dim3(256), 0, s, n, F, ldf, sF, info);
     FX_LAUNCH_CHECK();
