@@ -26,6 +26,26 @@ PEAK_FP32_MFMA = 157.3      # TFLOP/s, dense
 PEAK_FP64_MFMA = 78.6
 N, COUNT, M0, NE, TOL, SEED = 4096, 200, 300, 8, 1e-10, 2001
 
+# HBM bytes per launch of the roofline kernel (FETCH_SIZE + WRITE_SIZE, each
+# scaled by a 256 MiB copy's reading, averaged over the launches of one
+# solve), from the rocprofv3 counter passes summarised in
+# profiles/hbm_traffic_realgen_n4096_m0300.md.  It holds only for the
+# kernel sources it was measured on: `traffic` is null when they differ.
+TRAFFIC_BYTES_PER_LAUNCH = 1.312e8
+TRAFFIC_SOURCES_SHA256 = "0567859b39c19ba955225613be571e500fee7f726d9f4f14e86a8920427b144a"
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1203_4031_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".hpp", ".h")):
+            h.update(name.encode())
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -191,11 +211,14 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "feast_loops": loops,
         "stage_ms_last_solve": stage_ms,
-        "roofline": {"kernel": "gemm_kernel<float, true, false, 128, 128, 32, 64, 64>: complex64 "
+        "roofline": {"kernel": "gemm_kernel<float, true, false, 128, 64, 16, 64, 32, 3>: complex64 "
                                "matrix product on the FP32 matrix cores (LU trailing updates and "
                                "triangular-solve updates), every launch of the timed solves",
                      "bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA,
+                     "traffic": (TRAFFIC_BYTES_PER_LAUNCH
+                                 if kernel_sources_sha256() == TRAFFIC_SOURCES_SHA256 else None),
+                     "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "launches": lu[2], "avg_launch_ms": lu[0] / max(lu[2], 1),
                      "flops_per_launch": lu[1] / max(lu[2], 1),
                      "measured_over": f"{args.roofline_steps} extra mixed solves with per-launch HIP events"},
