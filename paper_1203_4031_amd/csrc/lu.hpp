@@ -415,14 +415,14 @@ __global__ __launch_bounds__(NT) void lu_panel_kernel(int n, cplx<T> *__restrict
 }
 
 // Row interchanges of one panel (columns k..k+nbw-1) applied to a set of
-// columns outside it -- the concatenation of [c0, c1) and [c2, c3) -- and
-// U12 = L11^{-1} A12 for those of them right of the panel.  Each block owns
-// 64 columns of that set; moved values are staged through LDS so that all
-// reads happen before any write.
+// columns outside it -- the concatenation of [c0, c1) and [c2, c3) -- (mode
+// bit 0), and U12 = L11^{-1} A12 for those of them right of the panel (mode
+// bit 1).  Each block owns 64 columns of that set; moved values are staged
+// through LDS so that all reads happen before any write.
 template <typename T, int NB>
 __global__ __launch_bounds__(256) void lu_swap_trsm_kernel(int n, cplx<T> *__restrict__ Fall, long ldf,
                                                            long sF, int k, int nbw, int c0, int c1, int c2,
-                                                           int c3, const int *__restrict__ swapmap_all)
+                                                           int c3, int mode, const int *__restrict__ swapmap_all)
 {
     using V = cplx<T>;
     constexpr int CB = 64;
@@ -433,7 +433,7 @@ __global__ __launch_bounds__(256) void lu_swap_trsm_kernel(int n, cplx<T> *__res
     __shared__ V Lsh[NB][NB + 1];
     __shared__ int dst[2 * NB], src[2 * NB];
 
-    const int nm = swapmap[0];
+    const int nm = (mode & 1) ? swapmap[0] : 0;
     for (int e = tid; e < nm; e += 256) {
         dst[e] = swapmap[1 + e];
         src[e] = swapmap[1 + 2 * NB + e];
@@ -441,9 +441,10 @@ __global__ __launch_bounds__(256) void lu_swap_trsm_kernel(int n, cplx<T> *__res
     const int w1 = c1 - c0, ncols = w1 + (c3 - c2);
     auto col_of = [&](int oc) { return oc < w1 ? c0 + oc : c2 + (oc - w1); };
     const int colbase = blockIdx.x * CB;
-    bool right = false;   // block holds a column right of the panel
-    for (int c = 0; c < CB; ++c)
-        if (colbase + c < ncols && col_of(colbase + c) >= k + nbw) right = true;
+    bool right = false;   // block holds a column right of the panel (and U12 is asked for)
+    if (mode & 2)
+        for (int c = 0; c < CB; ++c)
+            if (colbase + c < ncols && col_of(colbase + c) >= k + nbw) right = true;
     if (right)
         for (int e = tid; e < nbw * nbw; e += 256) {
             const int i = e % nbw, l = e / nbw;
@@ -545,29 +546,28 @@ static void launch_panel_rows(hipStream_t s, int n, cplx<T> *F, long ldf, long s
     else launch_panel<T, 16>(s, n, F, ldf, sF, k, ipiv, perm, sPiv, swapmap, info, batch);
 }
 
-template <typename T>
-static void lu_update(hipStream_t s, int n, cplx<T> *F, long ldf, long sF, int k, int nbw, int c0, int c1,
-                      int batch)
-{
-    // A[k+nbw:, c0:c1] -= L21 U12[:, c0:c1]
-    const int m2 = n - k - nbw, nc = c1 - c0;
-    if (m2 <= 0 || nc <= 0) return;
-    cplx<T> *L21 = F + (k + nbw) + (long)k * ldf;
-    cplx<T> *U12 = F + k + (long)c0 * ldf;
-    cplx<T> *A22 = F + (k + nbw) + (long)c0 * ldf;
-    gemm<T, true, false>(s, m2, nc, nbw, T(-1), L21, ldf, sF, U12, ldf, sF, T(1), A22, ldf, sF, batch);
-}
+constexpr int LU_SWAP = 1, LU_TRSM = 2;
 
 template <typename T>
 static void swap_trsm(hipStream_t s, int n, cplx<T> *F, long ldf, long sF, int k, int nbw, int c0, int c1, int c2,
-                      int c3, const int *swapmap, int batch)
+                      int c3, int mode, const int *swapmap, int batch)
 {
     const int ncols = (c1 - c0) + (c3 - c2);
     if (ncols <= 0) return;
     dim3 grid(ceil_div(ncols, 64), batch);
     hipLaunchKernelGGL((lu_swap_trsm_kernel<T, LU_NB>), grid, dim3(256), 0, s, n, F, ldf, sF, k, nbw, c0, c1, c2, c3,
-                       swapmap);
+                       mode, swapmap);
     FX_LAUNCH_CHECK();
+}
+
+// F[r0:r1, c0:c1] -= F[r0:r1, kc0:kc1] F[kc0:kc1, c0:c1]
+template <typename T>
+static void lu_gemm(hipStream_t s, cplx<T> *F, long ldf, long sF, int r0, int r1, int c0, int c1, int kc0, int kc1,
+                    int batch)
+{
+    if (r1 <= r0 || c1 <= c0 || kc1 <= kc0) return;
+    gemm<T, true, false>(s, r1 - r0, c1 - c0, kc1 - kc0, T(-1), F + r0 + (long)kc0 * ldf, ldf, sF,
+                         F + kc0 + (long)c0 * ldf, ldf, sF, T(1), F + r0 + (long)c0 * ldf, ldf, sF, batch);
 }
 
 // Factor `batch` matrices of order n (stride sF, leading dimension ldf) in
@@ -575,43 +575,90 @@ static void swap_trsm(hipStream_t s, int n, cplx<T> *F, long ldf, long sF, int k
 // ints per matrix of scratch.  info: one int per matrix, 0 on success, else
 // 1 + the first zero/non-finite pivot index.
 //
-// Look-ahead of depth one: panel k+1 is factored on the side stream s2
-// while the rest of step k's work runs on s (ev_a and ev_b order the two
-// streams; s2 == nullptr runs everything on s, in the same order).
-// Per step, the critical chain is: panel k -> its interchanges and U12 on
-// the next panel's columns -> the next panel's update -> panel k+1.  The
-// interchanges on every other column (left of panel k and right of the
-// next panel) and the rest of the trailing update go after panel k+1 is
-// launched, on s, while it runs on s2.  swapmap holds two move lists per
-// matrix (panels alternate), so panel k+1 can write its own while panel
-// k's is still being applied.
+// Panels are NB = 32 columns wide and taken in pairs (k0, k1 = k0 + 32).
+// The far trailing update of a pair is one product of depth 64 instead of
+// two of depth 32, which halves the trailing-matrix traffic.  Per pair:
+//   1. panel k1's columns get panel k0's interchanges, U rows and update;
+//      panel k1 is factored on s2 (the look-ahead stream) while
+//   2. the far columns get panel k0's interchanges, the previous pair's
+//      deferred update (below), then panel k0's U rows;
+//   3. panel k2 = k1 + 32's columns get panel k1's interchanges (applied
+//      to panel k0's L too, so that its rows match), the depth-32
+//      correction of rows k1..k2 by panel k0, panel k1's U rows and the
+//      depth-64 update of rows k2.. by both panels; panel k2 is factored
+//      on s2 while
+//   4. the far columns get the same as in 3, except that the depth-64
+//      update of the far half of them is deferred to step 2 of the next
+//      pair, so that both panels of a pair overlap a trailing product.
+// A row permutation commutes with a row-wise update, so applying a later
+// panel's interchanges before an earlier panel's update gives the same
+// matrix, as long as the update's L rows get them too.  The columns left
+// of a panel get its interchanges off the critical chain.  ev_a and ev_b
+// order the two streams; s2 == nullptr runs everything on s in the same
+// order.  The move lists alternate between two buffers.
 template <typename T>
 void getrf_batched(hipStream_t s, hipStream_t s2, hipEvent_t ev_a, hipEvent_t ev_b, int n, cplx<T> *F, long ldf,
                    long sF, int *ipiv, int *perm, long sPiv, int *swapmap, int *info, int batch)
 {
-    const long smap = (long)batch * (1 + 4 * LU_NB);   // one move list per matrix
-    auto sm = [&](int k) { return swapmap + ((k / LU_NB) & 1) * smap; };
-    launch_panel_rows<T>(s, n, F, ldf, sF, 0, ipiv, perm, sPiv, sm(0), info, batch);
-    for (int k = 0; k < n; k += LU_NB) {
-        const int nbw = std::min(LU_NB, n - k);
-        const int kn = k + nbw;            // next panel start
-        if (kn >= n) {
-            swap_trsm<T>(s, n, F, ldf, sF, k, nbw, 0, k, 0, 0, sm(k), batch);   // left columns only
-            break;
-        }
-        const int nbw2 = std::min(LU_NB, n - kn);
-        hipStream_t sp = s2 ? s2 : s;
-        swap_trsm<T>(s, n, F, ldf, sF, k, nbw, kn, kn + nbw2, 0, 0, sm(k), batch);
-        lu_update<T>(s, n, F, ldf, sF, k, nbw, kn, kn + nbw2, batch);
+    constexpr int NB = LU_NB;
+    const long smap = (long)batch * (1 + 4 * NB);   // one move list per matrix
+    auto sm = [&](int k) { return swapmap + ((k / NB) & 1) * smap; };
+    hipStream_t sp = s2 ? s2 : s;
+    auto panel_side = [&](int k) {
         if (s2) {
             FX_CHECK(hipEventRecord(ev_a, s));
             FX_CHECK(hipStreamWaitEvent(s2, ev_a, 0));
         }
-        launch_panel_rows<T>(sp, n, F, ldf, sF, kn, ipiv, perm, sPiv, sm(kn), info, batch);
+        launch_panel_rows<T>(sp, n, F, ldf, sF, k, ipiv, perm, sPiv, sm(k), info, batch);
         if (s2) FX_CHECK(hipEventRecord(ev_b, s2));
-        swap_trsm<T>(s, n, F, ldf, sF, k, nbw, 0, k, kn + nbw2, n, sm(k), batch);
-        lu_update<T>(s, n, F, ldf, sF, k, nbw, kn + nbw2, n, batch);
+    };
+    auto join = [&]() {
         if (s2) FX_CHECK(hipStreamWaitEvent(s, ev_b, 0));
+    };
+    // the deferred depth-64 update: F[pr0:, pc0:] -= F[pr0:, pk0:pk1] F[pk0:pk1, pc0:]
+    int pc0 = n, pr0 = n, pk0 = 0, pk1 = 0;
+    launch_panel_rows<T>(s, n, F, ldf, sF, 0, ipiv, perm, sPiv, sm(0), info, batch);
+    for (int k0 = 0; k0 < n; k0 += 2 * NB) {
+        const int w0 = std::min(NB, n - k0), k1 = k0 + w0;
+        if (k1 >= n) {   // a last panel on its own (no far columns, nothing deferred)
+            swap_trsm<T>(s, n, F, ldf, sF, k0, w0, 0, k0, 0, 0, LU_SWAP, sm(k0), batch);
+            break;
+        }
+        const int w1 = std::min(NB, n - k1), k2 = k1 + w1;
+        // 1. panel k1's columns
+        swap_trsm<T>(s, n, F, ldf, sF, k0, w0, k1, k2, 0, 0, LU_SWAP | LU_TRSM, sm(k0), batch);
+        lu_gemm<T>(s, F, ldf, sF, k1, n, k1, k2, k0, k1, batch);
+        panel_side(k1);
+        // 2. far and left columns: panel k0's interchanges, the deferred
+        //    update, panel k0's U rows on the far ones
+        swap_trsm<T>(s, n, F, ldf, sF, k0, w0, 0, k0, k2, n, LU_SWAP, sm(k0), batch);
+        lu_gemm<T>(s, F, ldf, sF, pr0, n, pc0, n, pk0, pk1, batch);
+        pc0 = n;
+        swap_trsm<T>(s, n, F, ldf, sF, k0, w0, k2, n, 0, 0, LU_TRSM, sm(k0), batch);
+        join();
+        if (k2 >= n) {   // panel k1 was the last
+            swap_trsm<T>(s, n, F, ldf, sF, k1, w1, 0, k1, 0, 0, LU_SWAP, sm(k1), batch);
+            break;
+        }
+        const int w2 = std::min(NB, n - k2), k3 = k2 + w2;
+        // 3. panel k2's columns
+        swap_trsm<T>(s, n, F, ldf, sF, k1, w1, k0, k1, k2, k3, LU_SWAP, sm(k1), batch);
+        lu_gemm<T>(s, F, ldf, sF, k1, k2, k2, k3, k0, k1, batch);
+        swap_trsm<T>(s, n, F, ldf, sF, k1, w1, k2, k3, 0, 0, LU_TRSM, sm(k1), batch);
+        lu_gemm<T>(s, F, ldf, sF, k2, n, k2, k3, k0, k2, batch);
+        panel_side(k2);
+        // 4. far and left columns; the far columns past `mid` wait for the
+        //    next pair's step 2 (panel k3 = k2 + 32's columns are before mid)
+        swap_trsm<T>(s, n, F, ldf, sF, k1, w1, 0, k0, k3, n, LU_SWAP, sm(k1), batch);
+        lu_gemm<T>(s, F, ldf, sF, k1, k2, k3, n, k0, k1, batch);
+        swap_trsm<T>(s, n, F, ldf, sF, k1, w1, k3, n, 0, 0, LU_TRSM, sm(k1), batch);
+        const int mid = std::min(n, k3 + NB + ((n - k3 - NB) / 2 + 63) / 64 * 64);
+        lu_gemm<T>(s, F, ldf, sF, k2, n, k3, mid, k0, k2, batch);
+        pc0 = mid;
+        pr0 = k2;
+        pk0 = k0;
+        pk1 = k2;
+        join();
     }
     hipLaunchKernelGGL((lu_finish_kernel<T>), dim3(batch), dim3(256), 0, s, n, F, ldf, sF, info);
     FX_LAUNCH_CHECK();
