@@ -535,7 +535,12 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
     int *perm = static_cast<int *>(ws.get("perm", sizeof(int) * (size_t)ne * n));
     int *swapmap = static_cast<int *>(ws.get("swapmap", sizeof(int) * 2 * (size_t)ne * (1 + 4 * LU_NB)));
     int *dinfo = static_cast<int *>(ws.get("info", sizeof(int) * ne));
-    const long sInv = tri_inv_stride(n);
+    const bool compose = solve_nb<T>() > TRI_INV_NB;   // 128-row solve blocks from 64-row inverses
+    const long sI64 = compose ? tri_inv_stride(n) : 0, sInv = solve_inv_stride<T>(n);
+    const long sItmp = compose ? (long)ceil_div(n, solve_nb<T>()) * 64 * 64 : 0;
+    V *L64 = compose ? static_cast<V *>(ws.get("L64inv", sizeof(V) * (size_t)ne * sI64)) : nullptr;
+    V *U64 = compose ? static_cast<V *>(ws.get("U64inv", sizeof(V) * (size_t)ne * sI64)) : nullptr;
+    V *Itmp = compose ? static_cast<V *>(ws.get("Invtmp", sizeof(V) * (size_t)ne * sItmp)) : nullptr;
     V *Linv = static_cast<V *>(ws.get(mixed ? "Linv32" : "Linv64", sizeof(V) * (size_t)ne * sInv));
     V *Uinv = static_cast<V *>(ws.get(mixed ? "Uinv32" : "Uinv64", sizeof(V) * (size_t)ne * sInv));
     V *Ytmp = static_cast<V *>(ws.get(mixed ? "Yt32" : "Yt64", sizeof(V) * (size_t)ne * nm));
@@ -585,7 +590,7 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
                 getrf_batched<T>(s, g_no_lookahead ? nullptr : ws.side, ws.ev_a, ws.ev_b, n, F, ldf, sF, ipiv,
                                  perm, n, swapmap, dinfo, ne);
             }
-            tri_inv_batched<T>(s, n, F, ldf, sF, Linv, Uinv, sInv, ne);
+            solve_inverses<T>(s, n, F, ldf, sF, L64, U64, sI64, Linv, Uinv, sInv, Itmp, sItmp, ne);
             tm.mark(&st.t_factor);
             FX_CHECK(hipMemcpyAsync(h_info, dinfo, sizeof(int) * ne, hipMemcpyDeviceToHost, s));
             FX_CHECK(hipStreamSynchronize(s));
@@ -951,6 +956,7 @@ static double footprint_bytes(bool cplx, int n, int m0, const feast_opts &o, boo
     const double nn = (double)n * n, nm = (double)n * m0, mm = (double)m0 * m0;
     double b = o.ne * nn * vb;                            // factors
     b += o.ne * nm * vb * (cplx ? 4.0 : 2.0);             // solve panels
+    b += o.ne * (double)n * 448.0 * vb;                   // inverted diagonal blocks (64 and 128 wide)
     b += 7.0 * nm * eb + 16.0 * mm * eb;                  // subspace blocks, reduced problem
     if (staged) b += 2.0 * nn * eb + nm * eb;             // copies of A, B, X
     return b;

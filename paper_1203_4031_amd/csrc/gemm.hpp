@@ -1,6 +1,7 @@
 // Batched dense matrix product on the gfx950 matrix cores:
 //   C = alpha * op(A) * B + beta * C,  op(A) = A or A^H (A^T for real data),
-// column-major operands, one batch entry per blockIdx.z.
+// column-major operands, one batch entry per (blockIdx.z, blockIdx.y) with
+// strides (sA, sB, sC) and (sA2, sB2, sC2).
 //
 // Complex products are four real 16x16x4 MFMAs on the real and imaginary
 // parts of interleaved {re, im} elements.  The MFMA computes the transposed
@@ -33,7 +34,7 @@ template <typename T, bool CPLX, bool OPA_H, int BM, int BN, int BK, int WM, int
 __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, MINB) void gemm_kernel(
     int m, int n, int k, T alpha, const typename elem<T, CPLX>::type *__restrict__ A, long lda,
     long sA, const typename elem<T, CPLX>::type *__restrict__ B, long ldb, long sB, T beta,
-    typename elem<T, CPLX>::type *__restrict__ C, long ldc, long sC)
+    typename elem<T, CPLX>::type *__restrict__ C, long ldc, long sC, long sA2, long sB2, long sC2)
 {
     using E = typename elem<T, CPLX>::type;
     using MF = mfma16<T>;
@@ -53,10 +54,10 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, MINB) void gemm_kernel(
     const int tile = blockIdx.x;
     const int tm = tile % tiles_m, tn = tile / tiles_m;
     const int m0 = tm * BM, n0 = tn * BN;
-    const long bz = blockIdx.z;
-    A += bz * sA;
-    B += bz * sB;
-    C += bz * sC;
+    const long bz = blockIdx.z, by = blockIdx.y;
+    A += bz * sA + by * sA2;
+    B += bz * sB + by * sB2;
+    C += bz * sC + by * sC2;
 
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int wm = wid % WAVES_M, wn = wid / WAVES_M;
@@ -198,27 +199,35 @@ template <> struct gemm_cfg<float, false> {
 void gemm_timing_begin(hipStream_t s, hipEvent_t *e);
 void gemm_timing_end(hipStream_t s, hipEvent_t e0, double flops);
 
+// Two-level batch: entry (z, y), z < batch, y < batch2, at offsets
+// z * s? + y * s?2.
+template <typename T, bool CPLX, bool OPA_H>
+void gemm2(hipStream_t s, int m, int n, int k, T alpha, const typename elem<T, CPLX>::type *A, long lda, long sA,
+           long sA2, const typename elem<T, CPLX>::type *B, long ldb, long sB, long sB2, T beta,
+           typename elem<T, CPLX>::type *C, long ldc, long sC, long sC2, int batch, int batch2)
+{
+    if (m <= 0 || n <= 0 || batch <= 0 || batch2 <= 0) return;
+    if (alpha == T(0)) throw hip_error{hipErrorInvalidValue};   // the kernel scales C by beta / alpha
+    using cfg = gemm_cfg<T, CPLX>;
+    constexpr int NT = (cfg::BM / cfg::WM) * (cfg::BN / cfg::WN) * 64;
+    // k <= 0: C = beta C (the k loop does not run)
+    dim3 grid(ceil_div(m, cfg::BM) * ceil_div(n, cfg::BN), batch2, batch);
+    constexpr bool timed = std::is_same<T, float>::value && CPLX;
+    hipEvent_t e0 = nullptr;
+    if (timed) gemm_timing_begin(s, &e0);
+    hipLaunchKernelGGL((gemm_kernel<T, CPLX, OPA_H, cfg::BM, cfg::BN, cfg::BK, cfg::WM, cfg::WN, cfg::MINB>),
+                       grid, dim3(NT), 0, s, m, n, k, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, sA2, sB2,
+                       sC2);
+    FX_LAUNCH_CHECK();
+    if (timed) gemm_timing_end(s, e0, 8.0 * m * (double)n * (k > 0 ? k : 0) * batch * batch2);
+}
+
 template <typename T, bool CPLX, bool OPA_H>
 void gemm(hipStream_t s, int m, int n, int k, T alpha, const typename elem<T, CPLX>::type *A,
           long lda, long sA, const typename elem<T, CPLX>::type *B, long ldb, long sB, T beta,
           typename elem<T, CPLX>::type *C, long ldc, long sC, int batch)
 {
-    if (m <= 0 || n <= 0 || batch <= 0) return;
-    if (alpha == T(0)) throw hip_error{hipErrorInvalidValue};   // the kernel scales C by beta / alpha
-    using cfg = gemm_cfg<T, CPLX>;
-    constexpr int NT = (cfg::BM / cfg::WM) * (cfg::BN / cfg::WN) * 64;
-    if (k <= 0) {
-        // C = beta C: reuse the kernel with k = 0 (the k loop does not run)
-    }
-    dim3 grid(ceil_div(m, cfg::BM) * ceil_div(n, cfg::BN), 1, batch);
-    constexpr bool timed = std::is_same<T, float>::value && CPLX;
-    hipEvent_t e0 = nullptr;
-    if (timed) gemm_timing_begin(s, &e0);
-    hipLaunchKernelGGL((gemm_kernel<T, CPLX, OPA_H, cfg::BM, cfg::BN, cfg::BK, cfg::WM, cfg::WN, cfg::MINB>),
-                       grid, dim3(NT), 0, s, m, n, k, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc,
-                       sC);
-    FX_LAUNCH_CHECK();
-    if (timed) gemm_timing_end(s, e0, 8.0 * m * (double)n * (k > 0 ? k : 0) * batch);
+    gemm2<T, CPLX, OPA_H>(s, m, n, k, alpha, A, lda, sA, 0, B, ldb, sB, 0, beta, C, ldc, sC, 0, batch, 1);
 }
 
 }  // namespace fx

@@ -3,9 +3,11 @@
 // Hermitian pencils, reusing the same factors):
 //   A_z Y = R   :  Y = U^{-1} L^{-1} P R
 //   A_z^H Y = R :  Y = P^T L^{-H} U^{-H} R
-// Blocked by NBS rows, with the diagonal blocks of L and U inverted once per
-// factorisation, so every step is a matrix-core product.  All contour nodes
-// are solved in one launch per step (blockIdx.y / blockIdx.z = node).
+// Blocked by solve_nb rows (128 in FP64, 64 in complex64), with the
+// diagonal blocks of L and U inverted once per factorisation (128-row
+// blocks from inverted 64 x 64 halves), so every step is a matrix-core
+// product of that depth.  All contour nodes are
+// solved in one launch per step (blockIdx.y / blockIdx.z = node).
 #pragma once
 
 #include "common.hpp"
@@ -13,7 +15,12 @@
 
 namespace fx {
 
-constexpr int SOLVE_NB = 64;
+constexpr int TRI_INV_NB = 64;   // diagonal blocks inverted directly
+// Solve block: 128 rows (two inverted halves composed) in FP64; 64 in
+// complex64, where the explicit inverse of a 128-row triangle loses enough
+// accuracy (its condition number times the unit roundoff) to cost the mixed
+// path an extra FEAST loop.
+template <typename T> constexpr int solve_nb() { return sizeof(T) == 8 ? 128 : 64; }
 
 // Y_b[i, c] = R[perm_b[i], c] in the solve precision.  R is FP64 real or
 // complex, shared by all nodes.
@@ -117,12 +124,102 @@ template <typename T>
 void tri_inv_batched(hipStream_t s, int n, const cplx<T> *F, long ldf, long sF, cplx<T> *Linv, cplx<T> *Uinv,
                      long sInv, int batch)
 {
-    dim3 grid(ceil_div(n, SOLVE_NB), batch);
-    hipLaunchKernelGGL((tri_inv_kernel<T, SOLVE_NB>), grid, dim3(SOLVE_NB), 0, s, n, F, ldf, sF, Linv, Uinv, sInv);
+    dim3 grid(ceil_div(n, TRI_INV_NB), batch);
+    hipLaunchKernelGGL((tri_inv_kernel<T, TRI_INV_NB>), grid, dim3(TRI_INV_NB), 0, s, n, F, ldf, sF, Linv, Uinv,
+                       sInv);
     FX_LAUNCH_CHECK();
 }
 
-inline long tri_inv_stride(int n) { return (long)ceil_div(n, SOLVE_NB) * SOLVE_NB * SOLVE_NB; }
+inline long tri_inv_stride(int n) { return (long)ceil_div(n, TRI_INV_NB) * TRI_INV_NB * TRI_INV_NB; }
+template <typename T> inline long solve_inv_stride(int n)
+{
+    return (long)ceil_div(n, solve_nb<T>()) * solve_nb<T>() * solve_nb<T>();
+}
+
+// 128 x 128 inverse blocks from the 64 x 64 ones: the diagonal halves are
+// copied here (identity past the matrix end), the off-diagonal half is zero
+// and, where both halves exist, filled by solve_inverses with
+//   [[A, 0], [C, D]]^{-1} = [[A^{-1}, 0], [-D^{-1} C A^{-1}, D^{-1}]]   (L)
+//   [[A, B], [0, D]]^{-1} = [[A^{-1}, -A^{-1} B D^{-1}], [0, D^{-1}]]   (U)
+template <typename T>
+__global__ __launch_bounds__(256) void inv128_assemble_kernel(int n, const cplx<T> *__restrict__ L64,
+                                                              const cplx<T> *__restrict__ U64, long s64,
+                                                              cplx<T> *__restrict__ L128, cplx<T> *__restrict__ U128,
+                                                              long s128)
+{
+    using V = cplx<T>;
+    constexpr int H = TRI_INV_NB, W = 2 * TRI_INV_NB;
+    const int b = blockIdx.x, nb64 = (n + H - 1) / H;
+    const V *l = L64 + blockIdx.y * s64, *u = U64 + blockIdx.y * s64;
+    V *lo = L128 + blockIdx.y * s128 + (long)b * W * W, *uo = U128 + blockIdx.y * s128 + (long)b * W * W;
+    for (int e = threadIdx.x; e < W * W; e += 256) {
+        const int i = e % W, j = e / W, hi = i / H, hj = j / H;
+        V lv = cmake<V>(0, 0), uv = cmake<V>(0, 0);
+        if (hi == hj) {
+            const int blk = 2 * b + hi;
+            if (blk < nb64) {
+                const long o = (long)blk * H * H + (i % H) + (long)(j % H) * H;
+                lv = l[o];
+                uv = u[o];
+            } else if (i == j) {
+                lv = uv = cmake<V>(1, 0);
+            }
+        }
+        lo[e] = lv;
+        uo[e] = uv;
+    }
+}
+
+// Inverted diagonal blocks for the solves (L128, U128, stride s128, blocks
+// of solve_nb rows).  For 128-row blocks: 64 x 64 inverses first (L64,
+// U64, stride s64), then the composition; tmp: ceil(n / 128) * 64 * 64
+// elements per matrix (stride stmp).  For 64-row blocks only L128/U128 are
+// used.
+template <typename T>
+void solve_inverses(hipStream_t s, int n, const cplx<T> *F, long ldf, long sF, cplx<T> *L64, cplx<T> *U64, long s64,
+                    cplx<T> *L128, cplx<T> *U128, long s128, cplx<T> *tmp, long stmp, int batch)
+{
+    constexpr int H = TRI_INV_NB, W = solve_nb<T>();
+    constexpr long HH = (long)H * H, WW = (long)W * W;
+    if constexpr (W == H) {   // the 64-row inverses are the solve blocks
+        tri_inv_batched<T>(s, n, F, ldf, sF, L128, U128, s128, batch);
+        return;
+    } else {
+    tri_inv_batched<T>(s, n, F, ldf, sF, L64, U64, s64, batch);
+    const int nb128 = ceil_div(n, W);
+    hipLaunchKernelGGL((inv128_assemble_kernel<T>), dim3(nb128, batch), dim3(256), 0, s, n, L64, U64, s64, L128, U128,
+                       s128);
+    FX_LAUNCH_CHECK();
+    const int nfull = n / W;
+    const long sFb = W + (long)W * ldf;   // one 128-block down the diagonal
+    const T one = T(1), mone = T(-1), zero = T(0);
+    if (nfull > 0) {
+        // L: tmp = C A^{-1}, lower-left = -D^{-1} tmp
+        gemm2<T, true, false>(s, H, H, H, one, F + H, ldf, sF, sFb, L64, H, s64, 2 * HH, zero, tmp, H, stmp, HH,
+                              batch, nfull);
+        gemm2<T, true, false>(s, H, H, H, mone, L64 + HH, H, s64, 2 * HH, tmp, H, stmp, HH, zero, L128 + H, W, s128,
+                              WW, batch, nfull);
+        // U: tmp = A^{-1} B, upper-right = -tmp D^{-1}
+        gemm2<T, true, false>(s, H, H, H, one, U64, H, s64, 2 * HH, F + (long)H * ldf, ldf, sF, sFb, zero, tmp, H,
+                              stmp, HH, batch, nfull);
+        gemm2<T, true, false>(s, H, H, H, mone, tmp, H, stmp, HH, U64 + HH, H, s64, 2 * HH, zero, U128 + (long)H * W,
+                              W, s128, WW, batch, nfull);
+    }
+    const int w = n - nfull * W;
+    if (w > H) {   // a last, partial 128-block whose second half has w2 rows
+        const int b = nfull, kb = b * W, w2 = w - H;
+        const long o64a = (long)(2 * b) * HH, o64b = (long)(2 * b + 1) * HH, o128 = (long)b * WW;
+        gemm<T, true, false>(s, w2, H, H, one, F + (kb + H) + (long)kb * ldf, ldf, sF, L64 + o64a, H, s64, zero, tmp,
+                             H, stmp, batch);
+        gemm<T, true, false>(s, w2, H, w2, mone, L64 + o64b, H, s64, tmp, H, stmp, zero, L128 + o128 + H, W, s128,
+                             batch);
+        gemm<T, true, false>(s, H, w2, H, one, U64 + o64a, H, s64, F + kb + (long)(kb + H) * ldf, ldf, sF, zero, tmp,
+                             H, stmp, batch);
+        gemm<T, true, false>(s, H, w2, w2, mone, tmp, H, stmp, U64 + o64b, H, s64, zero, U128 + o128 + (long)H * W, W,
+                             s128, batch);
+    }
+    }
+}
 
 // Multi-RHS solve with the stored factors using only matrix products:
 //   adjoint = false:  Y <- U^{-1} L^{-1} Y   (Y already row-permuted)
@@ -136,7 +233,7 @@ void getrs_batched(hipStream_t s, bool adjoint, int n, int ncols, const cplx<T> 
                    const cplx<T> *Linv, const cplx<T> *Uinv, long sInv, cplx<T> *Y, cplx<T> *X, long ldy,
                    long sY, int batch)
 {
-    constexpr int NB = SOLVE_NB;
+    constexpr int NB = solve_nb<T>();
     const int nblk = ceil_div(n, NB);
     auto inv_blk = [&](const cplx<T> *base, int b) { return base + (long)b * NB * NB; };
     if (!adjoint) {
