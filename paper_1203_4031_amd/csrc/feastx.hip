@@ -541,6 +541,7 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
     V *L64 = compose ? static_cast<V *>(ws.get("L64inv", sizeof(V) * (size_t)ne * sI64)) : nullptr;
     V *U64 = compose ? static_cast<V *>(ws.get("U64inv", sizeof(V) * (size_t)ne * sI64)) : nullptr;
     V *Itmp = compose ? static_cast<V *>(ws.get("Invtmp", sizeof(V) * (size_t)ne * sItmp)) : nullptr;
+    V *Wsv = static_cast<V *>(ws.get(mixed ? "Wsolve32" : "Wsolve64", sizeof(V) * (size_t)ne * sF));
     V *Linv = static_cast<V *>(ws.get(mixed ? "Linv32" : "Linv64", sizeof(V) * (size_t)ne * sInv));
     V *Uinv = static_cast<V *>(ws.get(mixed ? "Uinv32" : "Uinv64", sizeof(V) * (size_t)ne * sInv));
     V *Ytmp = static_cast<V *>(ws.get(mixed ? "Yt32" : "Yt64", sizeof(V) * (size_t)ne * nm));
@@ -591,6 +592,7 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
                                  perm, n, swapmap, dinfo, ne);
             }
             solve_inverses<T>(s, n, F, ldf, sF, L64, U64, sI64, Linv, Uinv, sInv, Itmp, sItmp, ne);
+            build_w<T>(s, n, F, ldf, sF, Linv, Uinv, sInv, Wsv, ne);
             tm.mark(&st.t_factor);
             FX_CHECK(hipMemcpyAsync(h_info, dinfo, sizeof(int) * ne, hipMemcpyDeviceToHost, s));
             FX_CHECK(hipStreamSynchronize(s));
@@ -620,12 +622,12 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
             hipLaunchKernelGGL((gather_rows_kernel<T, CPLX>), g, dim3(256), 0, s, n, m0, perm, (long)n,
                                reinterpret_cast<const double *>(R), (long)n, Y, (long)n, (long)cur_nm);
             FX_LAUNCH_CHECK();
-            getrs_batched<T>(s, false, n, m0, F, ldf, sF, Linv, Uinv, sInv, Y, Ytmp, n, (long)cur_nm, ne);
+            getrs_batched<T>(s, false, n, m0, F, Wsv, ldf, sF, Linv, Uinv, sInv, Y, Ytmp, n, (long)cur_nm, ne);
             if (CPLX) {
                 hipLaunchKernelGGL((copy_rhs_kernel<T, CPLX>), g, dim3(256), 0, s, n, m0,
                                    reinterpret_cast<const double *>(R), (long)n, Yh, (long)n, (long)cur_nm);
                 FX_LAUNCH_CHECK();
-                getrs_batched<T>(s, true, n, m0, F, ldf, sF, Linv, Uinv, sInv, Yh, Ytmp, n, (long)cur_nm, ne);
+                getrs_batched<T>(s, true, n, m0, F, Wsv, ldf, sF, Linv, Uinv, sInv, Yh, Ytmp, n, (long)cur_nm, ne);
                 hipLaunchKernelGGL((scatter_rows_kernel<T>), g, dim3(256), 0, s, n, m0, perm, (long)n, Yh,
                                    (long)n, (long)cur_nm, Yh2, (long)n, (long)cur_nm);
                 FX_LAUNCH_CHECK();
@@ -954,7 +956,7 @@ static double footprint_bytes(bool cplx, int n, int m0, const feast_opts &o, boo
     const double vb = (o.precision == 1) ? 8.0 : 16.0;   // complex factor element
     const double eb = cplx ? 16.0 : 8.0;                  // FP64 element
     const double nn = (double)n * n, nm = (double)n * m0, mm = (double)m0 * m0;
-    double b = o.ne * nn * vb;                            // factors
+    double b = 2.0 * o.ne * nn * vb;                      // factors and their solve form W
     b += o.ne * nm * vb * (cplx ? 4.0 : 2.0);             // solve panels
     b += o.ne * (double)n * 448.0 * vb;                   // inverted diagonal blocks (64 and 128 wide)
     b += 7.0 * nm * eb + 16.0 * mm * eb;                  // subspace blocks, reduced problem

@@ -32,9 +32,9 @@ template <> __device__ inline double2 conj_elem<double2>(double2 v) { return mak
 
 template <typename T, bool CPLX, bool OPA_H, int BM, int BN, int BK, int WM, int WN, int MINB>
 __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, MINB) void gemm_kernel(
-    int m, int n, int k, T alpha, const typename elem<T, CPLX>::type *__restrict__ A, long lda,
+    int m_in, int n, int k, T alpha, const typename elem<T, CPLX>::type *__restrict__ A, long lda,
     long sA, const typename elem<T, CPLX>::type *__restrict__ B, long ldb, long sB, T beta,
-    typename elem<T, CPLX>::type *__restrict__ C, long ldc, long sC, long sA2, long sB2, long sC2)
+    typename elem<T, CPLX>::type *__restrict__ C, long ldc, long sC, long sA2, long sB2, long sC2, int dm)
 {
     using E = typename elem<T, CPLX>::type;
     using MF = mfma16<T>;
@@ -50,10 +50,13 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, MINB) void gemm_kernel(
     __shared__ E As[BK][BM + PAD];
     __shared__ E Bs[BK][BN + PAD];
 
-    const int tiles_m = (m + BM - 1) / BM;
+    // rows of this batch entry: m_in + y * dm (the grid covers the largest)
+    const int tiles_m = (m_in + (dm > 0 ? (int)(gridDim.y - 1) * dm : 0) + BM - 1) / BM;
+    const int m = m_in + (int)blockIdx.y * dm;
     const int tile = blockIdx.x;
     const int tm = tile % tiles_m, tn = tile / tiles_m;
     const int m0 = tm * BM, n0 = tn * BN;
+    if (m0 >= m) return;   // whole workgroup, before any barrier
     const long bz = blockIdx.z, by = blockIdx.y;
     A += bz * sA + by * sA2;
     B += bz * sB + by * sB2;
@@ -200,26 +203,30 @@ void gemm_timing_begin(hipStream_t s, hipEvent_t *e);
 void gemm_timing_end(hipStream_t s, hipEvent_t e0, double flops);
 
 // Two-level batch: entry (z, y), z < batch, y < batch2, at offsets
-// z * s? + y * s?2.
+// z * s? + y * s?2, with m + y * dm rows (dm may be negative; entries with
+// no rows do nothing).
 template <typename T, bool CPLX, bool OPA_H>
 void gemm2(hipStream_t s, int m, int n, int k, T alpha, const typename elem<T, CPLX>::type *A, long lda, long sA,
            long sA2, const typename elem<T, CPLX>::type *B, long ldb, long sB, long sB2, T beta,
-           typename elem<T, CPLX>::type *C, long ldc, long sC, long sC2, int batch, int batch2)
+           typename elem<T, CPLX>::type *C, long ldc, long sC, long sC2, int batch, int batch2, int dm = 0)
 {
-    if (m <= 0 || n <= 0 || batch <= 0 || batch2 <= 0) return;
+    const int mmax = std::max(m, m + (batch2 - 1) * dm);
+    if (mmax <= 0 || n <= 0 || batch <= 0 || batch2 <= 0) return;
     if (alpha == T(0)) throw hip_error{hipErrorInvalidValue};   // the kernel scales C by beta / alpha
     using cfg = gemm_cfg<T, CPLX>;
     constexpr int NT = (cfg::BM / cfg::WM) * (cfg::BN / cfg::WN) * 64;
     // k <= 0: C = beta C (the k loop does not run)
-    dim3 grid(ceil_div(m, cfg::BM) * ceil_div(n, cfg::BN), batch2, batch);
+    dim3 grid(ceil_div(mmax, cfg::BM) * ceil_div(n, cfg::BN), batch2, batch);
     constexpr bool timed = std::is_same<T, float>::value && CPLX;
     hipEvent_t e0 = nullptr;
     if (timed) gemm_timing_begin(s, &e0);
     hipLaunchKernelGGL((gemm_kernel<T, CPLX, OPA_H, cfg::BM, cfg::BN, cfg::BK, cfg::WM, cfg::WN, cfg::MINB>),
                        grid, dim3(NT), 0, s, m, n, k, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, sA2, sB2,
-                       sC2);
+                       sC2, dm);
     FX_LAUNCH_CHECK();
-    if (timed) gemm_timing_end(s, e0, 8.0 * m * (double)n * (k > 0 ? k : 0) * batch * batch2);
+    double rows = 0;   // summed over the y entries
+    for (int y = 0; y < batch2; ++y) rows += std::max(0, m + y * dm);
+    if (timed) gemm_timing_end(s, e0, 8.0 * rows * (double)n * (k > 0 ? k : 0) * batch);
 }
 
 template <typename T, bool CPLX, bool OPA_H>

@@ -221,53 +221,124 @@ void solve_inverses(hipStream_t s, int n, const cplx<T> *F, long ldf, long sF, c
     }
 }
 
+// W for the solves with A_z (not its adjoint): below each diagonal block b
+// (NB = solve_nb rows), W = L_{.,b} Linv_b; above it, W = U_{.,b} Uinv_b.
+// With it a triangular sweep is one product per block on the unscaled
+// running right-hand side, and the diagonal inverses are applied once at
+// the end (getrs_batched).  W has the factors' layout (ld ldf, stride sF);
+// its diagonal blocks are not used.
+template <typename T>
+void build_w(hipStream_t s, int n, const cplx<T> *F, long ldf, long sF, const cplx<T> *Linv, const cplx<T> *Uinv,
+             long sInv, cplx<T> *W, int batch)
+{
+    constexpr int NB = solve_nb<T>();
+    constexpr long NN = (long)NB * NB;
+    const int nfull = n / NB, w = n - nfull * NB;
+    const long sdiag = NB + (long)NB * ldf;
+    if (nfull > 0) {
+        // L part of block b: rows (b + 1) NB .. n-1, i.e. n - NB - b NB rows
+        gemm2<T, true, false>(s, n - NB, NB, NB, T(1), F + NB, ldf, sF, sdiag, Linv, NB, sInv, NN, T(0), W + NB, ldf,
+                              sF, sdiag, batch, nfull, -NB);
+        // U part of block b: rows 0 .. b NB - 1
+        gemm2<T, true, false>(s, 0, NB, NB, T(1), F, ldf, sF, (long)NB * ldf, Uinv, NB, sInv, NN, T(0), W, ldf, sF,
+                              (long)NB * ldf, batch, nfull, NB);
+    }
+    if (w > 0 && nfull > 0) {   // U part of a last, partial block
+        const int kb = nfull * NB;
+        gemm<T, true, false>(s, kb, w, w, T(1), F + (long)kb * ldf, ldf, sF, Uinv + nfull * NN, NB, sInv, T(0),
+                             W + (long)kb * ldf, ldf, sF, batch);
+    }
+}
+
+// Out = blockdiag(Dinv) In, both n x ncols (ld ldy, stride sY), one launch
+// for the full blocks and one for a partial last block.
+template <typename T>
+static void apply_block_diag(hipStream_t s, int n, int ncols, const cplx<T> *Dinv, long sInv, const cplx<T> *In,
+                             cplx<T> *Out, long ldy, long sY, int batch)
+{
+    constexpr int NB = solve_nb<T>();
+    constexpr long NN = (long)NB * NB;
+    const int nfull = n / NB, w = n - nfull * NB;
+    if (nfull > 0)
+        gemm2<T, true, false>(s, NB, ncols, NB, T(1), Dinv, NB, sInv, NN, In, ldy, sY, NB, T(0), Out, ldy, sY, NB,
+                              batch, nfull);
+    if (w > 0)
+        gemm<T, true, false>(s, w, ncols, w, T(1), Dinv + nfull * NN, NB, sInv, In + nfull * NB, ldy, sY, T(0),
+                             Out + nfull * NB, ldy, sY, batch);
+}
+
 // Multi-RHS solve with the stored factors using only matrix products:
 //   adjoint = false:  Y <- U^{-1} L^{-1} Y   (Y already row-permuted)
 //   adjoint = true:   Y <- L^{-H} U^{-H} Y   (row permutation applied by the caller)
-// Block k of the forward sweep: X_k = Dinv_k Y_k, then Y_rest -= T_rest,k X_k;
-// the backward sweep runs the other way with the roles of X and Y swapped,
-// so the result ends in Y with no copies.  Dinv_k are the inverted
-// diagonal blocks from tri_inv_batched.
+// The sweeps alternate between Y and X, so the result ends in Y with no
+// copies.  Dinv_b are the inverted diagonal blocks (NB = solve_nb rows).
+// Solves with A_z use W (build_w): each block is one product on the
+// running right-hand side, the diagonal inverses go last.  Adjoint solves:
+// block b of the forward sweep is X_b = Dinv_b^H Y_b, then the rows below
+// get -= T^H X_b; blocks are taken in groups of GB (two 64-row blocks in
+// complex64, one 128-row block in FP64): inside a group the later blocks
+// are updated block by block, the rows past the group get one product of
+// the group's depth (128).
 template <typename T>
-void getrs_batched(hipStream_t s, bool adjoint, int n, int ncols, const cplx<T> *F, long ldf, long sF,
-                   const cplx<T> *Linv, const cplx<T> *Uinv, long sInv, cplx<T> *Y, cplx<T> *X, long ldy,
+void getrs_batched(hipStream_t s, bool adjoint, int n, int ncols, const cplx<T> *F, const cplx<T> *W, long ldf,
+                   long sF, const cplx<T> *Linv, const cplx<T> *Uinv, long sInv, cplx<T> *Y, cplx<T> *X, long ldy,
                    long sY, int batch)
 {
     constexpr int NB = solve_nb<T>();
-    const int nblk = ceil_div(n, NB);
+    constexpr int GB = 128 / NB;   // blocks per group
+    const int nblk = ceil_div(n, NB), ngrp = ceil_div(nblk, GB);
     auto inv_blk = [&](const cplx<T> *base, int b) { return base + (long)b * NB * NB; };
+    auto grp = [&](int g, int &gs, int &ge, int &b0, int &b1) {   // rows [gs, ge), blocks [b0, b1)
+        b0 = g * GB;
+        b1 = std::min(nblk, b0 + GB);
+        gs = b0 * NB;
+        ge = std::min(n, b1 * NB);
+    };
+    int gs, ge, b0, b1;
     if (!adjoint) {
-        for (int b = 0; b < nblk; ++b) {       // L, forward: Y -> X
+        // L, forward, on Y in place with W, then X = blockdiag(Linv) Y
+        for (int b = 0; b < nblk; ++b) {
             const int kb = b * NB, w = std::min(NB, n - kb);
-            gemm<T, true, false>(s, w, ncols, w, T(1), inv_blk(Linv, b), NB, sInv, Y + kb, ldy, sY, T(0), X + kb,
-                                 ldy, sY, batch);
             if (kb + w < n)
-                gemm<T, true, false>(s, n - kb - w, ncols, w, T(-1), F + (kb + w) + (long)kb * ldf, ldf, sF, X + kb,
+                gemm<T, true, false>(s, n - kb - w, ncols, w, T(-1), W + (kb + w) + (long)kb * ldf, ldf, sF, Y + kb,
                                      ldy, sY, T(1), Y + kb + w, ldy, sY, batch);
         }
-        for (int b = nblk - 1; b >= 0; --b) {  // U, backward: X -> Y
+        apply_block_diag<T>(s, n, ncols, Linv, sInv, Y, X, ldy, sY, batch);
+        // U, backward, on X in place with W, then Y = blockdiag(Uinv) X
+        for (int b = nblk - 1; b >= 0; --b) {
             const int kb = b * NB, w = std::min(NB, n - kb);
-            gemm<T, true, false>(s, w, ncols, w, T(1), inv_blk(Uinv, b), NB, sInv, X + kb, ldy, sY, T(0), Y + kb,
-                                 ldy, sY, batch);
             if (kb > 0)
-                gemm<T, true, false>(s, kb, ncols, w, T(-1), F + (long)kb * ldf, ldf, sF, Y + kb, ldy, sY, T(1), X,
+                gemm<T, true, false>(s, kb, ncols, w, T(-1), W + (long)kb * ldf, ldf, sF, X + kb, ldy, sY, T(1), X,
                                      ldy, sY, batch);
         }
+        apply_block_diag<T>(s, n, ncols, Uinv, sInv, X, Y, ldy, sY, batch);
     } else {
-        for (int b = 0; b < nblk; ++b) {       // U^H, forward: Y -> X
-            const int kb = b * NB, w = std::min(NB, n - kb);
-            gemm<T, true, true>(s, w, ncols, w, T(1), inv_blk(Uinv, b), NB, sInv, Y + kb, ldy, sY, T(0), X + kb,
-                                ldy, sY, batch);
-            if (kb + w < n)
-                gemm<T, true, true>(s, n - kb - w, ncols, w, T(-1), F + kb + (long)(kb + w) * ldf, ldf, sF, X + kb,
-                                    ldy, sY, T(1), Y + kb + w, ldy, sY, batch);
+        for (int g = 0; g < ngrp; ++g) {       // U^H, forward: Y -> X
+            grp(g, gs, ge, b0, b1);
+            for (int b = b0; b < b1; ++b) {
+                const int kb = b * NB, w = std::min(NB, n - kb);
+                gemm<T, true, true>(s, w, ncols, w, T(1), inv_blk(Uinv, b), NB, sInv, Y + kb, ldy, sY, T(0),
+                                    X + kb, ldy, sY, batch);
+                if (kb + w < ge)
+                    gemm<T, true, true>(s, ge - kb - w, ncols, w, T(-1), F + kb + (long)(kb + w) * ldf, ldf, sF,
+                                        X + kb, ldy, sY, T(1), Y + kb + w, ldy, sY, batch);
+            }
+            if (ge < n)
+                gemm<T, true, true>(s, n - ge, ncols, ge - gs, T(-1), F + gs + (long)ge * ldf, ldf, sF, X + gs, ldy,
+                                    sY, T(1), Y + ge, ldy, sY, batch);
         }
-        for (int b = nblk - 1; b >= 0; --b) {  // L^H, backward: X -> Y
-            const int kb = b * NB, w = std::min(NB, n - kb);
-            gemm<T, true, true>(s, w, ncols, w, T(1), inv_blk(Linv, b), NB, sInv, X + kb, ldy, sY, T(0), Y + kb,
-                                ldy, sY, batch);
-            if (kb > 0)
-                gemm<T, true, true>(s, kb, ncols, w, T(-1), F + kb, ldf, sF, Y + kb, ldy, sY, T(1), X, ldy, sY,
+        for (int g = ngrp - 1; g >= 0; --g) {  // L^H, backward: X -> Y
+            grp(g, gs, ge, b0, b1);
+            for (int b = b1 - 1; b >= b0; --b) {
+                const int kb = b * NB, w = std::min(NB, n - kb);
+                gemm<T, true, true>(s, w, ncols, w, T(1), inv_blk(Linv, b), NB, sInv, X + kb, ldy, sY, T(0),
+                                    Y + kb, ldy, sY, batch);
+                if (kb > gs)
+                    gemm<T, true, true>(s, kb - gs, ncols, w, T(-1), F + kb + (long)gs * ldf, ldf, sF, Y + kb, ldy,
+                                        sY, T(1), X + gs, ldy, sY, batch);
+            }
+            if (gs > 0)
+                gemm<T, true, true>(s, gs, ncols, ge - gs, T(-1), F + gs, ldf, sF, Y + gs, ldy, sY, T(1), X, ldy, sY,
                                     batch);
         }
     }
