@@ -463,22 +463,42 @@ __global__ __launch_bounds__(256) void lu_swap_trsm_kernel(int n, cplx<T> *__res
         if (oc < ncols) a[dst[q] + (long)col_of(oc) * ldf] = stage[q][c];
     }
     __syncthreads();
-    if (right && tid < CB) {
-        const int oc = colbase + tid;
-        if (oc < ncols && col_of(oc) >= k + nbw) {
-            V *pc = a + (long)col_of(oc) * ldf + k;
-            V x[NB];
+    if (right) {
+        // U12 = L11^{-1} A12 by column-oriented substitution shared by the
+        // whole block: thread (c, g) = (tid mod 64, tid / 64) keeps rows
+        // g, g + 4, ... of column c in registers; at step l the wave that
+        // owns row l publishes it (two alternating LDS rows), so a step is
+        // one barrier and NB/4 independent multiply-adds per thread
+        static_assert(256 / CB == 4 && NB % 4 == 0, "4 row groups of 64 columns");
+        const int c = tid % CB, g = tid / CB;
+        const int oc = colbase + c;
+        const bool colok = oc < ncols && col_of(oc) >= k + nbw;
+        V *pc = a + (long)(colok ? col_of(oc) : 0) * ldf + k;
+        V xr[NB / 4];
 #pragma unroll
-            for (int i = 0; i < NB; ++i) x[i] = (i < nbw) ? pc[i] : cmake<V>(0, 0);
-#pragma unroll
-            for (int i = 1; i < NB; ++i)
-#pragma unroll
-                for (int l = 0; l < i; ++l)
-                    if (i < nbw) x[i] = csub(x[i], cmul(Lsh[i][l], x[l]));
-#pragma unroll
-            for (int i = 0; i < NB; ++i)
-                if (i < nbw) pc[i] = x[i];
+        for (int j = 0; j < NB / 4; ++j) {
+            const int i = g + 4 * j;
+            xr[j] = (colok && i < nbw) ? pc[i] : cmake<V>(0, 0);
         }
+        V(*xrow)[CB] = stage;   // free again: the moves are done
+#pragma unroll
+        for (int l = 0; l < NB - 1; ++l) {
+            if (l + 1 >= nbw) break;   // uniform
+            if (g == (l & 3)) xrow[l & 1][c] = xr[l >> 2];
+            __syncthreads();
+            const V xl = xrow[l & 1][c];
+#pragma unroll
+            for (int j = 0; j < NB / 4; ++j) {
+                const int i = g + 4 * j;
+                if (i > l && i < nbw) xr[j] = csub(xr[j], cmul(Lsh[i][l], xl));
+            }
+        }
+        if (colok)
+#pragma unroll
+            for (int j = 0; j < NB / 4; ++j) {
+                const int i = g + 4 * j;
+                if (i < nbw) pc[i] = xr[j];
+            }
     }
 }
 

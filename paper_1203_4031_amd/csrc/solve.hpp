@@ -104,18 +104,22 @@ __global__ __launch_bounds__(NBS) void tri_inv_kernel(int n, const cplx<T> *__re
         Tsh[i][l] = (i < w && l < w) ? a[(kb + i) + (long)(kb + l) * ldf] : cmake<V>(i == l ? 1 : 0, 0);
     }
     __syncthreads();
+    // Column c of each inverse, column-oriented substitution (once x_l is
+    // final it updates every later row), so the dependency chain is NBS
+    // steps long.
     // L^{-1}: forward substitution on e_c, unit diagonal
-    for (int i = 0; i < NBS; ++i) {
-        V s = cmake<V>(i == c ? 1 : 0, 0);
-        for (int l = c; l < i; ++l) s = csub(s, cmul(Tsh[i][l], Xs[l][c]));
-        Xs[i][c] = (i < c) ? cmake<V>(0, 0) : s;
+    for (int i = 0; i < NBS; ++i) Xs[i][c] = cmake<V>(i == c ? 1 : 0, 0);
+    for (int l = c; l < NBS - 1; ++l) {
+        const V xl = Xs[l][c];
+        for (int i = l + 1; i < NBS; ++i) Xs[i][c] = csub(Xs[i][c], cmul(Tsh[i][l], xl));
     }
     for (int i = 0; i < NBS; ++i) Li[i + c * NBS] = Xs[i][c];
     // U^{-1}: backward substitution on e_c
-    for (int i = NBS - 1; i >= 0; --i) {
-        V s = cmake<V>(i == c ? 1 : 0, 0);
-        for (int l = i + 1; l <= c; ++l) s = csub(s, cmul(Tsh[i][l], Xs[l][c]));
-        Xs[i][c] = (i > c) ? cmake<V>(0, 0) : cmul(s, cinv(Tsh[i][i]));
+    for (int i = 0; i < NBS; ++i) Xs[i][c] = cmake<V>(i == c ? 1 : 0, 0);
+    for (int l = c; l >= 0; --l) {
+        const V xl = cmul(Xs[l][c], cinv(Tsh[l][l]));
+        Xs[l][c] = xl;
+        for (int i = 0; i < l; ++i) Xs[i][c] = csub(Xs[i][c], cmul(Tsh[i][l], xl));
     }
     for (int i = 0; i < NBS; ++i) Ui[i + c * NBS] = Xs[i][c];
 }
