@@ -223,7 +223,9 @@ __global__ __launch_bounds__(BJ_NT) void bjacobi_kernel(int n, typename jelem<CP
                     L0[a][b] = (ia >= 0 && ib >= 0) ? C0[ia + (long)ib * ldc] : jzero<E>();
                 }
             } else {
-                // off-diagonal block C_t[I, J] from round t-1
+                // off-diagonal block C_t[I, J] from round t-1; every input
+                // (the C tile, both rotations, the diagonal blocks) is
+                // fetched at once
                 const int sp = (t - 1) % rounds;
                 int P1, h1, P2, h2;
                 rr_locate(sp, I, nbp, P1, h1);
@@ -231,13 +233,16 @@ __global__ __launch_bounds__(BJ_NT) void bjacobi_kernel(int n, typename jelem<CP
                 pair_idx(sp, P1, s_iQ);        // rows: pair P1 of round t-1
                 pair_idx(sp, P2, s_iP);        // columns: pair P2 (s_iP rebuilt below)
                 __syncthreads();
-                const E *R2 = Rprev + (long)P2 * BJ_W * BJ_W;
+                const E *R1 = Rprev + (long)P1 * BJ_W * BJ_W, *R2 = Rprev + (long)P2 * BJ_W * BJ_W;
                 for (int e = tid; e < BJ_W * BJ_W; e += BJ_NT) {
                     const int a = e % BJ_W, b = e / BJ_W;
                     const int ia = s_iQ[a], ib = s_iP[b];
                     L0[a][b] = (ia >= 0 && ib >= 0) ? Cprev[ia + (long)ib * ldc] : jzero<E>();
                     L1[a][b] = R2[a + b * BJ_W];
+                    L0b[a][b] = R1[a + b * BJ_W];
                 }
+                const E *DI = Dbuf + (long)I * BJ_BS * BJ_BS, *DJ = Dbuf + (long)J * BJ_BS * BJ_BS;
+                const E di = DI[tid], dj = DJ[tid];   // BJ_NT == BJ_BS^2: one entry each
                 __syncthreads();
                 // Y = C_{t-1}[P1, P2] R_{t-1,P2}[:, J part]   (W x BS)
                 for (int e = tid; e < BJ_W * BJ_BS; e += BJ_NT) {
@@ -248,26 +253,16 @@ __global__ __launch_bounds__(BJ_NT) void bjacobi_kernel(int n, typename jelem<CP
                     Ys[a][j] = sum;
                 }
                 __syncthreads();
-                const E *R1 = Rprev + (long)P1 * BJ_W * BJ_W;
-                for (int e = tid; e < BJ_W * BJ_W; e += BJ_NT) {
-                    const int a = e % BJ_W, b = e / BJ_W;
-                    L1[a][b] = R1[a + b * BJ_W];
-                }
-                __syncthreads();
                 // X = R_{t-1,P1}[:, I part]^H Y   (BS x BS, one entry per thread)
                 E xv = jzero<E>();
                 const int xi = tid % BJ_BS, xj = tid / BJ_BS;
 #pragma unroll 8
-                for (int k = 0; k < BJ_W; ++k) xv = jadd(xv, jmul(jconj(L1[k][h1 * BJ_BS + xi]), Ys[k][xj]));
+                for (int k = 0; k < BJ_W; ++k) xv = jadd(xv, jmul(jconj(L0b[k][h1 * BJ_BS + xi]), Ys[k][xj]));
                 pair_idx(s, P, s_iP);
                 __syncthreads();
                 // diagonal blocks from round t-1's rotated pairs
-                const E *DI = Dbuf + (long)I * BJ_BS * BJ_BS, *DJ = Dbuf + (long)J * BJ_BS * BJ_BS;
-                for (int e = tid; e < BJ_BS * BJ_BS; e += BJ_NT) {
-                    const int a = e % BJ_BS, b = e / BJ_BS;
-                    L0[a][b] = DI[a + b * BJ_BS];
-                    L0[BJ_BS + a][BJ_BS + b] = DJ[a + b * BJ_BS];
-                }
+                L0[xi][xj] = di;
+                L0[BJ_BS + xi][BJ_BS + xj] = dj;
                 L0[xi][BJ_BS + xj] = xv;
                 L0[BJ_BS + xj][xi] = jconj(xv);
             }
