@@ -31,8 +31,8 @@ N, COUNT, M0, NE, TOL, SEED = 4096, 200, 300, 8, 1e-10, 2001
 # solve), from the rocprofv3 counter passes summarised in
 # profiles/hbm_traffic_realgen_n4096_m0300.md.  It holds only for the
 # kernel sources it was measured on: `traffic` is null when they differ.
-TRAFFIC_BYTES_PER_LAUNCH = 1.312e8
-TRAFFIC_SOURCES_SHA256 = "0567859b39c19ba955225613be571e500fee7f726d9f4f14e86a8920427b144a"
+TRAFFIC_BYTES_PER_LAUNCH = 1.438e+08
+TRAFFIC_SOURCES_SHA256 = "18d2f24c876088456b9ed162f651a83e495bcab8a2b200f6ece6db71aeba7567"
 
 
 def kernel_sources_sha256():
