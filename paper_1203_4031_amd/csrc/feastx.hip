@@ -330,12 +330,69 @@ struct Result {
 
 template <bool CPLX> using F64 = typename jelem<CPLX>::type;
 
+// C = alpha (P_0 + P_1 + ... + P_{S-1}) + beta C, partials m x n contiguous,
+// summed in index order.
 template <bool CPLX>
-static void dgemm(hipStream_t s, bool opa_h, int m, int n, int k, double alpha, const F64<CPLX> *A,
+__global__ __launch_bounds__(256) void splitk_sum_kernel(int m, long mn, int S, const F64<CPLX> *__restrict__ P,
+                                                         double alpha, double beta, F64<CPLX> *__restrict__ C,
+                                                         long ldc)
+{
+    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= mn) return;
+    const long i = e % m, j = e / m;
+    if constexpr (CPLX) {
+        double2 acc = P[e];
+        for (int q = 1; q < S; ++q) {
+            const double2 v = P[(long)q * mn + e];
+            acc.x += v.x;
+            acc.y += v.y;
+        }
+        double2 out = make_double2(alpha * acc.x, alpha * acc.y);
+        if (beta != 0.0) {
+            const double2 c = C[i + j * ldc];
+            out.x += beta * c.x;
+            out.y += beta * c.y;
+        }
+        C[i + j * ldc] = out;
+    } else {
+        double acc = P[e];
+        for (int q = 1; q < S; ++q) acc += P[(long)q * mn + e];
+        double out = alpha * acc;
+        if (beta != 0.0) out += beta * C[i + j * ldc];
+        C[i + j * ldc] = out;
+    }
+}
+
+template <bool CPLX>
+static void dgemm(Workspace &ws, hipStream_t s, bool opa_h, int m, int n, int k, double alpha, const F64<CPLX> *A,
                   long lda, const F64<CPLX> *B, long ldb, double beta, F64<CPLX> *C, long ldc)
 {
-    if (opa_h) gemm<double, CPLX, true>(s, m, n, k, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1);
-    else gemm<double, CPLX, false>(s, m, n, k, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1);
+    using E = F64<CPLX>;
+    // Few output tiles and a long K (Rayleigh-Ritz: N x M0 x N and
+    // M0 x M0 x N): split K over S partial products in workspace, summed in
+    // a fixed order, so the result does not depend on scheduling.
+    const long tiles = (long)ceil_div(m, 64) * ceil_div(n, 64);
+    int S = 1;
+    if (tiles < 512 && k >= 512) {
+        S = 16;
+        while (S > 1 && (k % S != 0 || k / S < 256 || tiles * S > 2048)) S /= 2;
+    }
+    if (S == 1) {
+        if (opa_h) gemm<double, CPLX, true>(s, m, n, k, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1);
+        else gemm<double, CPLX, false>(s, m, n, k, alpha, A, lda, 0, B, ldb, 0, beta, C, ldc, 0, 1);
+        return;
+    }
+    const int kc = k / S;
+    const long mn = (long)m * n;
+    E *P = static_cast<E *>(ws.get("splitk", sizeof(E) * (size_t)S * mn));
+    if (opa_h)   // A is stored K x M: chunk s starts at row s kc
+        gemm2<double, CPLX, true>(s, m, n, kc, 1.0, A, lda, 0, kc, B, ldb, 0, kc, 0.0, P, m, 0, mn, 1, S);
+    else         // A is stored M x K: chunk s starts at column s kc
+        gemm2<double, CPLX, false>(s, m, n, kc, 1.0, A, lda, 0, (long)kc * lda, B, ldb, 0, kc, 0.0, P, m, 0, mn, 1,
+                                   S);
+    hipLaunchKernelGGL((splitk_sum_kernel<CPLX>), dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, s, m, mn, S, P,
+                       alpha, beta, C, ldc);
+    FX_LAUNCH_CHECK();
 }
 
 static dim3 grid1(long count) { return dim3((unsigned)((count + 255) / 256)); }
@@ -609,7 +666,7 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
                                (long)n, lam, R);
             FX_LAUNCH_CHECK();
         } else if (pb.B) {
-            dgemm<CPLX>(s, false, n, m0, n, 1.0, reinterpret_cast<const E *>(pb.B), pb.ldb, X, n, 0.0, R, n);
+            dgemm<CPLX>(ws, s, false, n, m0, n, 1.0, reinterpret_cast<const E *>(pb.B), pb.ldb, X, n, 0.0, R, n);
         } else {
             hipLaunchKernelGGL((copy_block_kernel<CPLX>), grid1(cur_nm), dim3(256), 0, s, n, m0, X, (long)n, R,
                                (long)n);
@@ -680,15 +737,15 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
         }
 
         // ---- Rayleigh-Ritz
-        dgemm<CPLX>(s, false, n, m0, n, 1.0, reinterpret_cast<const E *>(pb.A), pb.lda, Q, n, 0.0, AQ, n);
-        if (pb.B) dgemm<CPLX>(s, false, n, m0, n, 1.0, reinterpret_cast<const E *>(pb.B), pb.ldb, Q, n, 0.0, BQ, n);
+        dgemm<CPLX>(ws, s, false, n, m0, n, 1.0, reinterpret_cast<const E *>(pb.A), pb.lda, Q, n, 0.0, AQ, n);
+        if (pb.B) dgemm<CPLX>(ws, s, false, n, m0, n, 1.0, reinterpret_cast<const E *>(pb.B), pb.ldb, Q, n, 0.0, BQ, n);
         else {
             hipLaunchKernelGGL((copy_block_kernel<CPLX>), grid1(cur_nm), dim3(256), 0, s, n, m0, Q, (long)n, BQ,
                                (long)n);
             FX_LAUNCH_CHECK();
         }
-        dgemm<CPLX>(s, true, m0, m0, n, 1.0, Q, n, AQ, n, 0.0, Aq, m0);
-        dgemm<CPLX>(s, true, m0, m0, n, 1.0, Q, n, BQ, n, 0.0, Bq, m0);
+        dgemm<CPLX>(ws, s, true, m0, m0, n, 1.0, Q, n, AQ, n, 0.0, Aq, m0);
+        dgemm<CPLX>(ws, s, true, m0, m0, n, 1.0, Q, n, BQ, n, 0.0, Bq, m0);
         hipLaunchKernelGGL((hermitian_part_kernel<CPLX>), grid1((long)m0 * m0), dim3(256), 0, s, m0, Aq, (long)m0);
         hipLaunchKernelGGL((hermitian_part_kernel<CPLX>), grid1((long)m0 * m0), dim3(256), 0, s, m0, Bq, (long)m0);
         FX_LAUNCH_CHECK();
@@ -701,19 +758,19 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
             keep = bortho_cholesky<CPLX>(ws, s, m0, Bq, Tm);
         else
             keep = bortho_eigen<CPLX>(ws, s, m0, Bq, Wb, beta, Tm, st);
-        dgemm<CPLX>(s, false, m0, keep, m0, 1.0, Aq, m0, Tm, m0, 0.0, Tmp, m0);
-        dgemm<CPLX>(s, true, keep, keep, m0, 1.0, Tm, m0, Tmp, m0, 0.0, Cr, keep);
+        dgemm<CPLX>(ws, s, false, m0, keep, m0, 1.0, Aq, m0, Tm, m0, 0.0, Tmp, m0);
+        dgemm<CPLX>(ws, s, true, keep, keep, m0, 1.0, Tm, m0, Tmp, m0, 0.0, Cr, keep);
         hipLaunchKernelGGL((hermitian_part_kernel<CPLX>), grid1((long)keep * keep), dim3(256), 0, s, keep, Cr,
                            (long)keep);
         FX_LAUNCH_CHECK();
         device_eigh<CPLX>(ws, s, keep, Cr, Vc, lam, st);
-        dgemm<CPLX>(s, false, m0, keep, keep, 1.0, Tm, m0, Vc, keep, 0.0, Phi, m0);
+        dgemm<CPLX>(ws, s, false, m0, keep, keep, 1.0, Tm, m0, Vc, keep, 0.0, Phi, m0);
         tm.mark(&st.t_reduced);
 
         // ---- Ritz vectors, A X, B X, residuals
-        dgemm<CPLX>(s, false, n, keep, m0, 1.0, Q, n, Phi, m0, 0.0, X, n);
-        dgemm<CPLX>(s, false, n, keep, m0, 1.0, AQ, n, Phi, m0, 0.0, AX, n);
-        dgemm<CPLX>(s, false, n, keep, m0, 1.0, BQ, n, Phi, m0, 0.0, BX, n);
+        dgemm<CPLX>(ws, s, false, n, keep, m0, 1.0, Q, n, Phi, m0, 0.0, X, n);
+        dgemm<CPLX>(ws, s, false, n, keep, m0, 1.0, AQ, n, Phi, m0, 0.0, AX, n);
+        dgemm<CPLX>(ws, s, false, n, keep, m0, 1.0, BQ, n, Phi, m0, 0.0, BX, n);
         hipLaunchKernelGGL((resid_norm_kernel<CPLX>), dim3(keep), dim3(256), 0, s, n, AX, BX, (long)n, lam, alpha,
                            res);
         FX_LAUNCH_CHECK();
