@@ -181,12 +181,13 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, MINB) void gemm_kernel(
 }
 
 // Tile shapes per element type.  MINB workgroups per CU bound the register
-// use so that one workgroup's loads overlap another's matrix-core work
-// (measured: the complex64 product went from ~52 to ~71 TF/s on the LU
-// update and from ~58 to ~79 TF/s on the solve update at N = 4096).
+// use so that one workgroup's loads overlap another's matrix-core work.
+// Complex64, measured at N = 4096 over 8 matrices (depth-64 LU update /
+// 300-column solve update): 64x64 at four per CU 94 / 81 TF/s, 128x64 at
+// three 89 / 81, 128x128 at two 91 / 54, 256x64 at one 79 / 62.
 template <typename T, bool CPLX> struct gemm_cfg;
 template <> struct gemm_cfg<float, true> {
-    static constexpr int BM = 128, BN = 64, BK = 16, WM = 64, WN = 32, MINB = 3;
+    static constexpr int BM = 64, BN = 64, BK = 16, WM = 32, WN = 32, MINB = 4;
 };
 template <> struct gemm_cfg<double, true> {
     static constexpr int BM = 64, BN = 64, BK = 16, WM = 32, WN = 32, MINB = 2;
