@@ -59,6 +59,12 @@ struct Workspace {
     // the trailing update to drain the device.  Created on first use, only
     // for workspaces that ask for it (want_split).
     bool want_split = false;
+    // Look-ahead on a second stream.  Only the single-solve workspace uses
+    // it: an executor slot keeps all its work on one in-order stream,
+    // because with many slots the streams outnumber the hardware queues and
+    // a cross-stream wait (a barrier packet that blocks its queue) of one
+    // slot could sit in front of the work another slot's wait needs.
+    bool lookahead = false;
     int fres = 0;
     hipStream_t fmain = nullptr, fside = nullptr;
     hipEvent_t ev_c = nullptr, ev_d = nullptr;
@@ -637,7 +643,7 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
             shift_build<T>(s, CPLX, n, pb.A, pb.lda, pb.B, pb.ldb, dz, ne, F, ldf, sF);
             tm.mark(&st.t_shift);
             FX_CHECK(hipMemsetAsync(dinfo, 0, sizeof(int) * ne, s));
-            if (!g_no_lookahead && ws.split(ne)) {
+            if (!g_no_lookahead && ws.lookahead && ws.split(ne)) {
                 FX_CHECK(hipEventRecord(ws.ev_c, s));
                 FX_CHECK(hipStreamWaitEvent(ws.fmain, ws.ev_c, 0));
                 getrf_batched<T>(ws.fmain, ws.fside, ws.ev_a, ws.ev_b, n, F, ldf, sF, ipiv, perm, n, swapmap,
@@ -645,8 +651,8 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
                 FX_CHECK(hipEventRecord(ws.ev_d, ws.fmain));
                 FX_CHECK(hipStreamWaitEvent(s, ws.ev_d, 0));
             } else {
-                getrf_batched<T>(s, g_no_lookahead ? nullptr : ws.side, ws.ev_a, ws.ev_b, n, F, ldf, sF, ipiv,
-                                 perm, n, swapmap, dinfo, ne);
+                getrf_batched<T>(s, (g_no_lookahead || !ws.lookahead) ? nullptr : ws.side, ws.ev_a, ws.ev_b, n, F,
+                                 ldf, sF, ipiv, perm, n, swapmap, dinfo, ne);
             }
             solve_inverses<T>(s, n, F, ldf, sF, L64, U64, sI64, Linv, Uinv, sInv, Itmp, sItmp, ne);
             build_w<T>(s, n, F, ldf, sF, Linv, Uinv, sInv, Wsv, ne);
@@ -1274,6 +1280,7 @@ static int solve_single(bool cplx, int device, int N, const void *A, int lda, co
     fx::SolveOut so;
     std::lock_guard<std::mutex> lk(fx::g_mu);
     fx::g_ws.want_split = true;
+    fx::g_ws.lookahead = true;
     fx::solve_in(fx::g_ws, o, a, so);
     fx::g_stats = so.st;
     if (so.info == 0 || so.info == 1 || so.info == 2 || so.info == 3 || so.info == 4) {
