@@ -422,7 +422,8 @@ static void device_eigh(Workspace &ws, hipStream_t s, int m, F64<CPLX> *C, F64<C
     // workgroup, few enough to keep grid barriers cheap
     int G = std::max(npairs + 1, std::min(npairs + (nitems + 1) / 2, 96));
     G = std::min(G, ws.jac_max_blocks);
-    double *partial = static_cast<double *>(ws.get("jac_partial", sizeof(double) * 2 * 1024));
+    // two halves of per-workgroup off-norm partials (by sweep parity), then the Frobenius partials
+    double *partial = static_cast<double *>(ws.get("jac_partial", sizeof(double) * 3 * (size_t)G));
     int *status = static_cast<int *>(ws.get("jac_status", sizeof(int) * 2));
     double *hist = static_cast<double *>(ws.get("jac_hist", sizeof(double) * 64));
     int *rank = static_cast<int *>(ws.get("jac_rank", sizeof(int) * m));

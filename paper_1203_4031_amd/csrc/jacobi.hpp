@@ -64,7 +64,12 @@ __device__ inline void rr_pair(int s, int i, int p, int &a, int &b)
 // R; only the tiles P <= Q are formed (C is Hermitian), the others are
 // written as their mirror.  The off-diagonal norm is summed from
 // per-workgroup partials in a fixed order, so every workgroup takes the
-// same stopping decision.
+// same stopping decision.  The partials alternate between two halves by
+// sweep parity: with a single round per sweep (m <= 2 BS) a workgroup
+// writes the next sweep's partial before the next grid barrier, and a
+// shared half could change under a slower workgroup still summing the
+// current one, which would then take a different decision and leave the
+// others waiting at a barrier it never reaches.
 //
 // Rotation for a pair (a < b), c_ab = |c_ab| e^{i phi}, d = c_bb - c_aa:
 //   t = sign(d) 2|c_ab| / (|d| + sqrt(d^2 + 4 |c_ab|^2))  (tan of the angle),
@@ -197,10 +202,10 @@ __global__ __launch_bounds__(BJ_NT) void bjacobi_kernel(int n, typename jelem<CP
         acc += jabs2(C0[i + j * ldc]);
     }
     double bs = block_reduce(acc);
-    if (tid == 0) partial[G + bid] = bs;
+    if (tid == 0) partial[2 * G + bid] = bs;
     gs.sync();
     double fro2 = 0.0;
-    for (int q = 0; q < G; ++q) fro2 += partial[G + q];
+    for (int q = 0; q < G; ++q) fro2 += partial[2 * G + q];
     const double fro = sqrt(fro2);
 
     int sweep = 0, conv = 0, t = 0;
@@ -438,13 +443,13 @@ __global__ __launch_bounds__(BJ_NT) void bjacobi_kernel(int n, typename jelem<CP
         }
         if (lastp) {
             const double b2 = block_reduce(offacc);
-            if (tid == 0) partial[bid] = b2;
+            if (tid == 0) partial[(sweep & 1) * G + bid] = b2;
         }
         gs.sync();
         if (lastp) {
             // C_t is the matrix after a whole sweep
             double off2 = 0.0;
-            for (int q = 0; q < G; ++q) off2 += partial[q];
+            for (int q = 0; q < G; ++q) off2 += partial[(sweep & 1) * G + q];
             const double off = sqrt(off2);
             if (gtid == 0 && sweep < 64) hist[sweep] = fro > 0.0 ? off / fro : 0.0;
             ++sweep;
