@@ -115,7 +115,7 @@ int feast_solve_z_dev(int N, const feast_z *dA, int lda, const feast_z *dB, int 
  * level of parallelism, independent search intervals / problems).  Each job
  * carries its problem and receives its outputs; `opts` is shared (opts.x0 =
  * 1: every job's X holds its start subspace).  device = 1: A, B, X are device
- * arrays; 0: host arrays.  Up to `concurrency` problems (0: 4, at most 16)
+ * arrays; 0: host arrays.  Up to `concurrency` problems (0: 4, at most 8)
  * run at once, each on its own stream and device workspace, so their kernels
  * overlap on the GPU; every job runs the same kernels as a single solve and
  * gets the result it would get alone.  Returns 0 when every job ran (its
@@ -150,7 +150,7 @@ int feast_solve_batched_z(int njobs, feast_job *jobs, const feast_opts *opts, in
  * must stay valid until the request completes. */
 typedef struct feast_server feast_server;
 typedef struct {
-    int slots;              /* concurrent requests on the device (0: 4, at most 16) */
+    int slots;              /* concurrent requests on the device (0: 4, at most 8) */
     double hbm_budget_gb;   /* admission limit (0: 64 GB) */
 } feast_server_cfg;
 typedef struct {
