@@ -168,7 +168,6 @@ __global__ __launch_bounds__(NT) void lu_panel_kernel(int n, cplx<T> *__restrict
                                                       int *__restrict__ info_all)
 {
     using V = cplx<T>;
-    static_assert(IB <= NT / 64, "one wave per sub-block column in the U-row solve");
     static_assert(NB <= 32, "move composition tracks at most 64 rows");
     V *a = Fall + blockIdx.x * sF;
     int *ipiv = ipiv_all + blockIdx.x * sPiv;
@@ -197,15 +196,15 @@ __global__ __launch_bounds__(NT) void lu_panel_kernel(int n, cplx<T> *__restrict
         const int w = min(IB, nbw - jb);
 
         // (a) U rows k..c0-1 of this sub-block: L11 (jb x jb, unit lower)
-        //     solve, one wave per column, lane i holding row k + i
+        //     solve, one wave per column (waves take columns in turn), lane i
+        //     holding row k + i
         if (jb > 0) {
             for (int e = tid; e < jb * jb; e += NT) {
                 const int i = e % jb, l = e / jb;
                 Lsh[i][l] = a[(k + i) + (long)(k + l) * ldf];
             }
             __syncthreads();
-            if (wid < IB) {
-                const int c = wid;
+            for (int c = wid; c < IB; c += NW) {
                 V x = (c < w && lane < jb) ? a[(k + lane) + (long)(c0 + c) * ldf] : cmake<V>(0, 0);
                 for (int l = 0; l + 1 < jb; ++l) {
                     V xl;
@@ -522,20 +521,22 @@ __global__ __launch_bounds__(256) void lu_finish_kernel(int n, const cplx<T> *__
 
 constexpr int LU_NB = 32;
 
-
-
-template <typename T> struct panel_cfg;
 // Register budget: R rows x IB columns of complex values per thread.  Rows
-// per thread grow with n; the sub-block narrows so that R * IB stays <= 64
-// (c64) / 32 (c128) complex values.
+// per thread grow with n; the sub-block is as wide as the registers allow
+// without spilling (R * IB <= 64 complex values), since every sub-block costs
+// global round trips (L11, the left-looking reloads, the in-panel moves).
+// Measured per 32-column panel, batch 8: c64 4096 rows 224 -> 194 us going
+// from IB 4 to 8; c128 4096 rows 370 -> 296 us (IB 2 -> 4), 2048 rows
+// 192 -> 168 us and 1024 rows 133 -> 118 us (IB 4 -> 8).  Wider sub-blocks
+// (16, 32) spill and run several times slower.
 template <typename T> struct panel_cfg;
 template <> struct panel_cfg<float> {
     static constexpr int NT = 512;
-    static constexpr int ib(int R) { return R <= 4 ? 8 : 4; }
+    static constexpr int ib(int R) { return R <= 8 ? 8 : 4; }
 };
 template <> struct panel_cfg<double> {
     static constexpr int NT = 512;
-    static constexpr int ib(int R) { return R <= 4 ? 4 : 2; }
+    static constexpr int ib(int R) { return R == 1 ? 4 : (R <= 4 ? 8 : (R <= 8 ? 4 : 2)); }
 };
 
 template <typename T, int R>
