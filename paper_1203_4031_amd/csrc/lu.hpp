@@ -417,7 +417,10 @@ __global__ __launch_bounds__(NT) void lu_panel_kernel(int n, cplx<T> *__restrict
 // columns outside it -- the concatenation of [c0, c1) and [c2, c3) -- (mode
 // bit 0), and U12 = L11^{-1} A12 for those of them right of the panel (mode
 // bit 1).  Each block owns 64 columns of that set; moved values are staged
-// through LDS so that all reads happen before any write.
+// through LDS so that all reads happen before any write.  The moves of one
+// column go to consecutive lanes: about half of the moved rows are the
+// panel's top rows, which are contiguous in a column, so a wave's access
+// covers a few cache lines for them instead of one line per element.
 template <typename T, int NB>
 __global__ __launch_bounds__(256) void lu_swap_trsm_kernel(int n, cplx<T> *__restrict__ Fall, long ldf,
                                                            long sF, int k, int nbw, int c0, int c1, int c2,
@@ -428,7 +431,7 @@ __global__ __launch_bounds__(256) void lu_swap_trsm_kernel(int n, cplx<T> *__res
     V *a = Fall + blockIdx.y * sF;
     const int *swapmap = swapmap_all + blockIdx.y * (1 + 4 * NB);
     const int tid = threadIdx.x;
-    __shared__ V stage[2 * NB][CB];
+    __shared__ V stage[2 * NB][CB + 1];
     __shared__ V Lsh[NB][NB + 1];
     __shared__ int dst[2 * NB], src[2 * NB];
 
@@ -451,13 +454,13 @@ __global__ __launch_bounds__(256) void lu_swap_trsm_kernel(int n, cplx<T> *__res
         }
     __syncthreads();
     for (int e = tid; e < nm * CB; e += 256) {
-        const int c = e % CB, q = e / CB;
+        const int q = e % nm, c = e / nm;
         const int oc = colbase + c;
         if (oc < ncols) stage[q][c] = a[src[q] + (long)col_of(oc) * ldf];
     }
     __syncthreads();
     for (int e = tid; e < nm * CB; e += 256) {
-        const int c = e % CB, q = e / CB;
+        const int q = e % nm, c = e / nm;
         const int oc = colbase + c;
         if (oc < ncols) a[dst[q] + (long)col_of(oc) * ldf] = stage[q][c];
     }
@@ -479,7 +482,7 @@ __global__ __launch_bounds__(256) void lu_swap_trsm_kernel(int n, cplx<T> *__res
             const int i = g + 4 * j;
             xr[j] = (colok && i < nbw) ? pc[i] : cmake<V>(0, 0);
         }
-        V(*xrow)[CB] = stage;   // free again: the moves are done
+        V(*xrow)[CB + 1] = stage;   // free again: the moves are done
 #pragma unroll
         for (int l = 0; l < NB - 1; ++l) {
             if (l + 1 >= nbw) break;   // uniform
