@@ -416,11 +416,38 @@ __global__ __launch_bounds__(NT) void lu_panel_kernel(int n, cplx<T> *__restrict
 // Row interchanges of one panel (columns k..k+nbw-1) applied to a set of
 // columns outside it -- the concatenation of [c0, c1) and [c2, c3) -- (mode
 // bit 0), and U12 = L11^{-1} A12 for those of them right of the panel (mode
-// bit 1).  Each block owns 64 columns of that set; moved values are staged
-// through LDS so that all reads happen before any write.  The moves of one
-// column go to consecutive lanes: about half of the moved rows are the
-// panel's top rows, which are contiguous in a column, so a wave's access
-// covers a few cache lines for them instead of one line per element.
+// bit 1).  Each block owns 64 columns of that set.  The kernel is latency
+// bound, so it is laid out for few dependent steps:
+//   1. the move list, L11 and the top nbw rows of the solve columns are
+//      fetched at once;
+//   2. the moved rows are staged through LDS (all reads before any write;
+//      a column's moves sit on consecutive lanes, so the panel's top rows,
+//      contiguous in a column, share cache lines);
+//   3. moved rows are stored, except the top rows of solve columns, which
+//      the solve takes from the stage and writes itself;
+//   4. the solve: column c's rows g, g + 4, ... are held by lane g of a
+//      quad, so the pivot row of step l is a DPP broadcast within the quad
+//      and the substitution needs no barrier.
+template <int CTRL> __device__ inline float2 dpp_v(float2 v)
+{
+    return make_float2(dpp_mov<CTRL>(v.x), dpp_mov<CTRL>(v.y));
+}
+template <int CTRL> __device__ inline double2 dpp_v(double2 v)
+{
+    return make_double2(dpp_mov<CTRL>(v.x), dpp_mov<CTRL>(v.y));
+}
+// v of lane g of each quad, for every lane of the quad (quad_perm [g,g,g,g]);
+// g is a constant once the caller's loop is unrolled
+template <typename V> __device__ inline V quad_bcast(V v, int g)
+{
+    switch (g) {
+    case 0: return dpp_v<0x00>(v);
+    case 1: return dpp_v<0x55>(v);
+    case 2: return dpp_v<0xAA>(v);
+    default: return dpp_v<0xFF>(v);
+    }
+}
+
 template <typename T, int NB>
 __global__ __launch_bounds__(256) void lu_swap_trsm_kernel(int n, cplx<T> *__restrict__ Fall, long ldf,
                                                            long sF, int k, int nbw, int c0, int c1, int c2,
@@ -428,18 +455,16 @@ __global__ __launch_bounds__(256) void lu_swap_trsm_kernel(int n, cplx<T> *__res
 {
     using V = cplx<T>;
     constexpr int CB = 64;
+    static_assert(NB % 4 == 0 && NB <= 32, "rows of the solve in 4 groups; at most 2 NB moves");
     V *a = Fall + blockIdx.y * sF;
     const int *swapmap = swapmap_all + blockIdx.y * (1 + 4 * NB);
     const int tid = threadIdx.x;
     __shared__ V stage[2 * NB][CB + 1];
     __shared__ V Lsh[NB][NB + 1];
     __shared__ int dst[2 * NB], src[2 * NB];
+    __shared__ int top_q[NB];   // top row k + i is written by move top_q[i] (-1: none)
+    __shared__ int s_nm;
 
-    const int nm = (mode & 1) ? swapmap[0] : 0;
-    for (int e = tid; e < nm; e += 256) {
-        dst[e] = swapmap[1 + e];
-        src[e] = swapmap[1 + 2 * NB + e];
-    }
     const int w1 = c1 - c0, ncols = w1 + (c3 - c2);
     auto col_of = [&](int oc) { return oc < w1 ? c0 + oc : c2 + (oc - w1); };
     const int colbase = blockIdx.x * CB;
@@ -447,53 +472,80 @@ __global__ __launch_bounds__(256) void lu_swap_trsm_kernel(int n, cplx<T> *__res
     if (mode & 2)
         for (int c = 0; c < CB; ++c)
             if (colbase + c < ncols && col_of(colbase + c) >= k + nbw) right = true;
-    if (right)
-        for (int e = tid; e < nbw * nbw; e += 256) {
-            const int i = e % nbw, l = e / nbw;
-            Lsh[i][l] = a[(k + i) + (long)(k + l) * ldf];
+
+    // solve layout: column c = 16 wave + lane / 4, rows g + 4 j (g = lane mod 4)
+    const int sc = (tid >> 6) * 16 + ((tid & 63) >> 2), g = tid & 3;
+    const int soc = colbase + sc;
+    const bool colok = right && soc < ncols && col_of(soc) >= k + nbw;
+    V *pc = a + (long)(colok ? col_of(soc) : 0) * ldf + k;
+
+    // 1. move list, L11, the solve columns' top rows
+    if (mode & 1) {
+        for (int e = tid; e < 1 + 4 * NB; e += 256) {
+            const int v = swapmap[e];
+            if (e == 0) s_nm = v;
+            else if (e <= 2 * NB) dst[e - 1] = v;
+            else src[e - 1 - 2 * NB] = v;
         }
+    } else if (tid == 0) {
+        s_nm = 0;
+    }
+    if (tid < NB) top_q[tid] = -1;
+    // L11 strictly below the diagonal; zeros elsewhere (and past nbw), so
+    // that the substitution below needs no per-row guard
+    if (right)
+        for (int e = tid; e < NB * NB; e += 256) {
+            const int i = e % NB, l = e / NB;
+            Lsh[i][l] = (i > l && i < nbw) ? a[(k + i) + (long)(k + l) * ldf] : cmake<V>(0, 0);
+        }
+    V xr[NB / 4];
+#pragma unroll
+    for (int j = 0; j < NB / 4; ++j) {
+        const int i = g + 4 * j;
+        xr[j] = (colok && i < nbw) ? pc[i] : cmake<V>(0, 0);
+    }
     __syncthreads();
+    const int nm = s_nm;
+
+    // 2. stage the moved rows
+    if (right && tid < nm) {
+        const int d = dst[tid] - k;
+        if (d >= 0 && d < nbw) top_q[d] = tid;
+    }
     for (int e = tid; e < nm * CB; e += 256) {
         const int q = e % nm, c = e / nm;
         const int oc = colbase + c;
         if (oc < ncols) stage[q][c] = a[src[q] + (long)col_of(oc) * ldf];
     }
     __syncthreads();
+
+    // 3. store the moves (the solve writes the top rows of its columns)
     for (int e = tid; e < nm * CB; e += 256) {
         const int q = e % nm, c = e / nm;
         const int oc = colbase + c;
-        if (oc < ncols) a[dst[q] + (long)col_of(oc) * ldf] = stage[q][c];
+        if (oc < ncols) {
+            const int col = col_of(oc), d = dst[q];
+            const bool solved = (mode & 2) && col >= k + nbw && d >= k && d < k + nbw;
+            if (!solved) a[d + (long)col * ldf] = stage[q][c];
+        }
     }
-    __syncthreads();
+
+    // 4. U12 = L11^{-1} A12, column-oriented forward substitution
     if (right) {
-        // U12 = L11^{-1} A12 by column-oriented substitution shared by the
-        // whole block: thread (c, g) = (tid mod 64, tid / 64) keeps rows
-        // g, g + 4, ... of column c in registers; at step l the wave that
-        // owns row l publishes it (two alternating LDS rows), so a step is
-        // one barrier and NB/4 independent multiply-adds per thread
-        static_assert(256 / CB == 4 && NB % 4 == 0, "4 row groups of 64 columns");
-        const int c = tid % CB, g = tid / CB;
-        const int oc = colbase + c;
-        const bool colok = oc < ncols && col_of(oc) >= k + nbw;
-        V *pc = a + (long)(colok ? col_of(oc) : 0) * ldf + k;
-        V xr[NB / 4];
 #pragma unroll
         for (int j = 0; j < NB / 4; ++j) {
             const int i = g + 4 * j;
-            xr[j] = (colok && i < nbw) ? pc[i] : cmake<V>(0, 0);
+            if (colok && i < nbw) {
+                const int q = top_q[i];
+                if (q >= 0) xr[j] = stage[q][sc];
+            }
         }
-        V(*xrow)[CB + 1] = stage;   // free again: the moves are done
 #pragma unroll
         for (int l = 0; l < NB - 1; ++l) {
             if (l + 1 >= nbw) break;   // uniform
-            if (g == (l & 3)) xrow[l & 1][c] = xr[l >> 2];
-            __syncthreads();
-            const V xl = xrow[l & 1][c];
+            const V xl = quad_bcast(xr[l >> 2], l & 3);
 #pragma unroll
-            for (int j = 0; j < NB / 4; ++j) {
-                const int i = g + 4 * j;
-                if (i > l && i < nbw) xr[j] = csub(xr[j], cmul(Lsh[i][l], xl));
-            }
+            for (int j = 0; j < NB / 4; ++j) xr[j] = csub(xr[j], cmul(Lsh[g + 4 * j][l], xl));
         }
         if (colok)
 #pragma unroll
