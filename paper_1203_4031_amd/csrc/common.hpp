@@ -111,19 +111,25 @@ struct grid_sync {
     }
     __device__ void sync()
     {
-        // __syncthreads() makes every wave's stores complete before thread 0
-        // publishes its arrival with release semantics at agent scope; the
-        // acquire on the generation word makes the other blocks' data visible.
+        // __syncthreads() orders every wave's stores before thread 0's
+        // arrival, a release at agent scope.  The last arrival reads the end
+        // of the release sequence on `count`, acquires (so it has every
+        // block's data) and releases the generation word; the others poll it
+        // with relaxed loads and acquire once it has moved.  Polling with
+        // acquire loads would invalidate the XCD's L2 on every poll and cost
+        // the other workgroups there their cached lines.
         __syncthreads();
         if (threadIdx.x == 0) {
-            unsigned g = local_gen;
-            unsigned prev = __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned g = local_gen;
+            const unsigned prev = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             if (prev == nblocks - 1) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             } else {
-                while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g)
+                while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g)
                     __builtin_amdgcn_s_sleep(1);
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
         }
         local_gen += 1;
