@@ -211,7 +211,7 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "feast_loops": loops,
         "stage_ms_last_solve": stage_ms,
-        "roofline": {"kernel": "gemm_kernel<float, true, false, 64, 64, 16, 32, 32, 4>: complex64 "
+        "roofline": {"kernel": "gemm_kernel<float, true, false, 64, 64, 16, 32, 32, 4, true, true>: complex64 "
                                "matrix product on the FP32 matrix cores (LU trailing updates and "
                                "triangular-solve updates), every launch of the timed solves",
                      "bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA,

@@ -30,7 +30,15 @@ template <typename E> __device__ inline E conj_elem(E v) { return v; }
 template <> __device__ inline float2 conj_elem<float2>(float2 v) { return make_float2(v.x, -v.y); }
 template <> __device__ inline double2 conj_elem<double2>(double2 v) { return make_double2(v.x, -v.y); }
 
-template <typename T, bool CPLX, bool OPA_H, int BM, int BN, int BK, int WM, int WN, int MINB>
+// C = alpha op(A) B + beta C for one tile of BM x BN per workgroup.
+// DB: the LDS tiles are double-buffered (one barrier per BK step instead of
+// two).  G3: complex products in the three-multiplication form -- with
+// T1 = sum Br Ar, T2 = sum Bi Ai, T3 = sum (Br + Bi)(Ar + Ai),
+// re = T1 - T2 and im = T3 - T1 - T2 -- three real matrix-core products
+// per complex step instead of four.  Its rounding error is bounded by a
+// small multiple of eps |A| |B| like the four-product form, but it is not
+// the same per component (the imaginary part carries the error of T1 and T2).
+template <typename T, bool CPLX, bool OPA_H, int BM, int BN, int BK, int WM, int WN, int MINB, bool DB, bool G3_>
 __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, MINB) void gemm_kernel(
     int m_in, int n, int k, T alpha, const typename elem<T, CPLX>::type *__restrict__ A, long lda,
     long sA, const typename elem<T, CPLX>::type *__restrict__ B, long ldb, long sB, T beta,
@@ -47,8 +55,9 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, MINB) void gemm_kernel(
     static_assert(BK % 4 == 0, "BK must be a multiple of 4");
     static_assert((BM * BK) % NT == 0 && (BN * BK) % NT == 0, "tile not divisible");
 
-    __shared__ E As[BK][BM + PAD];
-    __shared__ E Bs[BK][BN + PAD];
+    constexpr bool G3 = CPLX && G3_;
+    __shared__ E As_[DB ? 2 : 1][BK][BM + PAD];
+    __shared__ E Bs_[DB ? 2 : 1][BK][BN + PAD];
 
     // rows of this batch entry: m_in + y * dm (the grid covers the largest)
     const int tiles_m = (m_in + (dm > 0 ? (int)(gridDim.y - 1) * dm : 0) + BM - 1) / BM;
@@ -69,6 +78,7 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, MINB) void gemm_kernel(
     // plain store of alpha * acc; the loads are issued before the k loop
     acc_t acc_re[FN][FM];
     acc_t acc_im[CPLX ? FN : 1][CPLX ? FM : 1];
+    acc_t acc_t2[G3 ? FN : 1][G3 ? FM : 1];
     const T cscale = (beta != T(0)) ? beta / alpha : T(0);
 #pragma unroll
     for (int a = 0; a < FN; ++a)
@@ -80,7 +90,11 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, MINB) void gemm_kernel(
                 const int gi = m0 + wm * WM + b * 16 + (lane & 15);
                 E c = zero_elem<E>();
                 if (cscale != T(0) && gi < m && gj < n) c = C[gi + (long)gj * ldc];
-                if constexpr (CPLX) {
+                if constexpr (G3) {
+                    acc_re[a][b][r] = cscale * c.x;
+                    acc_im[a][b][r] = cscale * (c.x + c.y);
+                    acc_t2[a][b][r] = T(0);
+                } else if constexpr (CPLX) {
                     acc_re[a][b][r] = cscale * c.x;
                     acc_im[a][b][r] = cscale * c.y;
                 } else {
@@ -113,38 +127,37 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, MINB) void gemm_kernel(
             rb[u] = (gj < n && gk < k) ? B[gk + (long)gj * ldb] : zero_elem<E>();
         }
     };
-    auto store_tiles = [&]() {
+    auto store_tiles = [&](int buf) {
 #pragma unroll
         for (int u = 0; u < LA; ++u) {
             const int e = tid + u * NT;
-            if constexpr (!OPA_H) As[e / BM][e % BM] = ra[u];
-            else As[e % BK][e / BK] = ra[u];
+            if constexpr (!OPA_H) As_[buf][e / BM][e % BM] = ra[u];
+            else As_[buf][e % BK][e / BK] = ra[u];
         }
 #pragma unroll
         for (int u = 0; u < LB; ++u) {
             const int e = tid + u * NT;
-            Bs[e % BK][e / BK] = rb[u];
+            Bs_[buf][e % BK][e / BK] = rb[u];
         }
     };
-
-    if (k > 0) load_tiles(0);
-    for (int k0 = 0; k0 < k; k0 += BK) {
-        store_tiles();
-        __syncthreads();
-        if (k0 + BK < k) load_tiles(k0 + BK);   // in flight during the MFMAs below
+    auto compute = [&](int buf) {
 #pragma unroll
         for (int k4 = 0; k4 < BK / 4; ++k4) {
             const int kr = k4 * 4 + (lane >> 4);
             E af[FM], bf[FN];
 #pragma unroll
-            for (int b = 0; b < FM; ++b) af[b] = As[kr][wm * WM + b * 16 + (lane & 15)];
+            for (int b = 0; b < FM; ++b) af[b] = As_[buf][kr][wm * WM + b * 16 + (lane & 15)];
 #pragma unroll
-            for (int a = 0; a < FN; ++a) bf[a] = Bs[kr][wn * WN + a * 16 + (lane & 15)];
+            for (int a = 0; a < FN; ++a) bf[a] = Bs_[buf][kr][wn * WN + a * 16 + (lane & 15)];
 #pragma unroll
             for (int a = 0; a < FN; ++a)
 #pragma unroll
                 for (int b = 0; b < FM; ++b) {
-                    if constexpr (CPLX) {
+                    if constexpr (G3) {
+                        acc_re[a][b] = MF::step(bf[a].x, af[b].x, acc_re[a][b]);
+                        acc_t2[a][b] = MF::step(bf[a].y, af[b].y, acc_t2[a][b]);
+                        acc_im[a][b] = MF::step(bf[a].x + bf[a].y, af[b].x + af[b].y, acc_im[a][b]);
+                    } else if constexpr (CPLX) {
                         acc_re[a][b] = MF::step(bf[a].x, af[b].x, acc_re[a][b]);
                         acc_re[a][b] = MF::step(-bf[a].y, af[b].y, acc_re[a][b]);
                         acc_im[a][b] = MF::step(bf[a].y, af[b].x, acc_im[a][b]);
@@ -154,7 +167,32 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, MINB) void gemm_kernel(
                     }
                 }
         }
+    };
+
+    if constexpr (DB) {
+        if (k > 0) {
+            load_tiles(0);
+            store_tiles(0);
+        }
         __syncthreads();
+        int buf = 0;
+        for (int k0 = 0; k0 < k; k0 += BK) {
+            const bool more = k0 + BK < k;
+            if (more) load_tiles(k0 + BK);
+            compute(buf);
+            if (more) store_tiles(buf ^ 1);
+            __syncthreads();
+            buf ^= 1;
+        }
+    } else {
+        if (k > 0) load_tiles(0);
+        for (int k0 = 0; k0 < k; k0 += BK) {
+            store_tiles(0);
+            __syncthreads();
+            if (k0 + BK < k) load_tiles(k0 + BK);
+            compute(0);
+            __syncthreads();
+        }
     }
 
     // ---- epilogue: acc'[row j][col i] of the transposed tile; 16 lanes
@@ -169,7 +207,10 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, MINB) void gemm_kernel(
                 const int gi = m0 + wm * WM + b * 16 + (lane & 15);
                 if (gi < m && gj < n) {
                     E o;
-                    if constexpr (CPLX) {
+                    if constexpr (G3) {
+                        o.x = alpha * (acc_re[a][b][r] - acc_t2[a][b][r]);
+                        o.y = alpha * (acc_im[a][b][r] - acc_re[a][b][r] - acc_t2[a][b][r]);
+                    } else if constexpr (CPLX) {
                         o.x = alpha * acc_re[a][b][r];
                         o.y = alpha * acc_im[a][b][r];
                     } else {
@@ -183,20 +224,28 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, MINB) void gemm_kernel(
 // Tile shapes per element type.  MINB workgroups per CU bound the register
 // use so that one workgroup's loads overlap another's matrix-core work.
 // Complex64, measured at N = 4096 over 8 matrices (depth-64 LU update /
-// 300-column solve update): 64x64 at four per CU 94 / 81 TF/s, 128x64 at
-// three 89 / 81, 128x128 at two 91 / 54, 256x64 at one 79 / 62.
+// 300-column solve update, zero data): 64x64 at four per CU 94 / 81 TF/s,
+// 128x64 at three 89 / 81, 128x128 at two 91 / 54, 256x64 at one 79 / 62.
+// On random data the 64x64 four-product kernel gives 74-90 TF/s on the
+// depth-64 updates and 64-77 on the solve updates; double-buffered with the
+// three-product form, 96-109 and 81-90 (flops counted as 8 per complex
+// multiply-add).
 template <typename T, bool CPLX> struct gemm_cfg;
 template <> struct gemm_cfg<float, true> {
     static constexpr int BM = 64, BN = 64, BK = 16, WM = 32, WN = 32, MINB = 4;
+    static constexpr bool DB = true, G3 = true;
 };
 template <> struct gemm_cfg<double, true> {
     static constexpr int BM = 64, BN = 64, BK = 16, WM = 32, WN = 32, MINB = 2;
+    static constexpr bool DB = true, G3 = true;
 };
 template <> struct gemm_cfg<double, false> {
     static constexpr int BM = 64, BN = 64, BK = 16, WM = 32, WN = 32, MINB = 2;
+    static constexpr bool DB = false, G3 = false;
 };
 template <> struct gemm_cfg<float, false> {
     static constexpr int BM = 128, BN = 64, BK = 16, WM = 64, WN = 32, MINB = 3;
+    static constexpr bool DB = false, G3 = false;
 };
 
 // Optional per-launch timing of the complex64 product (defined by the driver).
@@ -221,7 +270,8 @@ void gemm2(hipStream_t s, int m, int n, int k, T alpha, const typename elem<T, C
     constexpr bool timed = std::is_same<T, float>::value && CPLX;
     hipEvent_t e0 = nullptr;
     if (timed) gemm_timing_begin(s, &e0);
-    hipLaunchKernelGGL((gemm_kernel<T, CPLX, OPA_H, cfg::BM, cfg::BN, cfg::BK, cfg::WM, cfg::WN, cfg::MINB>),
+    hipLaunchKernelGGL((gemm_kernel<T, CPLX, OPA_H, cfg::BM, cfg::BN, cfg::BK, cfg::WM, cfg::WN, cfg::MINB, cfg::DB,
+                                    cfg::G3>),
                        grid, dim3(NT), 0, s, m, n, k, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, sA2, sB2,
                        sC2, dm);
     FX_LAUNCH_CHECK();
