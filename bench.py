@@ -30,9 +30,11 @@ N, COUNT, M0, NE, TOL, SEED = 4096, 200, 300, 8, 1e-10, 2001
 # scaled by a 256 MiB copy's reading, averaged over the launches of one
 # solve), from the rocprofv3 counter passes summarised in
 # profiles/hbm_traffic_realgen_n4096_m0300.md.  It holds only for the
-# kernel sources it was measured on: `traffic` is null when they differ.
-TRAFFIC_BYTES_PER_LAUNCH = 1.438e+08
-TRAFFIC_SOURCES_SHA256 = "18d2f24c876088456b9ed162f651a83e495bcab8a2b200f6ece6db71aeba7567"
+# sources it was measured on -- the kernel itself and every file that
+# launches it (the FP64 reduced-problem kernels in jacobi.hpp and
+# bortho.hpp do not): `traffic` is null when they differ.
+TRAFFIC_BYTES_PER_LAUNCH = 1.442e+08
+TRAFFIC_SOURCES_SHA256 = "1aac3d9e72dd0c15b218215f102449b680d6c8ddfa0173002f975a084309ed5f"
 
 
 def kernel_sources_sha256():
@@ -40,7 +42,7 @@ def kernel_sources_sha256():
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1203_4031_amd", "csrc")
     for name in sorted(os.listdir(d)):
-        if name.endswith((".hip", ".hpp", ".h")):
+        if name.endswith((".hip", ".hpp", ".h")) and name not in ("jacobi.hpp", "bortho.hpp"):
             h.update(name.encode())
             with open(os.path.join(d, name), "rb") as f:
                 h.update(f.read())
@@ -219,6 +221,8 @@ def main():
                      "traffic": (TRAFFIC_BYTES_PER_LAUNCH
                                  if kernel_sources_sha256() == TRAFFIC_SOURCES_SHA256 else None),
                      "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "flop_count": "algorithmic, 8 per complex multiply-add; the kernel's three-multiplication "
+                                   "form issues 6 of them to the matrix cores (executed rate 0.75 x achieved)",
                      "launches": lu[2], "avg_launch_ms": lu[0] / max(lu[2], 1),
                      "flops_per_launch": lu[1] / max(lu[2], 1),
                      "measured_over": f"{args.roofline_steps} extra mixed solves with per-launch HIP events"},
