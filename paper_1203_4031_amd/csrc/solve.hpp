@@ -276,8 +276,11 @@ static void apply_block_diag(hipStream_t s, int n, int ncols, const cplx<T> *Din
 //   adjoint = true:   Y <- L^{-H} U^{-H} Y   (row permutation applied by the caller)
 // The sweeps alternate between Y and X, so the result ends in Y with no
 // copies.  Dinv_b are the inverted diagonal blocks (NB = solve_nb rows).
-// Solves with A_z use W (build_w): each block is one product on the
-// running right-hand side, the diagonal inverses go last.  Adjoint solves:
+// Solves with A_z use W (build_w): the diagonal inverses go last, and the
+// blocks are taken in groups of GB as below (each block updates the later
+// blocks of its group, the rows past the group get one product of the
+// group's depth), which halves the passes over the right-hand side of
+// depth-64 products in complex64.  Adjoint solves:
 // block b of the forward sweep is X_b = Dinv_b^H Y_b, then the rows below
 // get -= T^H X_b; blocks are taken in groups of GB (two 64-row blocks in
 // complex64, one 128-row block in FP64): inside a group the later blocks
@@ -300,20 +303,34 @@ void getrs_batched(hipStream_t s, bool adjoint, int n, int ncols, const cplx<T> 
     };
     int gs, ge, b0, b1;
     if (!adjoint) {
-        // L, forward, on Y in place with W, then X = blockdiag(Linv) Y
-        for (int b = 0; b < nblk; ++b) {
-            const int kb = b * NB, w = std::min(NB, n - kb);
-            if (kb + w < n)
-                gemm<T, true, false>(s, n - kb - w, ncols, w, T(-1), W + (kb + w) + (long)kb * ldf, ldf, sF, Y + kb,
-                                     ldy, sY, T(1), Y + kb + w, ldy, sY, batch);
+        // L, forward, on Y in place with W, then X = blockdiag(Linv) Y.
+        // Within a group each block updates the group's later blocks; the
+        // rows past the group get one product of the group's depth.
+        for (int g = 0; g < ngrp; ++g) {
+            grp(g, gs, ge, b0, b1);
+            for (int b = b0; b < b1; ++b) {
+                const int kb = b * NB, w = std::min(NB, n - kb);
+                if (kb + w < ge)
+                    gemm<T, true, false>(s, ge - kb - w, ncols, w, T(-1), W + (kb + w) + (long)kb * ldf, ldf, sF,
+                                         Y + kb, ldy, sY, T(1), Y + kb + w, ldy, sY, batch);
+            }
+            if (ge < n)
+                gemm<T, true, false>(s, n - ge, ncols, ge - gs, T(-1), W + ge + (long)gs * ldf, ldf, sF, Y + gs, ldy,
+                                     sY, T(1), Y + ge, ldy, sY, batch);
         }
         apply_block_diag<T>(s, n, ncols, Linv, sInv, Y, X, ldy, sY, batch);
         // U, backward, on X in place with W, then Y = blockdiag(Uinv) X
-        for (int b = nblk - 1; b >= 0; --b) {
-            const int kb = b * NB, w = std::min(NB, n - kb);
-            if (kb > 0)
-                gemm<T, true, false>(s, kb, ncols, w, T(-1), W + (long)kb * ldf, ldf, sF, X + kb, ldy, sY, T(1), X,
-                                     ldy, sY, batch);
+        for (int g = ngrp - 1; g >= 0; --g) {
+            grp(g, gs, ge, b0, b1);
+            for (int b = b1 - 1; b >= b0; --b) {
+                const int kb = b * NB, w = std::min(NB, n - kb);
+                if (kb > gs)
+                    gemm<T, true, false>(s, kb - gs, ncols, w, T(-1), W + gs + (long)kb * ldf, ldf, sF, X + kb, ldy,
+                                         sY, T(1), X + gs, ldy, sY, batch);
+            }
+            if (gs > 0)
+                gemm<T, true, false>(s, gs, ncols, ge - gs, T(-1), W + (long)gs * ldf, ldf, sF, X + gs, ldy, sY,
+                                     T(1), X, ldy, sY, batch);
         }
         apply_block_diag<T>(s, n, ncols, Uinv, sInv, X, Y, ldy, sY, batch);
     } else {
