@@ -656,8 +656,10 @@ static void lu_gemm(hipStream_t s, cplx<T> *F, long ldf, long sF, int r0, int r1
 // two of depth 32, which halves the trailing-matrix traffic.  Per pair:
 //   1. panel k1's columns get panel k0's interchanges, U rows and update;
 //      panel k1 is factored on s2 (the look-ahead stream) while
-//   2. the far columns get panel k0's interchanges, the previous pair's
-//      deferred update (below), then panel k0's U rows;
+//   2. the far columns get the previous pair's deferred update (below),
+//      then panel k0's interchanges and U rows in one launch (the left
+//      columns, which hold the deferred update's L rows, get the
+//      interchanges in the same launch, after the update has read them);
 //   3. panel k2 = k1 + 32's columns get panel k1's interchanges (applied
 //      to panel k0's L too, so that its rows match), the depth-32
 //      correction of rows k1..k2 by panel k0, panel k1's U rows and the
@@ -705,12 +707,13 @@ void getrf_batched(hipStream_t s, hipStream_t s2, hipEvent_t ev_a, hipEvent_t ev
         swap_trsm<T>(s, n, F, ldf, sF, k0, w0, k1, k2, 0, 0, LU_SWAP | LU_TRSM, sm(k0), batch);
         lu_gemm<T>(s, F, ldf, sF, k1, n, k1, k2, k0, k1, batch);
         panel_side(k1);
-        // 2. far and left columns: panel k0's interchanges, the deferred
-        //    update, panel k0's U rows on the far ones
-        swap_trsm<T>(s, n, F, ldf, sF, k0, w0, 0, k0, k2, n, LU_SWAP, sm(k0), batch);
+        // 2. far and left columns: the deferred update first, on rows and L
+        //    columns that panel k0's interchanges have not reached yet (the
+        //    two stay consistent), then panel k0's interchanges on the left
+        //    and far columns and its U rows on the far ones, in one launch
         lu_gemm<T>(s, F, ldf, sF, pr0, n, pc0, n, pk0, pk1, batch);
         pc0 = n;
-        swap_trsm<T>(s, n, F, ldf, sF, k0, w0, k2, n, 0, 0, LU_TRSM, sm(k0), batch);
+        swap_trsm<T>(s, n, F, ldf, sF, k0, w0, 0, k0, k2, n, LU_SWAP | LU_TRSM, sm(k0), batch);
         join();
         if (k2 >= n) {   // panel k1 was the last
             swap_trsm<T>(s, n, F, ldf, sF, k1, w1, 0, k1, 0, 0, LU_SWAP, sm(k1), batch);
