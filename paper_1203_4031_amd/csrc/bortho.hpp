@@ -19,7 +19,11 @@
 namespace fx {
 
 constexpr int CHOL_MAXM = 1024;   // one row per thread
-constexpr int CHOL_CB = 8;        // columns per left-looking block
+// Columns per left-looking block.  A block costs one global round trip per
+// 32 (real) or 8 (complex) earlier columns, so wider blocks mean fewer round
+// trips; 16 columns fit the registers of a 512-thread launch
+// (m <= 512), not of a 1024-thread one.
+template <bool CPLX, int NT> constexpr int chol_cb() { return NT <= 512 ? 16 : 8; }
 constexpr int TRI_NB = 64;
 
 // d_i = 1 / sqrt(Re Bq_ii); status[0] = -3 if some diagonal is not positive
@@ -68,13 +72,14 @@ __global__ __launch_bounds__(256) void set_identity_kernel(int r, typename jelem
 // Left-looking Cholesky with column dropping, one workgroup, thread i owns
 // row i.  L (m x m, lower, column-major) receives the factor; keep[j] = 1
 // for kept columns.  status[0] = -3 on a negative pivot, status[1] = rank.
-template <bool CPLX>
-__global__ __launch_bounds__(CHOL_MAXM) void chol_drop_kernel(int m, const typename jelem<CPLX>::type *Bt, long ldb,
+template <bool CPLX, int NT>
+__global__ __launch_bounds__(NT) void chol_drop_kernel(int m, const typename jelem<CPLX>::type *Bt, long ldb,
                                                               typename jelem<CPLX>::type *L, long ldl, int *keep,
                                                               double tol, double neg_tol, int *status)
 {
     using E = typename jelem<CPLX>::type;
-    __shared__ E Lrow[CHOL_CB][CHOL_MAXM];   // rows k0.. of L, previous columns
+    constexpr int CHOL_CB = chol_cb<CPLX, NT>();
+    __shared__ E Lrow[CHOL_CB][NT];   // rows k0.. of L, previous columns
     __shared__ E pv[CHOL_CB];
     __shared__ int s_bad, s_rank;
     const int i = threadIdx.x;
@@ -89,7 +94,7 @@ __global__ __launch_bounds__(CHOL_MAXM) void chol_drop_kernel(int m, const typen
     constexpr int CH = CPLX ? 8 : 32;
     for (int k0 = 0; k0 < m; k0 += CHOL_CB) {
         const int cb = min(CHOL_CB, m - k0);
-        for (int e = i; e < CHOL_CB * k0; e += CHOL_MAXM) {
+        for (int e = i; e < CHOL_CB * k0; e += NT) {
             const int c = e % CHOL_CB, j = e / CHOL_CB;
             Lrow[c][j] = (c < cb) ? L[(k0 + c) + (long)j * ldl] : jzero<E>();   // zero rows past the end
         }

@@ -495,8 +495,13 @@ static int bortho_cholesky(Workspace &ws, hipStream_t s, int m, F64<CPLX> *Bq, F
     FX_CHECK(hipMemcpyAsync(ord, order.data(), sizeof(int) * m, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL((sym_scale_kernel<CPLX>), grid1((long)mm), dim3(256), 0, s, m, Bq, (long)m, d, ord, Bt, (long)m);
     FX_LAUNCH_CHECK();
-    hipLaunchKernelGGL((chol_drop_kernel<CPLX>), dim3(1), dim3(CHOL_MAXM), 0, s, m, Bt, (long)m, L, (long)m, keepf,
-                       CHOL_DROP, INDEFINITE, status);
+    // one row per thread: a 512-thread launch up to m = 512 (wider column blocks fit its registers)
+    if (m <= 512)
+        hipLaunchKernelGGL((chol_drop_kernel<CPLX, 512>), dim3(1), dim3(512), 0, s, m, Bt, (long)m, L, (long)m, keepf,
+                           CHOL_DROP, INDEFINITE, status);
+    else
+        hipLaunchKernelGGL((chol_drop_kernel<CPLX, CHOL_MAXM>), dim3(1), dim3(CHOL_MAXM), 0, s, m, Bt, (long)m, L,
+                           (long)m, keepf, CHOL_DROP, INDEFINITE, status);
     FX_LAUNCH_CHECK();
     FX_CHECK(hipMemcpyAsync(h_i, status, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
     FX_CHECK(hipMemcpyAsync(h_i + 4, keepf, sizeof(int) * m, hipMemcpyDeviceToHost, s));
