@@ -448,10 +448,11 @@ template <typename V> __device__ inline V quad_bcast(V v, int g)
     }
 }
 
-template <typename T, int NB>
+template <typename T, int NB, bool CORR_MODE>
 __global__ __launch_bounds__(256) void lu_swap_trsm_kernel(int n, cplx<T> *__restrict__ Fall, long ldf,
                                                            long sF, int k, int nbw, int c0, int c1, int c2,
-                                                           int c3, int mode, const int *__restrict__ swapmap_all)
+                                                           int c3, int kc0, int kc1, int mode,
+                                                           const int *__restrict__ swapmap_all)
 {
     using V = cplx<T>;
     constexpr int CB = 64;
@@ -464,6 +465,7 @@ __global__ __launch_bounds__(256) void lu_swap_trsm_kernel(int n, cplx<T> *__res
     __shared__ int dst[2 * NB], src[2 * NB];
     __shared__ int top_q[NB];   // top row k + i is written by move top_q[i] (-1: none)
     __shared__ int s_nm;
+    __shared__ V Lc[(CORR_MODE ? NB : 1)][NB + 1];
 
     const int w1 = c1 - c0, ncols = w1 + (c3 - c2);
     auto col_of = [&](int oc) { return oc < w1 ? c0 + oc : c2 + (oc - w1); };
@@ -504,6 +506,14 @@ __global__ __launch_bounds__(256) void lu_swap_trsm_kernel(int n, cplx<T> *__res
         const int i = g + 4 * j;
         xr[j] = (colok && i < nbw) ? pc[i] : cmake<V>(0, 0);
     }
+    // correction rows of the solve column (rows kc0..kc1, final before this launch)
+    const int kw = (mode & 4) ? kc1 - kc0 : 0;
+    V u0[CORR_MODE ? NB : 1];
+    if constexpr (CORR_MODE) {
+        const V *pu = a + (long)(colok ? col_of(soc) : 0) * ldf + kc0;
+#pragma unroll
+        for (int q = 0; q < NB; ++q) u0[q] = (colok && q < kw) ? pu[q] : cmake<V>(0, 0);
+    }
     __syncthreads();
     const int nm = s_nm;
 
@@ -530,7 +540,11 @@ __global__ __launch_bounds__(256) void lu_swap_trsm_kernel(int n, cplx<T> *__res
         }
     }
 
-    // 4. U12 = L11^{-1} A12, column-oriented forward substitution
+    // 4. U12 = L11^{-1} A12, column-oriented forward substitution, after
+    //    the correction of the top rows by an earlier panel when asked
+    //    (mode bit 2): rows k.. -= F[k.., kc0:kc1] F[kc0:kc1, col].  Those
+    //    L rows are read back after this launch's moves are stored, so
+    //    they may be columns of this launch, handled by this block.
     if (right) {
 #pragma unroll
         for (int j = 0; j < NB / 4; ++j) {
@@ -538,6 +552,20 @@ __global__ __launch_bounds__(256) void lu_swap_trsm_kernel(int n, cplx<T> *__res
             if (colok && i < nbw) {
                 const int q = top_q[i];
                 if (q >= 0) xr[j] = stage[q][sc];
+            }
+        }
+        if constexpr (CORR_MODE) {
+            if (kw > 0) {
+                __syncthreads();
+                for (int e = tid; e < NB * NB; e += 256) {
+                    const int i = e % NB, q = e / NB;
+                    Lc[i][q] = (i < nbw && q < kw) ? a[(k + i) + (long)(kc0 + q) * ldf] : cmake<V>(0, 0);
+                }
+                __syncthreads();
+#pragma unroll
+                for (int q = 0; q < NB; ++q)
+#pragma unroll
+                    for (int j = 0; j < NB / 4; ++j) xr[j] = csub(xr[j], cmul(Lc[g + 4 * j][q], u0[q]));
             }
         }
 #pragma unroll
@@ -622,17 +650,28 @@ static void launch_panel_rows(hipStream_t s, int n, cplx<T> *F, long ldf, long s
     else launch_panel<T, 16>(s, n, F, ldf, sF, k, ipiv, perm, sPiv, swapmap, info, batch);
 }
 
-constexpr int LU_SWAP = 1, LU_TRSM = 2;
+constexpr int LU_SWAP = 1, LU_TRSM = 2, LU_CORR = 4;
 
+// mode LU_CORR (with LU_TRSM): before the U-row solve, the top rows of the
+// solved columns get -= F[k:k+nbw, kc0:kc1] F[kc0:kc1, col].  When those L
+// columns are among this launch's columns, one block must hold them all.
 template <typename T>
 static void swap_trsm(hipStream_t s, int n, cplx<T> *F, long ldf, long sF, int k, int nbw, int c0, int c1, int c2,
-                      int c3, int mode, const int *swapmap, int batch)
+                      int c3, int mode, const int *swapmap, int batch, int kc0 = 0, int kc1 = 0)
 {
     const int ncols = (c1 - c0) + (c3 - c2);
     if (ncols <= 0) return;
     dim3 grid(ceil_div(ncols, 64), batch);
-    hipLaunchKernelGGL((lu_swap_trsm_kernel<T, LU_NB>), grid, dim3(256), 0, s, n, F, ldf, sF, k, nbw, c0, c1, c2, c3,
-                       mode, swapmap);
+    if (mode & LU_CORR) {
+        const bool inside = (kc0 < c1 && kc1 > c0) || (kc0 < c3 && kc1 > c2);
+        if (!(mode & LU_TRSM) || kc1 - kc0 > LU_NB || kc1 < kc0 || kc1 > k || (inside && ncols > 64))
+            throw hip_error{hipErrorInvalidValue};
+        hipLaunchKernelGGL((lu_swap_trsm_kernel<T, LU_NB, true>), grid, dim3(256), 0, s, n, F, ldf, sF, k, nbw, c0,
+                           c1, c2, c3, kc0, kc1, mode, swapmap);
+    } else {
+        hipLaunchKernelGGL((lu_swap_trsm_kernel<T, LU_NB, false>), grid, dim3(256), 0, s, n, F, ldf, sF, k, nbw, c0,
+                           c1, c2, c3, 0, 0, mode, swapmap);
+    }
     FX_LAUNCH_CHECK();
 }
 
@@ -720,17 +759,16 @@ void getrf_batched(hipStream_t s, hipStream_t s2, hipEvent_t ev_a, hipEvent_t ev
             break;
         }
         const int w2 = std::min(NB, n - k2), k3 = k2 + w2;
-        // 3. panel k2's columns
-        swap_trsm<T>(s, n, F, ldf, sF, k1, w1, k0, k1, k2, k3, LU_SWAP, sm(k1), batch);
-        lu_gemm<T>(s, F, ldf, sF, k1, k2, k2, k3, k0, k1, batch);
-        swap_trsm<T>(s, n, F, ldf, sF, k1, w1, k2, k3, 0, 0, LU_TRSM, sm(k1), batch);
+        // 3. panel k2's columns: panel k1's interchanges (on panel k0's L
+        //    columns too), the depth-32 correction of rows k1..k2 by panel
+        //    k0 and panel k1's U rows in one launch, then the depth-64
+        //    update of rows k2.. by both panels
+        swap_trsm<T>(s, n, F, ldf, sF, k1, w1, k0, k1, k2, k3, LU_SWAP | LU_CORR | LU_TRSM, sm(k1), batch, k0, k1);
         lu_gemm<T>(s, F, ldf, sF, k2, n, k2, k3, k0, k2, batch);
         panel_side(k2);
         // 4. far and left columns; the far columns past `mid` wait for the
         //    next pair's step 2 (panel k3 = k2 + 32's columns are before mid)
-        swap_trsm<T>(s, n, F, ldf, sF, k1, w1, 0, k0, k3, n, LU_SWAP, sm(k1), batch);
-        lu_gemm<T>(s, F, ldf, sF, k1, k2, k3, n, k0, k1, batch);
-        swap_trsm<T>(s, n, F, ldf, sF, k1, w1, k3, n, 0, 0, LU_TRSM, sm(k1), batch);
+        swap_trsm<T>(s, n, F, ldf, sF, k1, w1, 0, k0, k3, n, LU_SWAP | LU_CORR | LU_TRSM, sm(k1), batch, k0, k1);
         const int mid = std::min(n, k3 + NB + ((n - k3 - NB) / 2 + 63) / 64 * 64);
         lu_gemm<T>(s, F, ldf, sF, k2, n, k3, mid, k0, k2, batch);
         pc0 = mid;
