@@ -93,3 +93,26 @@ def test_server_admission_budget_serialises():
         assert r.info == 0 and r.M == p.count_in_interval()
     # admitted one at a time: each waits for the previous
     assert rs[2].queue_ms >= rs[0].run_ms * 0.5
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_batched_one_round_jacobi(precision):
+    """Reduced problems of m <= 32 give the block Jacobi a single round per
+    sweep, where every workgroup rewrites its off-norm partial before the
+    next grid barrier; the partials alternate by sweep parity so that no
+    workgroup can read a partial of the next sweep.  Sixteen such problems
+    at the executor's full 8 slots, each checked against its spectrum."""
+    probs = [W.dense_real_generalized(n, count=c, seed=4300 + i, tol=1e-10)
+             for i, (n, c) in enumerate([(256, 12), (300, 16), (270, 14), (320, 18)] * 4)]
+    assert all(p.m0 <= 32 for p in probs)
+    print(f"batched one-round Jacobi {precision}", flush=True)
+    out = feastx.solve_batched([(p.A, p.B, p.emin, p.emax, p.m0, p.X0) for p in probs], concurrency=8, ne=8,
+                               tol=1e-10, precision=precision)
+    for p, r in zip(probs, out):
+        s = p.spectrum
+        ref = s[(s >= p.emin) & (s <= p.emax)]
+        alpha = max(abs(p.emin), abs(p.emax))
+        assert r.info == 0, (p.name, r.info)
+        assert r.M == len(ref), p.name
+        assert np.all(np.abs(r.E[:r.M] - ref) <= 1e-10 * np.maximum(np.abs(ref), alpha)), p.name
+        assert np.all(r.res[:r.M] < 1e-10), p.name
