@@ -55,7 +55,9 @@ def log(msg):
 
 def run_steps(feastx, torch, A, B, X0, X, p, precision, steps, timing):
     feastx.set_timing(timing)
-    times, results, lu = [], [], [0.0, 0.0, 0]
+    # product launches: all of them (time, flops, count), then the shifted
+    # LU's own (time, flops, count), then the factor stage (time, flops)
+    times, results, lu = [], [], [0.0, 0.0, 0, 0.0, 0.0, 0, 0.0, 0.0]
     stream = torch.cuda.current_stream()
     for _ in range(steps):
         torch.cuda.synchronize()
@@ -71,6 +73,11 @@ def run_steps(feastx, torch, A, B, X0, X, p, precision, steps, timing):
             lu[0] += s.t_lu_gemm
             lu[1] += s.lu_gemm_flops
             lu[2] += s.lu_gemm_launches
+            lu[3] += s.t_lu_update
+            lu[4] += s.lu_update_flops
+            lu[5] += s.lu_update_launches
+            lu[6] += s.t_factor
+            lu[7] += s.factor_flops
     feastx.set_timing(False)
     return times, results, lu
 
@@ -215,7 +222,9 @@ def main():
         "stage_ms_last_solve": stage_ms,
         "roofline": {"kernel": "gemm_kernel<float, true, false, 64, 64, 16, 32, 32, 4, true, true>: complex64 "
                                "matrix product on the FP32 matrix cores (LU trailing updates and "
-                               "triangular-solve updates), every launch of the timed solves",
+                               "triangular-solve updates), every launch of the timed solves; products of at "
+                               "most 32 columns use its 64x32 instance gemm_kernel<float, true, false, 64, 32, "
+                               "16, 32, 16, 4, true, true>, counted here too",
                      "bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA,
                      "traffic": (TRAFFIC_BYTES_PER_LAUNCH
@@ -227,6 +236,18 @@ def main():
                      "flops_per_launch": lu[1] / max(lu[2], 1),
                      "measured_over": f"{args.roofline_steps} extra mixed solves with per-launch HIP events"},
     }
+    # the shifted LU on its own: its product launches (trailing and panel-column
+    # updates), and the whole factor stage (panels, interchanges, products and
+    # the solve form W) against the (8/3) N^3 flops of each LU
+    upd = lu[4] / (lu[3] * 1e-3) / 1e12 if lu[3] > 0 else 0.0
+    fac = lu[7] / (lu[6] * 1e-3) / 1e12 if lu[6] > 0 else 0.0
+    out["shifted_lu"] = {"update_achieved": upd, "update_frac": upd / PEAK_FP32_MFMA,
+                         "update_launches": lu[5], "unit": "TFLOP/s", "peak": PEAK_FP32_MFMA,
+                         "factor_ms": lu[6] / max(args.roofline_steps, 1),
+                         "factor_rate": fac, "factor_frac": fac / PEAK_FP32_MFMA,
+                         "note": "update_*: the LU's complex64 product launches alone (8 flops per complex "
+                                 "multiply-add); factor_*: Ne (8/3) N^3 over the whole factor stage, timed with "
+                                 "per-launch events on (so slightly slow)"}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, loops)
     print(json.dumps(out), flush=True)

@@ -78,6 +78,10 @@ typedef struct {
     int m0_final;            /* subspace size at exit */
     int eig_calls;           /* reduced Hermitian eigensolves */
     int eig_sweeps;          /* Jacobi sweeps summed over those calls */
+    double t_lu_update;      /* with feast_set_timing(1): the part of t_lu_gemm issued by the shifted
+                                LU itself (its trailing and panel-column updates) */
+    double lu_update_flops;  /* algorithmic real flops of those launches */
+    long long lu_update_launches;
 } feast_stats;
 
 /* Defaults of the guide's feastinit (Table "tab_fpm"), with keep_factors = 1. */

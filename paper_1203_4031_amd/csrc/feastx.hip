@@ -307,10 +307,13 @@ struct StageTimer {
     }
 };
 
-// Per-launch timing of the LU trailing update (enabled by feast_set_timing).
+// Per-launch timing of the complex64 products (enabled by feast_set_timing);
+// those issued by the shifted LU itself are also summed apart.
 struct GemmTimer {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
-    double flops = 0;
+    std::vector<char> in_lu;
+    double flops = 0, lu_flops = 0;
+    bool lu = false;   // launches being recorded belong to getrf_batched
 };
 static thread_local GemmTimer *g_gemm_timer = nullptr;
 void gemm_timing_reset();
@@ -649,6 +652,7 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
             shift_build<T>(s, CPLX, n, pb.A, pb.lda, pb.B, pb.ldb, dz, ne, F, ldf, sF);
             tm.mark(&st.t_shift);
             FX_CHECK(hipMemsetAsync(dinfo, 0, sizeof(int) * ne, s));
+            if (g_gemm_timer) g_gemm_timer->lu = true;
             if (!g_no_lookahead && ws.lookahead && ws.split(ne)) {
                 FX_CHECK(hipEventRecord(ws.ev_c, s));
                 FX_CHECK(hipStreamWaitEvent(ws.fmain, ws.ev_c, 0));
@@ -660,6 +664,7 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
                 getrf_batched<T>(s, (g_no_lookahead || !ws.lookahead) ? nullptr : ws.side, ws.ev_a, ws.ev_b, n, F,
                                  ldf, sF, ipiv, perm, n, swapmap, dinfo, ne);
             }
+            if (g_gemm_timer) g_gemm_timer->lu = false;
             solve_inverses<T>(s, n, F, ldf, sF, L64, U64, sI64, Linv, Uinv, sInv, Itmp, sItmp, ne);
             build_w<T>(s, n, F, ldf, sF, Linv, Uinv, sInv, Wsv, ne);
             tm.mark(&st.t_factor);
@@ -863,18 +868,28 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
     st.t_total += st.t_shift + st.t_factor + st.t_solve + st.t_accum + st.t_rr + st.t_reduced + st.t_resid;
     if (g_gemm_timer) {
         FX_CHECK(hipStreamSynchronize(s));
-        double tot = 0;
-        for (auto &e : g_gemm_timer->ev) {
+        double tot = 0, tot_lu = 0;
+        long long n_lu = 0;
+        for (size_t q = 0; q < g_gemm_timer->ev.size(); ++q) {
             float ms = 0;
-            FX_CHECK(hipEventElapsedTime(&ms, e.first, e.second));
+            FX_CHECK(hipEventElapsedTime(&ms, g_gemm_timer->ev[q].first, g_gemm_timer->ev[q].second));
             tot += ms;
+            if (g_gemm_timer->in_lu[q]) {
+                tot_lu += ms;
+                ++n_lu;
+            }
         }
         gemm_timing_reset();
         st.t_lu_gemm = tot;
         st.lu_gemm_flops = g_gemm_timer->flops;
         st.lu_gemm_launches = (long long)g_gemm_timer->ev.size();
+        st.t_lu_update = tot_lu;
+        st.lu_update_flops = g_gemm_timer->lu_flops;
+        st.lu_update_launches = n_lu;
         g_gemm_timer->ev.clear();
+        g_gemm_timer->in_lu.clear();
         g_gemm_timer->flops = 0;
+        g_gemm_timer->lu_flops = 0;
     }
     st_out = st;
     return info;
@@ -1061,7 +1076,9 @@ void gemm_timing_end(hipStream_t s, hipEvent_t e0, double flops)
     hipEvent_t e1 = pooled_event();
     FX_CHECK(hipEventRecord(e1, s));
     g_gemm_timer->ev.push_back({e0, e1});
+    g_gemm_timer->in_lu.push_back(g_gemm_timer->lu ? 1 : 0);
     g_gemm_timer->flops += flops;
+    if (g_gemm_timer->lu) g_gemm_timer->lu_flops += flops;
 }
 void gemm_timing_reset() { t_event_next = 0; }
 }  // namespace fx

@@ -36,7 +36,8 @@ class feast_stats(C.Structure):
                 ("t_reduced", C.c_double), ("t_resid", C.c_double), ("t_lu_gemm", C.c_double),
                 ("lu_gemm_flops", C.c_double), ("lu_gemm_launches", C.c_longlong),
                 ("factor_flops", C.c_double), ("solve_flops", C.c_double), ("loops", C.c_int),
-                ("m0_final", C.c_int), ("eig_calls", C.c_int), ("eig_sweeps", C.c_int)]
+                ("m0_final", C.c_int), ("eig_calls", C.c_int), ("eig_sweeps", C.c_int),
+                ("t_lu_update", C.c_double), ("lu_update_flops", C.c_double), ("lu_update_launches", C.c_longlong)]
 
 
 class feast_job(C.Structure):
