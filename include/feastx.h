@@ -62,6 +62,13 @@ typedef struct {
     int verbose;      /* [fpm(1)] 1: print one line per loop to stderr */
     double tol;       /* [fpm(3)] convergence tolerance, > 0; default 1e-12 */
     unsigned long long seed; /* seed of the random start subspace (x0 = 0) */
+    int integration;  /* [fpm(16)] half-contour rule: 0 Gauss-Legendre (default), 1 trapezoidal;
+                         2 (Zolotarev) is not in this build: info 116 */
+    int ellipse;      /* [fpm(18)] contour ellipse, vertical over horizontal semi-axis in percent:
+                         100 circle (default), 50 flat, 200 tall; >= 1, else info 118 */
+    const feast_z *Zne; /* expert mode (the guide's Zne, Wne arguments): ne custom half-contour nodes */
+    const feast_z *Wne; /* and weights, both or neither (else info -113); read during the call (the
+                           server copies them at submit); integration and ellipse are then unused */
 } feast_opts;
 
 /* Per-stage timings of the most recent solve (milliseconds, from HIP events
@@ -188,13 +195,24 @@ int feast_server_wait(feast_server *srv, unsigned long long id, feast_result *ou
 /* finishes the queued requests, then frees everything */
 void feast_server_destroy(feast_server *srv);
 
-/* ---- tools (host only, no GPU).
- * Half-contour nodes and weights (tool "[cz]feast_contour", Gauss rule):
- * z_j = c + r e^{i theta_j}, w_j = (omega_j / 2) r e^{i theta_j},
- * theta_j = (pi/2)(1 - x_j), (x_j, omega_j) Gauss-Legendre on [-1, 1]. */
-int feast_contour(double Emin, double Emax, int ne, feast_z *Zne, feast_z *Wne);
-/* Filter rho(lambda) = Re sum_j w_j / (z_j - lambda) (tool "[sd]feast_rational"). */
-int feast_rational(double Emin, double Emax, int ne, const double *eig, int m, double *f);
+/* ---- tools (host only, no GPU), with the guide's arguments.
+ * Half-contour nodes and weights (tool "[cz]feast_contour"; section "Defining
+ * a search contour"): with c = (Emin + Emax)/2, r = (Emax - Emin)/2 and
+ * a = fpm18 / 100, the contour is z(theta) = c + r cos(theta) + i a r sin(theta),
+ * and the filter rho(lambda) = (1 / 2 pi i) contour-integral dz / (z - lambda)
+ * taken over its upper half (doubled real part) at fpm2 nodes:
+ *   fpm16 = 0: theta_j = (pi/2)(1 - x_j), dtheta_j = (pi/2) omega_j,
+ *              (x_j, omega_j) Gauss-Legendre on [-1, 1];
+ *   fpm16 = 1: theta_j = pi (fpm2 - j - 1/2) / fpm2, dtheta_j = pi / fpm2;
+ *   z_j = z(theta_j), w_j = (dtheta_j / pi)(a r cos(theta_j) + i r sin(theta_j)).
+ * Nodes come in increasing real part.  Returns 0, 102 (fpm2 < 1), 116
+ * (fpm16), 118 (fpm18 < 1), 200 (Emin >= Emax), -105/-106 (NULL output). */
+int feast_contour(double Emin, double Emax, int fpm2, int fpm16, int fpm18, feast_z *Zne, feast_z *Wne);
+/* Filter rho(lambda) = Re sum_j w_j / (z_j - lambda) at the m points eig
+ * (tool "[sd]feast_rational"); the same codes, -108 for a NULL eig or f. */
+int feast_rational(double Emin, double Emax, int fpm2, int fpm16, int fpm18, const double *eig, int m, double *f);
+/* The same filter for custom nodes and weights (tool "[sd]feast_rationalx"). */
+int feast_rationalx(const feast_z *Zne, const feast_z *Wne, int fpm2, const double *eig, int m, double *f);
 
 /* Statistics of the last solve on this process; 0 on success. */
 int feast_last_stats(feast_stats *stats);

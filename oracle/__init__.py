@@ -42,8 +42,10 @@ def _load():
         ip = C.POINTER(C.c_int)
         vp = C.c_void_p
         lib.orc_gauss_legendre.argtypes = [C.c_int, dp, dp]
-        lib.orc_contour.argtypes = [C.c_double, C.c_double, C.c_int, vp, vp]
-        lib.orc_rational.argtypes = [C.c_double, C.c_double, C.c_int, dp, C.c_int, dp]
+        lib.orc_contour.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int, C.c_int, vp, vp]
+        lib.orc_rational.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int, C.c_int, dp, C.c_int, dp]
+        lib.orc_rationalx.argtypes = [C.c_int, vp, vp, dp, C.c_int, dp]
+        lib.orc_rationalx.restype = None
         lib.orc_zgetrf.argtypes = [C.c_int, vp, C.c_int, ip]
         lib.orc_zgetrs.argtypes = [C.c_char, C.c_int, C.c_int, vp, C.c_int, ip, vp, C.c_int]
         lib.orc_zgemm.argtypes = [C.c_char, C.c_int, C.c_int, C.c_int, vp, C.c_int, vp, C.c_int,
@@ -52,7 +54,7 @@ def _load():
         lib.orc_zheev_jacobi.argtypes = [C.c_int, vp, C.c_int, dp, vp, C.c_int]
         lib.orc_feast.argtypes = [C.c_int, C.c_int, vp, vp, C.c_double, C.c_double, ip, C.c_int,
                                   C.c_double, C.c_int, C.c_int, C.c_int, vp, dp, vp, dp, ip, ip,
-                                  dp]
+                                  dp, C.c_int, C.c_int, vp, vp]
         _lib = lib
     return _lib
 
@@ -77,19 +79,31 @@ def gauss_legendre(n: int):
     return x, w
 
 
-def contour(emin: float, emax: float, ne: int):
+def contour(emin: float, emax: float, ne: int, integration: int = 0, ellipse: int = 100):
+    """Half-contour nodes and weights: integration = fpm(16) (0 Gauss-Legendre,
+    1 trapezoidal), ellipse = fpm(18) (vertical / horizontal semi-axis, %)."""
     z = np.zeros(ne, np.complex128)
     w = np.zeros(ne, np.complex128)
-    if _load().orc_contour(emin, emax, ne, z.ctypes.data, w.ctypes.data):
+    if _load().orc_contour(emin, emax, ne, integration, ellipse, z.ctypes.data, w.ctypes.data):
         raise ValueError("bad contour arguments")
     return z, w
 
 
-def rational(emin: float, emax: float, ne: int, lam):
+def rational(emin: float, emax: float, ne: int, lam, integration: int = 0, ellipse: int = 100):
     lam = np.ascontiguousarray(lam, dtype=np.float64)
     f = np.zeros(lam.size)
-    if _load().orc_rational(emin, emax, ne, _dp(lam), lam.size, _dp(f)):
+    if _load().orc_rational(emin, emax, ne, integration, ellipse, _dp(lam), lam.size, _dp(f)):
         raise ValueError("bad contour arguments")
+    return f
+
+
+def rationalx(z, w, lam):
+    """The filter Re sum_j w_j / (z_j - lambda) of given nodes and weights."""
+    z = np.ascontiguousarray(z, dtype=np.complex128)
+    w = np.ascontiguousarray(w, dtype=np.complex128)
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    f = np.zeros(lam.size)
+    _load().orc_rationalx(z.size, z.ctypes.data, w.ctypes.data, _dp(lam), lam.size, _dp(f))
     return f
 
 
@@ -148,7 +162,7 @@ class OracleResult:
 
 
 def feast(A, B, emin, emax, m0, ne, tol, X0, *, hermitian=False, maxloop=20, conv=1,
-          mode=0) -> OracleResult:
+          mode=0, integration=0, ellipse=100, zne=None, wne=None) -> OracleResult:
     """Run the oracle's FEAST iteration.  Real symmetric input returns real X."""
     A = _z(A)
     n = A.shape[0]
@@ -163,11 +177,20 @@ def feast(A, B, emin, emax, m0, ne, tol, X0, *, hermitian=False, maxloop=20, con
     loop = np.zeros(1, np.int32)
     eps = np.zeros(1)
     m0a = np.array([m0], np.int32)
+    if (zne is None) != (wne is None):
+        raise ValueError("zne and wne go together")
+    if zne is not None:
+        zc = np.ascontiguousarray(zne, dtype=np.complex128)
+        wc = np.ascontiguousarray(wne, dtype=np.complex128)
+        if zc.size != ne or wc.size != ne:
+            raise ValueError("zne and wne need ne entries")
     info = _load().orc_feast(int(bool(hermitian)), n, A.ctypes.data,
                              None if Bz is None else Bz.ctypes.data, float(emin), float(emax),
                              _ip(m0a), int(ne), float(tol), int(maxloop), int(conv), int(mode),
                              X0z.ctypes.data, _dp(E), X.ctypes.data, _dp(res), _ip(M),
-                             _ip(loop), _dp(eps))
+                             _ip(loop), _dp(eps), int(integration), int(ellipse),
+                             None if zne is None else zc.ctypes.data,
+                             None if wne is None else wc.ctypes.data)
     m0o = int(m0a[0])
     if not hermitian:
         X = np.asfortranarray(X.real)

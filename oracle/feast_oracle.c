@@ -74,40 +74,70 @@ int orc_gauss_legendre(int n, double *x, double *w)
     return 0;
 }
 
-/* Half-contour nodes and weights for the circle through Emin and Emax
- * (section "Defining a search contour"; tool "[cz]feast_contour").
- * c = (Emin+Emax)/2, r = (Emax-Emin)/2, theta_j = (pi/2)(1 - x_j),
- * z_j = c + r e^{i theta_j}, w_j = (omega_j / 2) r e^{i theta_j}.
- * Reading: the 1/2 and the orientation are fixed so that the filter below
- * equals 1 at the centre and 1/2 at both endpoints.                       */
-int orc_contour(double emin, double emax, int ne, zc *z, zc *w)
+/* Half-contour nodes and weights (section "Defining a search contour";
+ * tool "[cz]feast_contour"; Table "tab_fpm" fpm(2), fpm(16), fpm(18)).
+ * The contour through Emin and Emax is the ellipse
+ *     z(t) = c + r cos t + i a r sin t,  c = (Emin+Emax)/2, r = (Emax-Emin)/2,
+ * a = ratio/100 (vertical over horizontal semi-axis; 1 is the circle).  The
+ * filter is (1/(2 pi i)) times the contour integral of dz/(z - lambda); the
+ * lower half mirrors the upper one, so for real lambda it is twice the real
+ * part of the upper-half integral:
+ *     rho(lambda) = Re (1/pi) int_0^pi (a r cos t + i r sin t)/(z(t) - lambda) dt,
+ * since dz/(2 pi i) = (a r cos t + i r sin t) dt / (2 pi).  A rule with
+ * points t_j and weights dt_j on [0, pi] gives z_j = z(t_j) and
+ * w_j = (dt_j/pi)(a r cos t_j + i r sin t_j):
+ *   integ 0 (Gauss-Legendre): t_j = (pi/2)(1 - x_j), dt_j = (pi/2) omega_j;
+ *   integ 1 (trapezoidal, midpoints): t_j = pi (ne - j - 1/2)/ne, dt_j = pi/ne.
+ * Both list the nodes from t near pi down to t near 0 (increasing real part).
+ * Reading: the 1/2-free form above is fixed so that the Gauss circle filter
+ * equals 1 at the centre and 1/2 at both endpoints, and the trapezoidal
+ * circle filter is 1/(1 + t^(2 ne)) with t = (lambda - c)/r.                */
+int orc_contour(double emin, double emax, int ne, int integ, int ratio, zc *z, zc *w)
 {
-    if (ne < 1 || !(emin < emax)) return -1;
-    double *x = malloc(sizeof(double) * ne), *om = malloc(sizeof(double) * ne);
-    orc_gauss_legendre(ne, x, om);
-    double c = 0.5 * (emin + emax), r = 0.5 * (emax - emin);
-    for (int j = 0; j < ne; ++j) {
-        double th = 0.5 * M_PI * (1.0 - x[j]);
-        zc e = cos(th) + I * sin(th);
-        z[j] = c + r * e;
-        w[j] = 0.5 * om[j] * r * e;
+    if (ne < 1 || !(emin < emax) || (integ != 0 && integ != 1) || ratio < 1) return -1;
+    double *t = malloc(sizeof(double) * ne), *dt = malloc(sizeof(double) * ne);
+    if (integ == 0) {
+        double *x = malloc(sizeof(double) * ne), *om = malloc(sizeof(double) * ne);
+        orc_gauss_legendre(ne, x, om);
+        for (int j = 0; j < ne; ++j) {
+            t[j] = 0.5 * M_PI * (1.0 - x[j]);
+            dt[j] = 0.5 * M_PI * om[j];
+        }
+        free(x);
+        free(om);
+    } else {
+        for (int j = 0; j < ne; ++j) {
+            t[j] = M_PI * (ne - j - 0.5) / ne;
+            dt[j] = M_PI / ne;
+        }
     }
-    free(x);
-    free(om);
+    double c = 0.5 * (emin + emax), r = 0.5 * (emax - emin), a = ratio / 100.0;
+    for (int j = 0; j < ne; ++j) {
+        z[j] = c + r * cos(t[j]) + I * a * r * sin(t[j]);
+        w[j] = (dt[j] / M_PI) * (a * r * cos(t[j]) + I * r * sin(t[j]));
+    }
+    free(t);
+    free(dt);
     return 0;
 }
 
-/* Rational filter rho(lambda) = Re sum_j w_j / (z_j - lambda): what one
- * contour pass multiplies each eigencomponent by (tool "[sd]feast_rational"). */
-int orc_rational(double emin, double emax, int ne, const double *lam, int m, double *f)
+/* Rational filter rho(lambda) = Re sum_j w_j / (z_j - lambda) of given
+ * nodes and weights: what one contour pass multiplies each eigencomponent by
+ * (tools "[sd]feast_rational", "[sd]feast_rationalx").                     */
+void orc_rationalx(int ne, const zc *z, const zc *w, const double *lam, int m, double *f)
 {
-    zc *z = malloc(sizeof(zc) * ne), *w = malloc(sizeof(zc) * ne);
-    if (orc_contour(emin, emax, ne, z, w)) { free(z); free(w); return -1; }
     for (int i = 0; i < m; ++i) {
         zc s = 0;
         for (int j = 0; j < ne; ++j) s += w[j] / (z[j] - lam[i]);
         f[i] = creal(s);
     }
+}
+
+int orc_rational(double emin, double emax, int ne, int integ, int ratio, const double *lam, int m, double *f)
+{
+    zc *z = malloc(sizeof(zc) * ne), *w = malloc(sizeof(zc) * ne);
+    if (orc_contour(emin, emax, ne, integ, ratio, z, w)) { free(z); free(w); return -1; }
+    orc_rationalx(ne, z, w, lam, m, f);
     free(z);
     free(w);
     return 0;
@@ -291,6 +321,9 @@ int orc_zheev_jacobi(int n, zc *a, int lda, double *w, zc *v, int ldv)
  *   E, X, res outputs of size m0, n x m0, m0 (first M are the eigenpairs in
  *             the interval, ascending)
  *   mode      0: full iteration; 1: return Q after one contour (info 4)
+ *   integ, ratio  fpm(16) (0 Gauss-Legendre, 1 trapezoidal) and fpm(18)
+ *             (ellipse ratio in percent), see orc_contour
+ *   zne, wne  custom nodes and weights (expert mode), or NULL
  * Returns info with the codes of Table "tab_info".                         */
 #define ORC_SPURIOUS_RES 0.1
 #define ORC_TRUNC 1e-14
@@ -299,7 +332,7 @@ int orc_zheev_jacobi(int n, zc *a, int lda, double *w, zc *v, int ldv)
 int orc_feast(int herm, int n, const zc *A, const zc *B, double emin, double emax,
               int *m0_io, int ne, double tol, int maxloop, int conv, int mode,
               const zc *X0, double *E, zc *X, double *res, int *M_out, int *loop_out,
-              double *epsout_out)
+              double *epsout_out, int integ, int ratio, const zc *zne, const zc *wne)
 {
     int m0 = m0_io ? *m0_io : 0;
     /* input checks, Table "tab_info" */
@@ -311,13 +344,22 @@ int orc_feast(int herm, int n, const zc *A, const zc *B, double emin, double ema
     if (maxloop < 0) return 104;
     if (conv != 0 && conv != 1) return 106;
     if (mode != 0 && mode != 1) return 114;
+    if (integ != 0 && integ != 1) return 116;
+    if (ratio < 1) return 118;
 
     const double alpha = fmax(fabs(emin), fabs(emax));
     const size_t nn = (size_t)n * n, nm = (size_t)n * m0;
     int info = 0;
 
     zc *z = malloc(sizeof(zc) * ne), *w = malloc(sizeof(zc) * ne);
-    orc_contour(emin, emax, ne, z, w);
+    if (zne && wne) {   /* expert mode: the caller's nodes and weights */
+        for (int j = 0; j < ne; ++j) {
+            z[j] = zne[j];
+            w[j] = wne[j];
+        }
+    } else {
+        orc_contour(emin, emax, ne, integ, ratio, z, w);
+    }
 
     zc *fac = malloc(sizeof(zc) * nn * ne);
     int *piv = malloc(sizeof(int) * (size_t)n * ne);

@@ -252,19 +252,55 @@ struct Contour {
     std::vector<double2> z, w;
 };
 
-static Contour make_contour(double emin, double emax, int ne)
+// Half-contour nodes and weights (section "Defining a search contour";
+// Table "tab_fpm" fpm(2), fpm(16), fpm(18)).  The contour through Emin and
+// Emax is z(t) = c + r cos t + i a r sin t (a = ellipse / 100), and the
+// filter is (1 / 2 pi i) times its integral of dz / (z - lambda): over the
+// upper half, doubled real part, that is (1 / pi) Re of the integral of
+// (a r cos t + i r sin t) / (z(t) - lambda) dt on [0, pi].  The rule on
+// [0, pi]: Gauss-Legendre (t = (pi/2)(1 - x), dt = (pi/2) omega) or the
+// trapezoidal midpoints t_j = pi (ne - j - 1/2) / ne with dt = pi / ne.
+// Nodes come in increasing real part.
+static Contour make_contour(double emin, double emax, int ne, int integration = 0, int ellipse = 100)
 {
-    std::vector<double> x, om;
-    gauss_legendre(ne, x, om);
+    // th: node parameter; f = dt / pi, written out per rule (omega / 2 for
+    // Gauss-Legendre, 1 / ne for the trapezoidal rule) so that the default
+    // circle's weights are formed exactly as 0.5 omega r e^{i th}
+    std::vector<double> th(ne), f(ne);
+    if (integration == 1) {
+        for (int j = 0; j < ne; ++j) {
+            th[j] = M_PI * (ne - j - 0.5) / ne;
+            f[j] = 1.0 / ne;
+        }
+    } else {
+        std::vector<double> x, om;
+        gauss_legendre(ne, x, om);
+        for (int j = 0; j < ne; ++j) {
+            th[j] = 0.5 * M_PI * (1.0 - x[j]);
+            f[j] = 0.5 * om[j];
+        }
+    }
     Contour c;
     c.z.resize(ne);
     c.w.resize(ne);
-    const double mid = 0.5 * (emin + emax), r = 0.5 * (emax - emin);
+    const double mid = 0.5 * (emin + emax), r = 0.5 * (emax - emin), a = ellipse / 100.0;
     for (int j = 0; j < ne; ++j) {
-        const double th = 0.5 * M_PI * (1.0 - x[j]);
-        const double ct = std::cos(th), st = std::sin(th);
-        c.z[j] = make_double2(mid + r * ct, r * st);
-        c.w[j] = make_double2(0.5 * om[j] * r * ct, 0.5 * om[j] * r * st);
+        const double ct = std::cos(th[j]), st = std::sin(th[j]);
+        c.z[j] = make_double2(mid + r * ct, a * r * st);
+        c.w[j] = make_double2(f[j] * a * r * ct, f[j] * r * st);
+    }
+    return c;
+}
+
+// Caller-supplied nodes and weights (the guide's expert mode, Zne / Wne).
+static Contour custom_contour(const feast_z *zne, const feast_z *wne, int ne)
+{
+    Contour c;
+    c.z.resize(ne);
+    c.w.resize(ne);
+    for (int j = 0; j < ne; ++j) {
+        c.z[j] = make_double2(zne[j].re, zne[j].im);
+        c.w[j] = make_double2(wne[j].re, wne[j].im);
     }
     return c;
 }
@@ -576,7 +612,8 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
     StageTimer tm(s);
     tm.start();
 
-    Contour ct = make_contour(pb.emin, pb.emax, ne);
+    Contour ct = o.Zne ? custom_contour(o.Zne, o.Wne, ne)
+                       : make_contour(pb.emin, pb.emax, ne, o.integration, o.ellipse);
     double2 *dz = static_cast<double2 *>(ws.get("z", sizeof(double2) * ne));
     FX_CHECK(hipMemcpyAsync(dz, ct.z.data(), sizeof(double2) * ne, hipMemcpyHostToDevice, s));
 
@@ -909,6 +946,9 @@ static int validate(int n, int m0, double emin, double emax, const feast_opts &o
     if (o.keep_factors != 0 && o.keep_factors != 1) return 110;
     if (o.mode != 0 && o.mode != 1) return 114;
     if (o.precision != 0 && o.precision != 1) return 140;
+    if (o.integration != 0 && o.integration != 1) return 116;   // Zolotarev (2) is not in this build
+    if (o.ellipse < 1) return 118;
+    if ((o.Zne == nullptr) != (o.Wne == nullptr)) return -113;
     if (o.refine != 0) return 141;   // per-solve refinement: not available in this build
     if (m0 > 4096) return 201;
     if (o.precision == 1 && n > lu_max_n<float>()) return 202;
@@ -1109,6 +1149,7 @@ struct Job {
     // server-owned host buffers
     std::vector<double> E, res;
     std::vector<unsigned char> X;
+    std::vector<feast_z> zne, wne;   // copies of custom contour nodes and weights
 };
 
 class Executor {
@@ -1237,33 +1278,26 @@ void feast_default_opts(feast_opts *o)
     o->verbose = 0;
     o->tol = 1e-12;
     o->seed = 0x5eedULL;
+    o->integration = 0;
+    o->ellipse = 100;
+    o->Zne = nullptr;
+    o->Wne = nullptr;
 }
 
 const char *feast_version(void) { return "feastx 0.1 (gfx950)"; }
 
-int feast_contour(double emin, double emax, int ne, feast_z *Zne, feast_z *Wne)
+static int contour_args(double emin, double emax, int ne, int integration, int ellipse)
 {
     if (ne < 1) return 102;
-    if (!(emin < emax)) return 200;
-    if (!Zne) return -104;
-    if (!Wne) return -105;
-    fx::Contour c = fx::make_contour(emin, emax, ne);
-    for (int j = 0; j < ne; ++j) {
-        Zne[j].re = c.z[j].x;
-        Zne[j].im = c.z[j].y;
-        Wne[j].re = c.w[j].x;
-        Wne[j].im = c.w[j].y;
-    }
+    if (integration != 0 && integration != 1) return 116;
+    if (ellipse < 1) return 118;
+    if (!(emin < emax) || !std::isfinite(emin) || !std::isfinite(emax)) return 200;
     return 0;
 }
 
-int feast_rational(double emin, double emax, int ne, const double *eig, int m, double *f)
+static void eval_rational(const fx::Contour &c, const double *eig, int m, double *f)
 {
-    if (ne < 1) return 102;
-    if (!(emin < emax)) return 200;
-    if (m < 0) return -105;
-    if (m > 0 && (!eig || !f)) return -104;
-    fx::Contour c = fx::make_contour(emin, emax, ne);
+    const int ne = (int)c.z.size();
     for (int i = 0; i < m; ++i) {
         double acc = 0.0;
         for (int j = 0; j < ne; ++j) {
@@ -1274,6 +1308,42 @@ int feast_rational(double emin, double emax, int ne, const double *eig, int m, d
         }
         f[i] = acc;
     }
+}
+
+int feast_contour(double emin, double emax, int ne, int integration, int ellipse, feast_z *Zne, feast_z *Wne)
+{
+    const int v = contour_args(emin, emax, ne, integration, ellipse);
+    if (v) return v;
+    if (!Zne) return -105;
+    if (!Wne) return -106;
+    fx::Contour c = fx::make_contour(emin, emax, ne, integration, ellipse);
+    for (int j = 0; j < ne; ++j) {
+        Zne[j].re = c.z[j].x;
+        Zne[j].im = c.z[j].y;
+        Wne[j].re = c.w[j].x;
+        Wne[j].im = c.w[j].y;
+    }
+    return 0;
+}
+
+int feast_rational(double emin, double emax, int ne, int integration, int ellipse, const double *eig, int m,
+                   double *f)
+{
+    const int v = contour_args(emin, emax, ne, integration, ellipse);
+    if (v) return v;
+    if (m < 0) return -107;
+    if (m > 0 && (!eig || !f)) return -108;
+    eval_rational(fx::make_contour(emin, emax, ne, integration, ellipse), eig, m, f);
+    return 0;
+}
+
+int feast_rationalx(const feast_z *Zne, const feast_z *Wne, int ne, const double *eig, int m, double *f)
+{
+    if (ne < 1) return 102;
+    if (!Zne || !Wne) return -101;
+    if (m < 0) return -105;
+    if (m > 0 && (!eig || !f)) return -106;
+    eval_rational(fx::custom_contour(Zne, Wne, ne), eig, m, f);
     return 0;
 }
 
@@ -1471,6 +1541,12 @@ int feast_server_submit(feast_server *srv, const feast_request *req, unsigned lo
     if (v) return v;
     j->args = fx::SolveArgs{cplx, r.n, r.A, r.lda, r.B, r.ldb, r.emin, r.emax, r.m0, j->X.data(), r.n,
                             j->E.data(), j->res.data(), 0, nullptr};
+    if (o.Zne) {   // the request's node arrays need not outlive the call
+        j->zne.assign(o.Zne, o.Zne + o.ne);
+        j->wne.assign(o.Wne, o.Wne + o.ne);
+        o.Zne = j->zne.data();
+        o.Wne = j->wne.data();
+    }
     j->opts = o;
     j->footprint = fx::footprint_bytes(cplx, r.n, r.m0, o, true);
     {

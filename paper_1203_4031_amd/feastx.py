@@ -27,7 +27,8 @@ class feast_opts(C.Structure):
     _fields_ = [("ne", C.c_int), ("maxloop", C.c_int), ("conv", C.c_int), ("x0", C.c_int),
                 ("keep_factors", C.c_int), ("precision", C.c_int), ("refine", C.c_int),
                 ("mode", C.c_int), ("verbose", C.c_int), ("tol", C.c_double),
-                ("seed", C.c_ulonglong)]
+                ("seed", C.c_ulonglong), ("integration", C.c_int), ("ellipse", C.c_int),
+                ("Zne", C.c_void_p), ("Wne", C.c_void_p)]
 
 
 class feast_stats(C.Structure):
@@ -89,8 +90,9 @@ def lib():
             f = getattr(L, name)
             f.argtypes = [C.c_int, vp, C.c_int, vp, C.c_int, C.c_double, C.c_double, ip, op, dp, vp,
                           C.c_int, ip, dp, ip, dp, vp]
-        L.feast_contour.argtypes = [C.c_double, C.c_double, C.c_int, vp, vp]
-        L.feast_rational.argtypes = [C.c_double, C.c_double, C.c_int, dp, C.c_int, dp]
+        L.feast_contour.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int, C.c_int, vp, vp]
+        L.feast_rational.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int, C.c_int, dp, C.c_int, dp]
+        L.feast_rationalx.argtypes = [vp, vp, C.c_int, dp, C.c_int, dp]
         L.feast_last_stats.argtypes = [C.POINTER(feast_stats)]
         L.feast_set_timing.argtypes = [C.c_int]
         L.feast_set_timing.restype = None
@@ -118,16 +120,38 @@ def default_opts() -> feast_opts:
     return o
 
 
+def _zarray(v):
+    v = np.asarray(v, dtype=np.complex128).ravel()
+    a = (feast_z * v.size)()
+    for i, x in enumerate(v):
+        a[i].re, a[i].im = float(x.real), float(x.imag)
+    return a
+
+
 def make_opts(ne=8, tol=1e-12, maxloop=20, conv=1, x0=None, keep_factors=1, precision="fp64",
-              refine=0, mode=0, verbose=0, seed=None) -> feast_opts:
+              refine=0, mode=0, verbose=0, seed=None, integration=0, ellipse=100, zne=None,
+              wne=None) -> feast_opts:
+    """Options (Table "tab_fpm"): integration = fpm(16) (0 Gauss-Legendre, 1
+    trapezoidal), ellipse = fpm(18) (percent), zne/wne = custom half-contour
+    nodes and weights (expert mode; ne is then their length)."""
     o = default_opts()
     o.ne, o.tol, o.maxloop, o.conv = ne, tol, maxloop, conv
     o.keep_factors, o.refine, o.mode, o.verbose = keep_factors, refine, mode, verbose
     o.precision = {"fp64": 0, "mixed": 1}[precision] if isinstance(precision, str) else precision
+    o.integration, o.ellipse = integration, ellipse
     if x0 is not None:
         o.x0 = int(bool(x0))
     if seed is not None:
         o.seed = seed
+    if (zne is None) != (wne is None):
+        raise ValueError("zne and wne go together")
+    if zne is not None:
+        za, wa = _zarray(zne), _zarray(wne)
+        if len(za) != len(wa):
+            raise ValueError("zne and wne differ in length")
+        o.ne = len(za)
+        o._keep = (za, wa)   # the arrays must outlive the call
+        o.Zne, o.Wne = C.addressof(za), C.addressof(wa)
     return o
 
 
@@ -212,21 +236,34 @@ def solve_device(A, B, emin, emax, m0, X, stream=None, **kw) -> Result:
     return Result(info, E[:k].copy(), X[:, :k], res[:k].copy(), M.value, k, loop.value, eps.value)
 
 
-def contour(emin, emax, ne):
+def contour(emin, emax, ne, integration=0, ellipse=100):
+    """Tool "[cz]feast_contour": half-contour nodes and weights."""
     z = (feast_z * ne)()
     w = (feast_z * ne)()
-    info = lib().feast_contour(emin, emax, ne, z, w)
+    info = lib().feast_contour(emin, emax, ne, integration, ellipse, z, w)
     if info:
         raise ValueError(f"feast_contour info {info}")
     return (np.array([v.re + 1j * v.im for v in z]), np.array([v.re + 1j * v.im for v in w]))
 
 
-def rational(emin, emax, ne, lam):
+def rational(emin, emax, ne, lam, integration=0, ellipse=100):
+    """Tool "[sd]feast_rational": the filter at the points lam."""
     lam = np.ascontiguousarray(lam, dtype=np.float64)
     f = np.zeros(lam.size)
-    info = lib().feast_rational(emin, emax, ne, _dp(lam), lam.size, _dp(f))
+    info = lib().feast_rational(emin, emax, ne, integration, ellipse, _dp(lam), lam.size, _dp(f))
     if info:
         raise ValueError(f"feast_rational info {info}")
+    return f
+
+
+def rationalx(zne, wne, lam):
+    """Tool "[sd]feast_rationalx": the filter of custom nodes and weights."""
+    za, wa = _zarray(zne), _zarray(wne)
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    f = np.zeros(lam.size)
+    info = lib().feast_rationalx(za, wa, len(za), _dp(lam), lam.size, _dp(f))
+    if info:
+        raise ValueError(f"feast_rationalx info {info}")
     return f
 
 

@@ -33,31 +33,48 @@ def test_default_opts_follow_feastinit():
 
 
 @pytest.mark.parametrize("ne", [1, 2, 3, 8, 16, 24])
-def test_contour_tool_matches_oracle(orc, ne):
-    z, w = feastx.contour(-0.7, 2.3, ne)
-    zo, wo = orc.contour(-0.7, 2.3, ne)
+@pytest.mark.parametrize("integration,ellipse", [(0, 100), (1, 100), (0, 50), (1, 200)])
+def test_contour_tool_matches_oracle(orc, ne, integration, ellipse):
+    z, w = feastx.contour(-0.7, 2.3, ne, integration, ellipse)
+    zo, wo = orc.contour(-0.7, 2.3, ne, integration, ellipse)
     assert np.abs(z - zo).max() < 1e-15 * 4 and np.abs(w - wo).max() < 1e-15 * 4
 
 
-def test_rational_tool_matches_oracle(orc):
+@pytest.mark.parametrize("integration,ellipse", [(0, 100), (1, 100), (1, 50)])
+def test_rational_tool_matches_oracle(orc, integration, ellipse):
     lam = np.linspace(-3, 5, 41)
-    assert np.abs(feastx.rational(0.0, 2.0, 8, lam) - orc.rational(0.0, 2.0, 8, lam)).max() < 1e-14
+    f = feastx.rational(0.0, 2.0, 8, lam, integration, ellipse)
+    assert np.abs(f - orc.rational(0.0, 2.0, 8, lam, integration, ellipse)).max() < 1e-14
+    z, w = feastx.contour(0.0, 2.0, 8, integration, ellipse)
+    assert np.abs(feastx.rationalx(z, w, lam) - f).max() < 1e-15
+
+
+@pytest.mark.parametrize("integration,ellipse,code", [(2, 100, 116), (-1, 100, 116), (0, 0, 118)])
+def test_contour_tool_argument_errors(integration, ellipse, code):
+    z = (feastx.feast_z * 4)()
+    w = (feastx.feast_z * 4)()
+    assert feastx.lib().feast_contour(0.0, 1.0, 4, integration, ellipse, z, w) == code
 
 
 @pytest.mark.parametrize("kw,code", [
     (dict(n=0), 202), (dict(m0=0), 201), (dict(m0=5), 201), (dict(emin=1.0, emax=1.0), 200),
     (dict(ne=0), 102), (dict(tol=0.0), 103), (dict(maxloop=-1), 104), (dict(conv=3), 106),
-    (dict(mode=2), 114), (dict(precision=7), 140),
+    (dict(mode=2), 114), (dict(precision=7), 140), (dict(integration=2), 116),
+    (dict(ellipse=0), 118), (dict(half_custom=True), -113),
 ])
 def test_argument_errors_need_no_gpu(kw, code):
     """Argument checks run before any device call (Table "tab_info" codes)."""
     args = dict(n=4, m0=2, emin=-1.0, emax=1.0, ne=8, tol=1e-12, maxloop=20, conv=1, mode=0,
-                precision=0)
+                precision=0, integration=0, ellipse=100, half_custom=False)
     args.update(kw)
     n = max(args["n"], 1)
     A = np.eye(n, order="F")
     o = feastx.make_opts(ne=args["ne"], tol=args["tol"], maxloop=args["maxloop"],
-                         conv=args["conv"], mode=args["mode"], precision=args["precision"])
+                         conv=args["conv"], mode=args["mode"], precision=args["precision"],
+                         integration=args["integration"], ellipse=args["ellipse"])
+    nodes = (feastx.feast_z * 8)()
+    if args["half_custom"]:   # custom nodes without weights
+        o.Zne = C.addressof(nodes)
     E = np.zeros(8)
     res = np.zeros(8)
     X = np.zeros((n, 8), order="F")

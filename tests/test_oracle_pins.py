@@ -89,6 +89,89 @@ def test_filter_is_the_contour_integral(orc):
     assert np.allclose(orc.rational(emin, emax, 48, lam), ref, atol=1e-10)
 
 
+# ------------------------------------------ other rules and contours (fpm(16), fpm(18))
+@pytest.mark.parametrize("ne", [1, 2, 3, 5, 8, 16])
+def test_trapezoidal_circle_closed_form(orc, ne):
+    """Equally spaced midpoint nodes on the circle give the rational filter
+    1 / (1 + t^(2 ne)), t = (lambda - c)/r, in closed form (sum of the
+    partial fractions of 1/(1 + s^(2 ne)) over its 2 ne roots)."""
+    emin, emax = -0.4, 2.6
+    c, r = 1.1, 1.5
+    t = np.array([0.0, 0.3, -0.3, 0.9, -0.9, 1.0, -1.0, 1.2, -1.7, 3.0])
+    ref = 1.0 / (1.0 + t ** (2 * ne))
+    assert np.allclose(orc.rational(emin, emax, ne, c + t * r, integration=1), ref, rtol=0, atol=64 * U)
+
+
+@pytest.mark.parametrize("integration", [0, 1])
+@pytest.mark.parametrize("ratio", [50, 200])
+def test_ellipse_geometry(orc, integration, ratio):
+    """Nodes on the upper half of the ellipse through Emin and Emax with
+    vertical semi-axis a r, and each weight along the contour's outward
+    normal i.e. -i times the tangent direction (the orientation dz/(2 pi i))."""
+    emin, emax, ne = -0.3, 1.7, 9
+    z, w = orc.contour(emin, emax, ne, integration, ratio)
+    c, r, a = 0.5 * (emin + emax), 0.5 * (emax - emin), ratio / 100.0
+    assert np.allclose(((z.real - c) / r) ** 2 + (z.imag / (a * r)) ** 2, 1.0, atol=16 * U)
+    assert (z.imag > 0).all() and (np.diff(z.real) > 0).all()
+    th = np.arctan2(z.imag / a, z.real - c)                 # the parameter of each node
+    tangent = -r * np.sin(th) + 1j * a * r * np.cos(th)
+    cosang = (w * np.conj(-1j * tangent)).real / (np.abs(w) * np.abs(tangent))
+    assert np.allclose(cosang, 1.0, atol=1e-12)
+
+
+@pytest.mark.parametrize("integration,ne", [(0, 56), (1, 400)])
+@pytest.mark.parametrize("ratio", [50, 100, 200])
+def test_ellipse_filter_is_the_contour_integral(orc, integration, ne, ratio):
+    """With many nodes the filter tends to (1 / 2 pi i) times the closed
+    contour integral of 1/(z - lambda) around the ellipse, i.e. 1 inside and
+    0 outside, computed here on the full ellipse with a fine independent rule."""
+    emin, emax = 0.0, 2.0
+    c, r, a = 1.0, 1.0, ratio / 100.0
+    lam = np.array([0.4, 1.0, 1.5, -1.0, 3.2, 5.0])
+    th = np.linspace(0, 2 * np.pi, 40001)[:-1]
+    zz = c + r * np.cos(th) + 1j * a * r * np.sin(th)
+    dz = -r * np.sin(th) + 1j * a * r * np.cos(th)
+    # (1 / 2 pi i) int dz/(z - l) = mean over theta of dz/dtheta / (i (z - l))
+    ref = np.array([(dz / (1j * (zz - l))).mean().real for l in lam])
+    assert np.allclose(ref, [1, 1, 1, 0, 0, 0], atol=1e-9)
+    f = orc.rational(emin, emax, ne, lam, integration=integration, ellipse=ratio)
+    assert np.allclose(f, ref, atol=1e-8)
+
+
+@pytest.mark.parametrize("integration,ratio", [(1, 100), (0, 50), (1, 200)])
+def test_other_contours_find_the_same_eigenpairs(orc, integration, ratio):
+    """The contour only changes the filter, not the answer: FEAST with the
+    trapezoidal rule or an ellipse finds the brute-force eigenvalues of a
+    small pencil, with residuals below tol."""
+    p = W.dense_real_generalized(40, count=7, seed=151, tol=1e-12)
+    r = orc.feast(p.A, p.B, p.emin, p.emax, p.m0, 12, p.tol, p.X0, integration=integration,
+                  ellipse=ratio)
+    assert r.info == 0
+    allev = sl.eigh(p.A, p.B, eigvals_only=True)
+    inside = allev[(allev >= p.emin) & (allev <= p.emax)]
+    alpha = max(abs(p.emin), abs(p.emax))
+    assert r.M == inside.size
+    assert np.abs(r.E[:r.M] - inside).max() < 1e-12 * alpha
+    assert (r.res[:r.M] < p.tol).all()
+
+
+def test_custom_nodes_are_used_as_given(orc):
+    """Expert mode: passing the trapezoidal nodes as custom nodes gives the
+    trapezoidal run exactly; passing a rule the solver would not pick (an
+    ellipse) changes the iterates but not the eigenvalues."""
+    p = W.dense_real_generalized(40, count=7, seed=152, tol=1e-12)
+    z, w = orc.contour(p.emin, p.emax, 10, 1, 100)
+    a = orc.feast(p.A, p.B, p.emin, p.emax, p.m0, 10, p.tol, p.X0, integration=1)
+    b = orc.feast(p.A, p.B, p.emin, p.emax, p.m0, 10, p.tol, p.X0, zne=z, wne=w)
+    assert a.info == b.info == 0 and a.M == b.M and a.loop == b.loop
+    assert np.array_equal(a.E, b.E) and np.array_equal(a.res, b.res)
+    z2, w2 = orc.contour(p.emin, p.emax, 10, 0, 60)
+    c = orc.feast(p.A, p.B, p.emin, p.emax, p.m0, 10, p.tol, p.X0, zne=z2, wne=w2)
+    assert c.info == 0 and c.M == a.M
+    assert np.abs(c.E[:c.M] - a.E[:a.M]).max() < 1e-12
+    assert np.allclose(orc.rationalx(z, w, [0.1, 7.0]), orc.rational(p.emin, p.emax, 10, [0.1, 7.0], 1), atol=0)
+
+
 # --------------------------------------------------------- dense linear algebra
 def _rand(n, m, seed, cplx=True):
     rng = np.random.default_rng(seed)
@@ -376,7 +459,7 @@ def test_info_sizes(orc):
         m[0] = m0
         return lib.orc_feast(0, n, z.ctypes.data, None, -1.0, 1.0, ip(m), 8, 1e-12, 5, 1, 0,
                              z.ctypes.data, dp(out[0]), out[1].ctypes.data, dp(out[2]),
-                             ip(out[3]), ip(out[4]), dp(out[5]))
+                             ip(out[3]), ip(out[4]), dp(out[5]), 0, 100, None, None)
     assert call(0, 1) == 202
     assert call(2, 0) == 201
     assert call(2, 3) == 201
