@@ -82,6 +82,30 @@ def run_steps(feastx, torch, A, B, X0, X, p, precision, steps, timing):
     return times, results, lu
 
 
+def count_estimate(feastx, torch, W, A, B, p, expected, steps=5):
+    """Stochastic count estimate (fpm(14) = 2) on the same pencil with the
+    guide's suggested small settings: M0 = 16 +-1 probes, Ne = 3, one contour."""
+    m0, ne = 16, 3
+    P0 = feastx.fortran_tensor(W.sign_probes(p.n, m0, seed=2106))
+    P = P0.clone(memory_format=torch.contiguous_format).t().contiguous().t()
+    stream = torch.cuda.current_stream()
+    times, r = [], None
+    for i in range(steps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P.copy_(P0)
+        r = feastx.solve_device(A, B, p.emin, p.emax, m0, P, stream=stream, x0=True, ne=ne, tol=p.tol,
+                                precision="mixed", mode=2)
+        torch.cuda.synchronize()
+        if i:
+            times.append(time.perf_counter() - t0)
+        if r.info != 5:
+            raise SystemExit(f"count estimate failed: info {r.info}")
+    return {"m0": m0, "ne": ne, "precision": "mixed", "ms": float(np.mean(times)) * 1e3, "estimate": r.M,
+            "running_average_last": float(r.res[-1]), "count": expected,
+            "sampling_sd": float(np.sqrt(2.0 * expected / m0))}
+
+
 def check(results, p, expected_m):
     for r in results:
         if r.info != 0:
@@ -248,6 +272,9 @@ def main():
                          "note": "update_*: the LU's complex64 product launches alone (8 flops per complex "
                                  "multiply-add); factor_*: Ne (8/3) N^3 over the whole factor stage, timed with "
                                  "per-launch events on (so slightly slow)"}
+    out["count_estimate"] = count_estimate(feastx, torch, W, A, B, p, expected)
+    log(f"count estimate: {out['count_estimate']['estimate']} (count {expected}) in "
+        f"{out['count_estimate']['ms']:.1f} ms")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, loops)
     print(json.dumps(out), flush=True)

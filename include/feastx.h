@@ -17,7 +17,8 @@
  *   - The return value is `info` with the codes of the guide's Table
  *     "tab_info": 0 success; 1 no eigenvalue in the interval; 2 no
  *     convergence within maxloop; 3 subspace too small (M0 <= M); 4 only the
- *     subspace Q was returned (mode 1); 200 bad interval; 201 bad M0;
+ *     subspace Q was returned (mode 1); 5 only the stochastic estimate of
+ *     the eigenvalue count was returned (mode 2); 200 bad interval; 201 bad M0;
  *     202 bad N; 100+i bad option i (fpm numbering: 102 ne, 103 tol,
  *     104 maxloop, 105 x0, 106 conv, 110 keep_factors, 114 mode, 140
  *     precision, 141 refine); -1 device allocation failed; -2 the factorisation
@@ -25,7 +26,8 @@
  *     eigenproblem failed (B not positive definite); -4 other GPU runtime
  *     error; -(100+i) argument i is invalid (e.g. a NULL pointer).
  *     No exception crosses the interface.
- *   - Outputs E, X, res are valid for info in {0, 2, 3}.  Their first M
+ *   - Outputs E, X, res are valid for info in {0, 2, 3} (for info 5 see
+ *     feast_opts.mode).  Their first M
  *     entries are the eigenpairs inside [Emin, Emax], ascending; then the
  *     remaining Ritz pairs outside the interval, ascending; spurious pairs
  *     (inside the interval but with residual > 0.1) come last with res = -1
@@ -58,7 +60,14 @@ typedef struct {
                             FP64 residual correction; everything else FP64) */
     int refine;       /* mixed only. 0: residual-correction form from the second loop on
                          (default); s > 0: s steps of per-solve FP64 iterative refinement */
-    int mode;         /* [fpm(14)] 0: normal; 1: return Q after one contour in X (info 4) */
+    int mode;         /* [fpm(14)] 0: normal; 1: return Q after one contour in X (info 4);
+                         2: stochastic estimate of the number of eigenvalues in the interval
+                         (section "Stochastic estimate", info 5): one contour pass over the M0
+                         probe columns of X (the caller's with x0 = 1, else random +-1 entries
+                         drawn from seed); sample c is N Re(x_c^H q_c) / (x_c^H x_c) with q_c the
+                         filtered probe; res[c] returns the running average of samples 0..c, M
+                         the nearest integer to res[M0-1] (at least 0), X the filtered probes,
+                         E zeros.  A small M0 (about 10) and Ne (about 3) suffice. */
     int verbose;      /* [fpm(1)] 1: print one line per loop to stderr */
     double tol;       /* [fpm(3)] convergence tolerance, > 0; default 1e-12 */
     unsigned long long seed; /* seed of the random start subspace (x0 = 0) */

@@ -312,6 +312,32 @@ int orc_zheev_jacobi(int n, zc *a, int lda, double *w, zc *v, int ldv)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Stochastic estimate of the number of eigenvalues in the interval (section
+ * "Stochastic estimate"; the method of the Di Napoli-Polizzi-Saad paper it
+ * cites).  One contour pass applied to probe vectors x_c gives
+ * q_c = rho(B^{-1} A) x_c, whose trace is sum_i rho(lambda_i), about the count.
+ * Each probe gives the sample e_c = n Re(x_c^H q_c) / (x_c^H x_c): the
+ * Hutchinson estimator when x_c has entries +-1 (then x_c^H x_c = n), and
+ * unbiased for any probe distribution invariant under rotations.
+ *   res[c]   running average (e_0 + ... + e_c) / (c + 1), summed in order
+ *   *M_out   nearest integer to res[m0 - 1], at least 0                    */
+void orc_count_estimate(int n, int m0, const zc *X0, const zc *Q, double *res, int *M_out)
+{
+    double sum = 0.0;
+    for (int c = 0; c < m0; ++c) {
+        double num = 0.0, den = 0.0;
+        for (int i = 0; i < n; ++i) {
+            const zc x = X0[IDX(i, c, n)];
+            num += creal(conj(x) * Q[IDX(i, c, n)]);
+            den += creal(x) * creal(x) + cimag(x) * cimag(x);
+        }
+        sum += den > 0.0 ? n * num / den : 0.0;
+        res[c] = sum / (c + 1);
+    }
+    const double est = floor(res[m0 - 1] + 0.5);
+    *M_out = est > 0.0 ? (int)est : 0;
+}
+
 /* The FEAST iteration for a dense Hermitian pencil (A, B), B = NULL for the
  * standard problem.  Arguments follow Table "tab_common":
  *   herm      0: real symmetric (A, B, X0 real, stored with zero imaginary
@@ -320,7 +346,9 @@ int orc_zheev_jacobi(int n, zc *a, int lda, double *w, zc *v, int ldv)
  *   X0        (n x m0) start subspace (the caller draws it, fpm(5) style)
  *   E, X, res outputs of size m0, n x m0, m0 (first M are the eigenpairs in
  *             the interval, ascending)
- *   mode      0: full iteration; 1: return Q after one contour (info 4)
+ *   mode      0: full iteration; 1: return Q after one contour (info 4);
+ *             2: stochastic estimate of the eigenvalue count (info 5), see
+ *             orc_count_estimate
  *   integ, ratio  fpm(16) (0 Gauss-Legendre, 1 trapezoidal) and fpm(18)
  *             (ellipse ratio in percent), see orc_contour
  *   zne, wne  custom nodes and weights (expert mode), or NULL
@@ -343,7 +371,7 @@ int orc_feast(int herm, int n, const zc *A, const zc *B, double emin, double ema
     if (!(tol > 0.0)) return 103;
     if (maxloop < 0) return 104;
     if (conv != 0 && conv != 1) return 106;
-    if (mode != 0 && mode != 1) return 114;
+    if (mode < 0 || mode > 2) return 114;
     if (integ != 0 && integ != 1) return 116;
     if (ratio < 1) return 118;
 
@@ -412,6 +440,15 @@ int orc_feast(int herm, int n, const zc *A, const zc *B, double emin, double ema
                 orc_zgetrs('C', n, m0, F, n, pv, Y, n);
                 for (size_t e = 0; e < (size_t)n * m0; ++e) Q[e] += 0.5 * conj(w[j]) * Y[e];
             }
+        }
+        if (mode == 2) {
+            orc_count_estimate(n, m0, X0, Q, res, M_out);
+            memcpy(X, Q, sizeof(zc) * (size_t)n * m0);
+            for (int c = 0; c < m0; ++c) E[c] = 0.0;
+            info = 5;
+            *loop_out = 0;
+            *epsout_out = 1.0;
+            goto done;
         }
         if (mode == 1) {
             memcpy(X, Q, sizeof(zc) * (size_t)n * m0);

@@ -670,7 +670,8 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
         hipLaunchKernelGGL((copy_block_kernel<CPLX>), grid1(nm), dim3(256), 0, s, n, m0,
                            reinterpret_cast<const E *>(pb.X), pb.ldx, X, (long)n);
     } else {
-        hipLaunchKernelGGL((random_start_kernel<CPLX>), grid1(nm), dim3(256), 0, s, n, m0, o.seed, X, (long)n);
+        hipLaunchKernelGGL((random_start_kernel<CPLX>), grid1(nm), dim3(256), 0, s, n, m0, o.seed,
+                           o.mode == 2 ? 1 : 0, X, (long)n);
     }
     FX_LAUNCH_CHECK();
     tm.mark(&st.t_shift);
@@ -773,6 +774,34 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
         FX_CHECK(hipStreamSynchronize(s));   // host vectors above are reused next loop
         tm.mark(&st.t_accum);
 
+        if (o.mode == 2) {
+            // stochastic count estimate from this one contour pass: samples,
+            // running averages into res, the estimate as M (info 5)
+            double *samp = static_cast<double *>(ws.get("cnt_samp", sizeof(double) * m0));
+            int *dest = static_cast<int *>(ws.get("cnt_est", sizeof(int)));
+            int *h_est = static_cast<int *>(ws.pinned("h_cnt_est", sizeof(int)));
+            hipLaunchKernelGGL((count_sample_kernel<CPLX>), dim3(m0), dim3(256), 0, s, n, X, (long)n, Q, (long)n,
+                               samp);
+            hipLaunchKernelGGL(count_mean_kernel, dim3(1), dim3(1024), 0, s, m0, samp, res, dest);
+            hipLaunchKernelGGL((copy_block_kernel<CPLX>), grid1(cur_nm), dim3(256), 0, s, n, m0, Q, (long)n,
+                               reinterpret_cast<E *>(pb.X), pb.ldx);
+            FX_LAUNCH_CHECK();
+            FX_CHECK(hipMemcpyAsync(h_res, res, sizeof(double) * m0, hipMemcpyDeviceToHost, s));
+            FX_CHECK(hipMemcpyAsync(h_est, dest, sizeof(int), hipMemcpyDeviceToHost, s));
+            FX_CHECK(hipStreamSynchronize(s));
+            out.M = *h_est;
+            out.loop = 0;
+            out.m0 = m0;
+            out.epsout = 1.0;
+            out.E.assign(m0, 0.0);
+            out.res.assign(h_res, h_res + m0);
+            tm.mark(&st.t_total);
+            tm.flush();
+            st.loops = 1;
+            st.m0_final = m0;
+            st_out = st;
+            return 5;
+        }
         if (o.mode == 1) {
             hipLaunchKernelGGL((copy_block_kernel<CPLX>), grid1(cur_nm), dim3(256), 0, s, n, m0, Q, (long)n,
                                reinterpret_cast<E *>(pb.X), pb.ldx);
@@ -944,7 +973,7 @@ static int validate(int n, int m0, double emin, double emax, const feast_opts &o
     if (o.x0 != 0 && o.x0 != 1) return 105;
     if (o.conv != 0 && o.conv != 1) return 106;
     if (o.keep_factors != 0 && o.keep_factors != 1) return 110;
-    if (o.mode != 0 && o.mode != 1) return 114;
+    if (o.mode < 0 || o.mode > 2) return 114;
     if (o.precision != 0 && o.precision != 1) return 140;
     if (o.integration != 0 && o.integration != 1) return 116;   // Zolotarev (2) is not in this build
     if (o.ellipse < 1) return 118;
@@ -1015,7 +1044,7 @@ struct SolveOut {
 static void copy_outputs(const Result &out, int info, const SolveArgs &a, SolveOut &so)
 {
     so.info = info;
-    if (info == 0 || info == 1 || info == 2 || info == 3) {
+    if (info == 0 || info == 1 || info == 2 || info == 3 || info == 5) {
         for (int i = 0; i < out.m0; ++i) {
             a.E[i] = out.E[i];
             a.res[i] = out.res[i];
@@ -1059,8 +1088,8 @@ static void solve_in(Workspace &ws, const feast_opts &o, const SolveArgs &a, Sol
         Problem pb{N, static_cast<const double *>(dA), N, static_cast<const double *>(dB), N, a.emin, a.emax, a.m0,
                    static_cast<double *>(dX), N};
         info = dispatch(a.cplx, pb, o, s, ws, out, so.st);
-        if (info == 0 || info == 1 || info == 2 || info == 3 || info == 4) {
-            const int mo = (info == 4) ? a.m0 : out.m0;
+        if (info == 0 || info == 1 || info == 2 || info == 3 || info == 4 || info == 5) {
+            const int mo = (info == 4 || info == 5) ? a.m0 : out.m0;
             FX_CHECK(hipMemcpy2DAsync(a.X, es * a.ldx, dX, es * N, es * N, mo, hipMemcpyDeviceToHost, s));
             FX_CHECK(hipStreamSynchronize(s));
         }
@@ -1381,7 +1410,7 @@ static int solve_single(bool cplx, int device, int N, const void *A, int lda, co
     fx::g_ws.lookahead = true;
     fx::solve_in(fx::g_ws, o, a, so);
     fx::g_stats = so.st;
-    if (so.info == 0 || so.info == 1 || so.info == 2 || so.info == 3 || so.info == 4) {
+    if (so.info == 0 || so.info == 1 || so.info == 2 || so.info == 3 || so.info == 4 || so.info == 5) {
         *M = so.M;
         *M0 = so.m0;
         if (loop) *loop = so.loop;

@@ -142,9 +142,11 @@ __global__ __launch_bounds__(256) void gather_cols_kernel(int n, int ncols, cons
 }
 
 // Seeded start subspace: real uniform(-1, 1), one splitmix64 draw per entry
-// (counter = column-major index).
+// (counter = column-major index).  With signs != 0 each entry is the sign of
+// that draw, -1 below the middle of [-1, 1) and +1 from it on (probe
+// vectors of the count estimate).
 template <bool CPLX>
-__global__ __launch_bounds__(256) void random_start_kernel(int n, int ncols, unsigned long long seed,
+__global__ __launch_bounds__(256) void random_start_kernel(int n, int ncols, unsigned long long seed, int signs,
                                                            typename jelem<CPLX>::type *__restrict__ X, long ldx)
 {
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -155,7 +157,71 @@ __global__ __launch_bounds__(256) void random_start_kernel(int n, int ncols, uns
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     z ^= z >> 31;
     const double u = (double)(z >> 11) * (1.0 / 9007199254740992.0);
-    jstore<CPLX>(X, i + (long)c * ldx, make_double2(2.0 * u - 1.0, 0.0));
+    const double v = 2.0 * u - 1.0;
+    jstore<CPLX>(X, i + (long)c * ldx, make_double2(signs ? (v < 0.0 ? -1.0 : 1.0) : v, 0.0));
+}
+
+// Stochastic count estimate (section "Stochastic estimate"): one contour pass
+// maps probe x_c to q_c = rho(B^{-1} A) x_c, and the trace of rho(B^{-1} A)
+// is sum_i rho(lambda_i), about the number of eigenvalues in the interval.
+// Probe c gives the sample e_c = n Re(x_c^H q_c) / (x_c^H x_c), the
+// Hutchinson estimator for +-1 probes.  One block per column.
+template <bool CPLX>
+__global__ __launch_bounds__(256) void count_sample_kernel(int n, const typename jelem<CPLX>::type *__restrict__ X,
+                                                           long ldx, const typename jelem<CPLX>::type *__restrict__ Q,
+                                                           long ldq, double *__restrict__ samp)
+{
+    const int c = blockIdx.x, tid = threadIdx.x;
+    double num = 0.0, den = 0.0;
+    for (int i = tid; i < n; i += 256) {
+        const double2 x = jload<CPLX>(X, i + (long)c * ldx), q = jload<CPLX>(Q, i + (long)c * ldq);
+        num += x.x * q.x + x.y * q.y;
+        den += x.x * x.x + x.y * x.y;
+    }
+    __shared__ double sn[4], sd[4];
+    num = wave_sum(num);
+    den = wave_sum(den);
+    if ((tid & 63) == 0) {
+        sn[tid >> 6] = num;
+        sd[tid >> 6] = den;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const double N = sn[0] + sn[1] + sn[2] + sn[3], D = sd[0] + sd[1] + sd[2] + sd[3];
+        samp[c] = D > 0.0 ? (double)n * N / D : 0.0;
+    }
+}
+
+// Running averages res[c] = (e_0 + ... + e_c) / (c + 1) of the samples, and
+// the estimate: the nearest integer to res[m - 1], at least 0.  One block of
+// 1024 threads scans the samples in chunks of 1024 (Hillis-Steele in LDS),
+// carrying each chunk's total into the next.
+__global__ __launch_bounds__(1024) void count_mean_kernel(int m, const double *__restrict__ samp,
+                                                          double *__restrict__ res, int *__restrict__ est)
+{
+    __shared__ double sh[2][1024];
+    const int tid = threadIdx.x;
+    double carry = 0.0;
+    for (int base = 0; base < m; base += 1024) {
+        const int i = base + tid;
+        int cur = 0;
+        sh[0][tid] = i < m ? samp[i] : 0.0;
+        __syncthreads();
+        for (int d = 1; d < 1024; d <<= 1) {
+            const double v = sh[cur][tid] + (tid >= d ? sh[cur][tid - d] : 0.0);
+            sh[cur ^ 1][tid] = v;
+            cur ^= 1;
+            __syncthreads();
+        }
+        const double incl = carry + sh[cur][tid];
+        if (i < m) res[i] = incl / (double)(i + 1);
+        carry += sh[cur][1023];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const double e = floor(res[m - 1] + 0.5);
+        *est = e > 0.0 ? (int)e : 0;
+    }
 }
 
 // Copy an n x ncols FP64 block between leading dimensions.

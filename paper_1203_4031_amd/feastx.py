@@ -193,7 +193,7 @@ def solve(A, B, emin, emax, m0, X0=None, **kw) -> Result:
     info = f(n, A.ctypes.data, n, None if Bf is None else Bf.ctypes.data, n, float(emin), float(emax),
              C.byref(m0c), C.byref(o), _dp(E), X.ctypes.data, n, C.byref(M), _dp(res),
              C.byref(loop), C.byref(eps))
-    k = m0c.value if info != 4 else m0
+    k = m0c.value if info not in (4, 5) else m0
     return Result(info, E[:k].copy(), X[:, :k].copy(order="F"), res[:k].copy(), M.value, k,
                   loop.value, eps.value)
 
@@ -232,7 +232,7 @@ def solve_device(A, B, emin, emax, m0, X, stream=None, **kw) -> Result:
              n if B is None else B.stride(1), float(emin), float(emax), C.byref(m0c), C.byref(o),
              _dp(E), X.data_ptr(), X.stride(1), C.byref(M), _dp(res), C.byref(loop),
              C.byref(eps), C.c_void_p(stream.cuda_stream))
-    k = m0c.value if info != 4 else m0
+    k = m0c.value if info not in (4, 5) else m0
     return Result(info, E[:k].copy(), X[:, :k], res[:k].copy(), M.value, k, loop.value, eps.value)
 
 
@@ -313,7 +313,7 @@ def solve_batched(problems, concurrency=4, **kw) -> list[Result]:
         raise ValueError(f"feast_solve_batched: {rc}")
     out = []
     for (A, Bf, X, E, res), j in zip(keep, jobs):
-        k = j.m0_out if j.info != 4 else j.m0
+        k = j.m0_out if j.info not in (4, 5) else j.m0
         r = Result(j.info, E[:k].copy(), X[:, :k].copy(order="F"), res[:k].copy(), j.M, k, j.loop,
                    j.epsout)
         r.ms = j.ms

@@ -72,6 +72,12 @@ def start_subspace(n: int, m0: int, seed: int) -> np.ndarray:
     return np.asfortranarray(_rng(seed).uniform(-1.0, 1.0, size=(n, m0)))
 
 
+def sign_probes(n: int, m0: int, seed: int) -> np.ndarray:
+    """Probe vectors for the eigenvalue-count estimate: independent +-1
+    entries with equal probability, (n, m0), Fortran order."""
+    return np.asfortranarray(np.where(_rng(seed).random((n, m0)) < 0.5, -1.0, 1.0))
+
+
 def pick_interval(spectrum: np.ndarray, count: int, centre_index: int | None = None):
     """Interval holding ``count`` eigenvalues with the widest end gaps.
 

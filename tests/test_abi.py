@@ -59,7 +59,7 @@ def test_contour_tool_argument_errors(integration, ellipse, code):
 @pytest.mark.parametrize("kw,code", [
     (dict(n=0), 202), (dict(m0=0), 201), (dict(m0=5), 201), (dict(emin=1.0, emax=1.0), 200),
     (dict(ne=0), 102), (dict(tol=0.0), 103), (dict(maxloop=-1), 104), (dict(conv=3), 106),
-    (dict(mode=2), 114), (dict(precision=7), 140), (dict(integration=2), 116),
+    (dict(mode=3), 114), (dict(mode=-1), 114), (dict(precision=7), 140), (dict(integration=2), 116),
     (dict(ellipse=0), 118), (dict(half_custom=True), -113),
 ])
 def test_argument_errors_need_no_gpu(kw, code):

@@ -181,6 +181,86 @@ def _rand(n, m, seed, cplx=True):
     return np.asfortranarray(a)
 
 
+# ------------------------------------------------ stochastic count estimate
+def _filter_matrix(A, B, rho):
+    """rho(B^{-1} A) = V diag(rho(lambda)) V^H B from the B-orthonormal
+    eigenvectors V of the whole pencil (LAPACK through scipy)."""
+    lam, V = sl.eigh(A, B)
+    return lam, (V * rho(lam)) @ V.conj().T @ B
+
+
+@pytest.mark.parametrize("herm", [False, True])
+@pytest.mark.parametrize("integration,ne", [(1, 4), (0, 8)])
+def test_count_estimate_with_identity_probes_is_the_trace(orc, herm, integration, ne):
+    """Probes e_1..e_n (M0 = n) make sample c equal to n P_cc, with P the
+    filter matrix rho(B^{-1} A), so res[c] is the running mean of n P_cc and
+    res[n-1] the trace sum_i rho(lambda_i) (section "Stochastic estimate").
+    rho is the trapezoidal circle's closed form 1/(1 + t^(2 ne)), or the
+    Gauss-Legendre filter through the (separately pinned) rational tool."""
+    n = 24
+    if herm:
+        p = W.dense_complex_hermitian(n, count=5, seed=171, ne=ne, nclusters=2)
+    else:
+        p = W.dense_real_generalized(n, count=5, seed=172)
+    c, r = 0.5 * (p.emin + p.emax), 0.5 * (p.emax - p.emin)
+    if integration == 1:
+        rho = lambda x: 1.0 / (1.0 + ((x - c) / r) ** (2 * ne))
+    else:
+        rho = lambda x: orc.rational(p.emin, p.emax, ne, np.asarray(x, float))
+    lam, P = _filter_matrix(p.A, p.B, rho)
+    X0 = np.eye(n, dtype=np.complex128 if herm else np.float64)
+    out = orc.feast(p.A, p.B, p.emin, p.emax, n, ne, 1e-10, X0, hermitian=herm, mode=2,
+                    integration=integration)
+    assert out.info == 5 and out.loop == 0 and out.m0 == n
+    ref = np.cumsum(n * np.diag(P).real) / np.arange(1, n + 1)
+    assert np.allclose(out.res, ref, rtol=0, atol=1e-11 * n)
+    assert abs(out.res[-1] - rho(lam).sum()) < 1e-11 * n
+    assert out.M == max(0, int(np.floor(out.res[-1] + 0.5)))
+    # the filtered probes come back in X: column c is P e_c
+    assert np.allclose(out.X, P, rtol=0, atol=1e-11)
+
+
+@pytest.mark.parametrize("ne", [2, 3, 8])
+def test_count_estimate_exact_for_sign_probes_on_a_diagonal_pencil(orc, ne):
+    """For diagonal A and B the filter matrix is diagonal, so a +-1 probe gives
+    x^T P x = sum_i rho(a_i / b_i) exactly: every sample, and so every running
+    average, equals the trace."""
+    rng = np.random.default_rng(173)
+    n, m0 = 40, 7
+    a = rng.uniform(-2.0, 2.0, n)
+    b = rng.uniform(0.5, 2.0, n)
+    emin, emax = -0.7, 0.9
+    lam = a / b
+    t = (lam - 0.5 * (emin + emax)) / (0.5 * (emax - emin))
+    trace = (1.0 / (1.0 + t ** (2 * ne))).sum()
+    X0 = W.sign_probes(n, m0, seed=174)
+    out = orc.feast(np.diag(a), np.diag(b), emin, emax, m0, ne, 1e-10, X0, mode=2, integration=1)
+    assert out.info == 5
+    assert np.allclose(out.res, trace, rtol=0, atol=1e-12 * n)
+    assert out.M == int(np.floor(trace + 0.5))
+
+
+def test_count_estimate_is_within_its_sampling_error(orc):
+    """A dense pencil with +-1 probes: the estimate lies within 5 standard
+    deviations of the trace.  For a +-1 probe, x^T P x has mean trace(P) and
+    variance 2 (||S||_F^2 - sum_i S_ii^2), S = (P + P^T)/2 (Hutchinson);
+    the mean of m0 probes divides it by m0."""
+    n, m0, ne = 160, 48, 8
+    p = W.dense_real_generalized(n, count=16, seed=175)
+    rho = lambda x: orc.rational(p.emin, p.emax, ne, np.asarray(x, float))
+    lam, P = _filter_matrix(p.A, p.B, rho)
+    S = 0.5 * (P + P.T)
+    sigma = math.sqrt(2.0 * (np.sum(S * S) - np.sum(np.diag(S) ** 2)) / m0)
+    X0 = W.sign_probes(n, m0, seed=176)
+    out = orc.feast(p.A, p.B, p.emin, p.emax, m0, ne, 1e-10, X0, mode=2)
+    assert out.info == 5
+    # the samples are the quadratic forms themselves, recomputed from P
+    samples = np.einsum("ic,ij,jc->c", X0, P, X0)
+    assert np.allclose(out.res, np.cumsum(samples) / np.arange(1, m0 + 1), rtol=0, atol=1e-10)
+    assert abs(out.res[-1] - rho(lam).sum()) < 5.0 * sigma
+    assert abs(rho(lam).sum() - p.count_in_interval()) < 0.5
+
+
 @pytest.mark.parametrize("n", [1, 2, 7, 33, 96])
 def test_lu_backward_error_and_solve(orc, n):
     A = _rand(n, n, n)
