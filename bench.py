@@ -106,6 +106,37 @@ def count_estimate(feastx, torch, W, A, B, p, expected, steps=5):
             "sampling_sd": float(np.sqrt(2.0 * expected / m0))}
 
 
+def slicing(feastx, torch, W, A, B, p, expected, single_ms, steps=3):
+    """Spectrum slicing on the same pencil: the interval's eigenvalues split
+    into 4 neighbouring slices of equal count (bounds at gap midpoints), each
+    with M0 = 1.5 x its count, solved as one batched job on device arrays
+    (mixed precision, 4 concurrent slices)."""
+    nsl = 4
+    counts = [expected // nsl] * nsl
+    counts[-1] += expected - sum(counts)
+    spec = np.sort(p.spectrum)
+    start = int(np.searchsorted(spec, p.emin))
+    bounds = W.slice_bounds(spec, start, counts)
+    m0s = [int(np.ceil(1.5 * c)) for c in counts]
+    X0 = [feastx.fortran_tensor(W.start_subspace(p.n, m, seed=2200 + k)) for k, m in enumerate(m0s)]
+    times, rs = [], None
+    for i in range(steps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rs = feastx.solve_slices(A, B, bounds, m0s, X0=X0, concurrency=nsl, ne=p.ne, tol=p.tol,
+                                 precision="mixed")
+        torch.cuda.synchronize()
+        if i:
+            times.append(time.perf_counter() - t0)
+    found = sum(r.M for r in rs)
+    if any(r.info != 0 for r in rs) or found != expected:
+        raise SystemExit(f"slicing failed: infos {[r.info for r in rs]}, found {found} of {expected}")
+    ms = float(np.mean(times)) * 1e3
+    return {"slices": nsl, "counts": counts, "m0": m0s, "ne": p.ne, "precision": "mixed", "ms": ms,
+            "eigenpairs_per_s": found / (ms * 1e-3), "single_interval_ms": single_ms,
+            "loops": [r.loop + 1 for r in rs], "slice_ms": [round(r.ms, 2) for r in rs]}
+
+
 def check(results, p, expected_m):
     for r in results:
         if r.info != 0:
@@ -272,6 +303,8 @@ def main():
                          "note": "update_*: the LU's complex64 product launches alone (8 flops per complex "
                                  "multiply-add); factor_*: Ne (8/3) N^3 over the whole factor stage, timed with "
                                  "per-launch events on (so slightly slow)"}
+    out["slicing"] = slicing(feastx, torch, W, A, B, p, expected, wall / args.steps * 1e3)
+    log(f"slicing: {out['slicing']['ms']:.1f} ms for {expected} eigenpairs in {out['slicing']['slices']} slices")
     out["count_estimate"] = count_estimate(feastx, torch, W, A, B, p, expected)
     log(f"count estimate: {out['count_estimate']['estimate']} (count {expected}) in "
         f"{out['count_estimate']['ms']:.1f} ms")

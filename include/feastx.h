@@ -160,6 +160,36 @@ typedef struct {
 int feast_solve_batched_d(int njobs, feast_job *jobs, const feast_opts *opts, int device, int concurrency);
 int feast_solve_batched_z(int njobs, feast_job *jobs, const feast_opts *opts, int device, int concurrency);
 
+/* ---- spectrum slicing (section "Multiple search intervals and FEAST-MPI":
+ * neighbouring search intervals without overlap, each an independent FEAST
+ * run; here one batched job on one GPU).  Slice s is the closed interval
+ * [bounds[s], bounds[s+1]] of the pencil (A, B); bounds has nslices + 1
+ * ascending entries.  A and B are staged on the device once and every slice
+ * reads them (device = 0: A, B and the slices' X are host arrays; 1: device
+ * arrays).  slices[s] carries m0 (with auto_m0: the most that slice may
+ * use), X (N x m0, leading dimension ldx; the start subspace if opts.x0 = 1),
+ * E and res (m0 entries each, host); the call sets its n, A, lda, B, ldb,
+ * emin and emax and fills info, M, m0_out, loop, epsout and ms as
+ * feast_solve_batched does.
+ * auto_m0 = 1: every slice first runs the stochastic count estimate (mode 2,
+ * 16 probes, Ne = 3) and then solves with M0 = min(m0, max(8, ceil(1.5
+ * estimate + 4))); a slice that ends with info 3 (M0 too small) runs again
+ * with twice its M0, up to its m0.  With auto_m0 the start subspaces are the
+ * library's random ones (opts.x0 is ignored).
+ * An eigenvalue exactly on a shared bound belongs to both neighbours and is
+ * reported by both.  Returns 0 when every slice ran (its status in
+ * slices[s].info), else: 200 bounds not ascending, 201 a slice's m0 outside
+ * [1, N], 202 N < 1, -102 A NULL, -103 lda < N, -105 ldb < N, -106
+ * nslices < 1, -107 bounds NULL, -108 slices NULL or a slice's X, E, res
+ * NULL or ldx < N, -110 device not 0 or 1; -1 staging allocation failed; -4
+ * other HIP error.  Slices run concurrently as in feast_solve_batched. */
+int feast_solve_slices_d(int N, const double *A, int lda, const double *B, int ldb, int nslices,
+                         const double *bounds, feast_job *slices, const feast_opts *opts, int device, int concurrency,
+                         int auto_m0);
+int feast_solve_slices_z(int N, const feast_z *A, int lda, const feast_z *B, int ldb, int nslices,
+                         const double *bounds, feast_job *slices, const feast_opts *opts, int device, int concurrency,
+                         int auto_m0);
+
 /* ---- serving: a request loop that admits eigenproblems of mixed size while
  * others run.  A request is admitted when a slot is free and its device
  * footprint (factors + subspaces + staged inputs) fits next to the running

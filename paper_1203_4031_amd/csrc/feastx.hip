@@ -1530,6 +1530,185 @@ int feast_solve_batched_z(int njobs, feast_job *jobs, const feast_opts *opts, in
     return solve_batched(true, njobs, jobs, opts, device, concurrency);
 }
 
+// ---------------------------------------------------------------- slicing
+// Device buffers the slicing call stages into, freed when it returns.
+struct StagedBuffers {
+    std::vector<void *> p;
+    void *get(size_t bytes)
+    {
+        void *q = nullptr;
+        if (hipMalloc(&q, std::max<size_t>(bytes, 256)) != hipSuccess) throw fx::alloc_error{};
+        p.push_back(q);
+        return q;
+    }
+    ~StagedBuffers()
+    {
+        (void)hipDeviceSynchronize();
+        for (void *q : p) (void)hipFree(q);
+    }
+};
+
+// Neighbouring intervals [bounds[s], bounds[s+1]] of one pencil as one batched
+// job: A and B live on the device once and every slice's solve reads them.
+static int solve_slices(bool cplx, int N, const void *A, int lda, const void *B, int ldb, int nslices,
+                        const double *bounds, feast_job *slices, const feast_opts *opts, int device, int concurrency,
+                        int auto_m0)
+{
+    if (N < 1) return 202;
+    if (!A) return -102;
+    if (lda < N) return -103;
+    if (B && ldb < N) return -105;
+    if (nslices < 1) return -106;
+    if (!bounds) return -107;
+    if (!slices) return -108;
+    if (device != 0 && device != 1) return -110;
+    for (int s = 0; s < nslices; ++s)
+        if (!(bounds[s] < bounds[s + 1])) return 200;
+    feast_opts o;
+    if (opts) o = *opts;
+    else feast_default_opts(&o);
+    if (auto_m0) o.x0 = 0;
+    const size_t es = cplx ? 16 : 8;
+    std::vector<int> cap(nslices);
+    for (int s = 0; s < nslices; ++s) {
+        cap[s] = slices[s].m0;
+        if (cap[s] < 1 || cap[s] > N) return 201;
+        if (!slices[s].X || !slices[s].E || !slices[s].res) return -108;
+        if (slices[s].ldx < N) return -108;
+    }
+    try {
+        StagedBuffers st;
+        const void *dA = A, *dB = B;
+        if (!device) {
+            void *a = st.get(es * (size_t)N * N);
+            FX_CHECK(hipMemcpy2D(a, es * N, A, es * lda, es * N, N, hipMemcpyHostToDevice));
+            dA = a;
+            if (B) {
+                void *b = st.get(es * (size_t)N * N);
+                FX_CHECK(hipMemcpy2D(b, es * N, B, es * ldb, es * N, N, hipMemcpyHostToDevice));
+                dB = b;
+            }
+        }
+        std::vector<feast_job> jobs(nslices);
+        std::vector<void *> dX(nslices);
+        for (int s = 0; s < nslices; ++s) {
+            feast_job &q = slices[s];
+            q.n = N;
+            q.A = A;
+            q.lda = lda;
+            q.B = B;
+            q.ldb = ldb;
+            q.emin = bounds[s];
+            q.emax = bounds[s + 1];
+            if (device) {
+                dX[s] = q.X;
+            } else {
+                dX[s] = st.get(es * (size_t)N * cap[s]);
+                if (o.x0)
+                    FX_CHECK(hipMemcpy2D(dX[s], es * N, q.X, es * q.ldx, es * N, cap[s], hipMemcpyHostToDevice));
+            }
+            feast_job &j = jobs[s];
+            j = q;
+            j.A = dA;
+            j.lda = device ? lda : N;
+            j.B = dB;
+            j.ldb = device ? ldb : N;
+            j.X = dX[s];
+            j.ldx = device ? q.ldx : N;
+        }
+        std::vector<int> m0(cap);
+        if (auto_m0) {
+            // stochastic count estimate per slice: 16 +-1 probes, 3 nodes
+            feast_opts oe = o;
+            oe.mode = 2;
+            oe.ne = 3;
+            oe.integration = 0;
+            oe.ellipse = 100;
+            oe.Zne = oe.Wne = nullptr;
+            const int pm = std::min(16, N);
+            std::vector<feast_job> ej(jobs);
+            std::vector<double> eE((size_t)nslices * pm), eres((size_t)nslices * pm);
+            for (int s = 0; s < nslices; ++s) {
+                ej[s].m0 = pm;
+                ej[s].X = st.get(es * (size_t)N * pm);
+                ej[s].ldx = N;
+                ej[s].E = eE.data() + (size_t)s * pm;
+                ej[s].res = eres.data() + (size_t)s * pm;
+            }
+            int rc = solve_batched(cplx, nslices, ej.data(), &oe, 1, concurrency);
+            if (rc) return rc;
+            for (int s = 0; s < nslices; ++s) {
+                if (ej[s].info != 5) {
+                    slices[s].info = ej[s].info;
+                    m0[s] = 0;
+                    continue;
+                }
+                const int want = std::max(8, (int)std::ceil(1.5 * ej[s].M + 4.0));
+                m0[s] = std::min(cap[s], want);
+            }
+        }
+        // the solves, then (auto_m0) slices that ran out of subspace again
+        // with twice the subspace, up to the caller's capacity
+        std::vector<int> todo;
+        for (int s = 0; s < nslices; ++s)
+            if (m0[s] > 0) todo.push_back(s);
+        while (!todo.empty()) {
+            std::vector<feast_job> run(todo.size());
+            for (size_t t = 0; t < todo.size(); ++t) {
+                run[t] = jobs[todo[t]];
+                run[t].m0 = m0[todo[t]];
+            }
+            int rc = solve_batched(cplx, (int)run.size(), run.data(), &o, 1, concurrency);
+            if (rc) return rc;
+            std::vector<int> again;
+            for (size_t t = 0; t < todo.size(); ++t) {
+                const int s = todo[t];
+                feast_job &q = slices[s];
+                q.info = run[t].info;
+                q.M = run[t].M;
+                q.m0_out = run[t].m0_out;
+                q.loop = run[t].loop;
+                q.epsout = run[t].epsout;
+                q.ms = run[t].ms;
+                if (auto_m0 && q.info == 3 && m0[s] < cap[s]) {
+                    m0[s] = std::min(cap[s], 2 * m0[s]);
+                    again.push_back(s);
+                }
+            }
+            todo.swap(again);
+        }
+        if (!device) {
+            FX_CHECK(hipDeviceSynchronize());
+            for (int s = 0; s < nslices; ++s) {
+                feast_job &q = slices[s];
+                const int i = q.info;
+                if (i == 0 || i == 1 || i == 2 || i == 3)
+                    FX_CHECK(hipMemcpy2D(q.X, es * q.ldx, dX[s], es * N, es * N, q.m0_out, hipMemcpyDeviceToHost));
+            }
+        }
+    } catch (const fx::alloc_error &) {
+        return -1;
+    } catch (const fx::hip_error &e) {
+        std::fprintf(stderr, "feastx: HIP error %s\n", hipGetErrorString(e.code));
+        return -4;
+    }
+    return 0;
+}
+
+int feast_solve_slices_d(int N, const double *A, int lda, const double *B, int ldb, int nslices,
+                         const double *bounds, feast_job *slices, const feast_opts *opts, int device, int concurrency,
+                         int auto_m0)
+{
+    return solve_slices(false, N, A, lda, B, ldb, nslices, bounds, slices, opts, device, concurrency, auto_m0);
+}
+
+int feast_solve_slices_z(int N, const feast_z *A, int lda, const feast_z *B, int ldb, int nslices,
+                         const double *bounds, feast_job *slices, const feast_opts *opts, int device, int concurrency,
+                         int auto_m0)
+{
+    return solve_slices(true, N, A, lda, B, ldb, nslices, bounds, slices, opts, device, concurrency, auto_m0);
+}
+
 // ---------------------------------------------------------------- server
 feast_server *feast_server_create(const feast_server_cfg *cfg)
 {

@@ -102,6 +102,9 @@ def lib():
         for name in ("feast_solve_batched_d", "feast_solve_batched_z"):
             f = getattr(L, name)
             f.argtypes = [C.c_int, C.POINTER(feast_job), op, C.c_int, C.c_int]
+        for f in (L.feast_solve_slices_d, L.feast_solve_slices_z):
+            f.argtypes = [C.c_int, vp, C.c_int, vp, C.c_int, C.c_int, dp, C.POINTER(feast_job), op, C.c_int,
+                          C.c_int, C.c_int]
         L.feast_server_create.argtypes = [C.POINTER(feast_server_cfg)]
         L.feast_server_create.restype = C.c_void_p
         L.feast_server_submit.argtypes = [C.c_void_p, C.POINTER(feast_request),
@@ -317,6 +320,72 @@ def solve_batched(problems, concurrency=4, **kw) -> list[Result]:
         r = Result(j.info, E[:k].copy(), X[:, :k].copy(order="F"), res[:k].copy(), j.M, k, j.loop,
                    j.epsout)
         r.ms = j.ms
+        out.append(r)
+    return out
+
+
+def solve_slices(A, B, bounds, m0, X0=None, concurrency=4, auto_m0=False, **kw) -> list[Result]:
+    """Spectrum slicing: the neighbouring intervals [bounds[s], bounds[s+1]] of
+    one pencil as one batched job sharing A and B on the device.  A, B: numpy
+    arrays (staged by the library), or column-major torch CUDA tensors (see
+    fortran_tensor; each slice's X is then a device tensor too).  m0: one
+    subspace size for every slice or a list (with auto_m0, the most each slice
+    may use); X0: None or a list of start subspaces, one per slice."""
+    device = hasattr(A, "is_cuda")
+    if device:
+        import torch
+
+        cplx = A.is_complex()
+        n = A.shape[0]
+        for t in (A, B):
+            if t is not None and (t.stride(0) != 1 or not t.is_cuda):
+                raise ValueError("device arrays must be column-major CUDA tensors")
+        pa = A.data_ptr()
+        pb = None if B is None else B.data_ptr()
+        lda, ldb = A.stride(1), (n if B is None else B.stride(1))
+        torch.cuda.synchronize()
+    else:
+        cplx = np.iscomplexobj(A) or (B is not None and np.iscomplexobj(B))
+        dt = np.complex128 if cplx else np.float64
+        A = np.asfortranarray(A, dtype=dt)
+        n = A.shape[0]
+        B = None if B is None else np.asfortranarray(B, dtype=dt)
+        pa, pb, lda, ldb = A.ctypes.data, (None if B is None else B.ctypes.data), n, n
+    b = np.ascontiguousarray(bounds, dtype=np.float64)
+    ns = b.size - 1
+    m0s = [int(m0)] * ns if np.isscalar(m0) else [int(x) for x in m0]
+    if len(m0s) != ns:
+        raise ValueError("one m0 per slice")
+    o = make_opts(x0=X0 is not None and not auto_m0, **kw)
+    keep, jobs = [], (feast_job * ns)()
+    for s_, mm in enumerate(m0s):
+        if device:
+            X = torch.zeros((mm, n), dtype=A.dtype, device=A.device).t()
+            if X0 is not None:
+                X.copy_(X0[s_])
+            px = X.data_ptr()
+        else:
+            X = np.zeros((n, mm), dtype=dt, order="F")
+            if X0 is not None:
+                X[:, :] = X0[s_]
+            px = X.ctypes.data
+        E, res = np.zeros(mm), np.zeros(mm)
+        keep.append((X, E, res))
+        j = jobs[s_]
+        j.m0, j.X, j.ldx, j.E, j.res = mm, px, n, E.ctypes.data, res.ctypes.data
+    if device:
+        torch.cuda.synchronize()
+    f = lib().feast_solve_slices_z if cplx else lib().feast_solve_slices_d
+    rc = f(n, pa, lda, pb, ldb, ns, _dp(b), jobs, C.byref(o), int(device), concurrency, int(bool(auto_m0)))
+    if rc:
+        raise ValueError(f"feast_solve_slices: {rc}")
+    out = []
+    for (X, E, res), j in zip(keep, jobs):
+        k = j.m0_out if j.info in (0, 1, 2, 3) else 0
+        Xk = X[:, :k] if device else X[:, :k].copy(order="F")
+        r = Result(j.info, E[:k].copy(), Xk, res[:k].copy(), j.M, k, j.loop, j.epsout)
+        r.ms = j.ms
+        r.emin, r.emax = j.emin, j.emax
         out.append(r)
     return out
 

@@ -78,6 +78,17 @@ def sign_probes(n: int, m0: int, seed: int) -> np.ndarray:
     return np.asfortranarray(np.where(_rng(seed).random((n, m0)) < 0.5, -1.0, 1.0))
 
 
+def slice_bounds(spectrum: np.ndarray, start: int, counts) -> np.ndarray:
+    """Bounds of neighbouring intervals over a sorted spectrum: slice k holds
+    counts[k] eigenvalues, the first starting at index ``start``; every bound
+    is the midpoint of the gap it sits in."""
+    s = np.sort(np.asarray(spectrum, dtype=np.float64))
+    idx = start + np.concatenate([[0], np.cumsum(counts)])
+    if idx[0] < 1 or idx[-1] >= s.size:
+        raise ValueError("slices must leave an eigenvalue outside each end")
+    return 0.5 * (s[idx - 1] + s[idx])
+
+
 def pick_interval(spectrum: np.ndarray, count: int, centre_index: int | None = None):
     """Interval holding ``count`` eigenvalues with the widest end gaps.
 

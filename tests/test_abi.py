@@ -86,3 +86,30 @@ def test_argument_errors_need_no_gpu(kw, code):
                                          n, C.byref(M), res.ctypes.data_as(C.POINTER(C.c_double)),
                                          None, None)
     assert info == code
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n=0), 202), (dict(lda=2), -103), (dict(ldb=2), -105), (dict(nslices=0), -106),
+    (dict(bounds=[0.0, 0.5, 0.5]), 200), (dict(bounds=[0.0, -0.5, 1.0]), 200), (dict(m0=0), 201),
+    (dict(m0=5), 201), (dict(ldx=3), -108), (dict(no_res=True), -108), (dict(device=2), -110),
+])
+def test_slice_argument_errors_need_no_gpu(kw, code):
+    """feast_solve_slices checks its arguments before any device call."""
+    args = dict(n=4, lda=4, ldb=4, nslices=2, bounds=[-1.0, 0.0, 1.0], m0=2, ldx=4, no_res=False, device=0)
+    args.update(kw)
+    n = max(args["n"], 1)
+    A = np.eye(n, order="F")
+    B = np.eye(n, order="F")
+    b = np.asarray(args["bounds"], dtype=np.float64)
+    jobs = (feastx.feast_job * 2)()
+    keep = []
+    for j in jobs:
+        X, E, res = np.zeros((n, 8), order="F"), np.zeros(8), np.zeros(8)
+        keep.append((X, E, res))
+        j.m0, j.X, j.ldx, j.E = args["m0"], X.ctypes.data, args["ldx"], E.ctypes.data
+        j.res = None if args["no_res"] else res.ctypes.data
+    o = feastx.make_opts()
+    info = feastx.lib().feast_solve_slices_d(args["n"], A.ctypes.data, args["lda"], B.ctypes.data, args["ldb"],
+                                             args["nslices"], b.ctypes.data_as(C.POINTER(C.c_double)), jobs,
+                                             C.byref(o), args["device"], 2, 0)
+    assert info == code
