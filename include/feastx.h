@@ -78,6 +78,11 @@ typedef struct {
     const feast_z *Zne; /* expert mode (the guide's Zne, Wne arguments): ne custom half-contour nodes */
     const feast_z *Wne; /* and weights, both or neither (else info -113); read during the call (the
                            server copies them at submit); integration and ellipse are then unused */
+    /* non-Hermitian FEAST (feast_gsolve_*) only: */
+    int ne_full;          /* [fpm(8)] nodes of the full contour, 1..256 (default 16), else info 108 */
+    int integration_full; /* [fpm(17)] 0: Gauss-Legendre, 1: trapezoidal (default); else info 117 */
+    int angle;            /* [fpm(19)] rotation of the ellipse in degrees, -180..180 (default 0), else
+                             info 119 */
 } feast_opts;
 
 /* Per-stage timings of the most recent solve (milliseconds, from HIP events
@@ -130,6 +135,38 @@ int feast_solve_d_dev(int N, const double *dA, int lda, const double *dB, int ld
 int feast_solve_z_dev(int N, const feast_z *dA, int lda, const feast_z *dB, int ldb, double Emin,
                       double Emax, int *M0, const feast_opts *opts, double *E, feast_z *dX, int ldx,
                       int *M, double *res, int *loop, double *epsout, void *stream);
+
+/* ---- non-Hermitian FEAST (guide: the variant for non-Hermitian pencils,
+ * with dual subspaces Q and Q-hat for the right and left eigenvectors, a full
+ * contour around a two-dimensional search region, Table "tab_fpm" fpm(8),
+ * fpm(17), fpm(18), fpm(19), Table "tab_common" for E, X, res):
+ *   A, B general (B = NULL: identity), complex (_z) or real (_d, solved in
+ *   complex arithmetic); host arrays, column-major.
+ *   Region: the ellipse centred at Emid with horizontal semi-axis r > 0,
+ *   vertical semi-axis r fpm(18)/100, turned by fpm(19) degrees
+ *   counter-clockwise.
+ *   E[M0] (complex out): the first M are the eigenvalues inside the region,
+ *   then the other Ritz values, spurious ones last; each group by increasing
+ *   real part, then imaginary part.
+ *   X (N x 2 M0, leading dimension ldx >= N, complex): on entry the right and
+ *   then the left start subspaces if opts.x0 = 1; on exit the right
+ *   eigenvectors in columns 0..M0-1 and the left eigenvectors in columns
+ *   M0..2 M0-1, in the order of E, each of unit 2-norm.
+ *   res[2 M0]: right residuals ||A x - lambda B x||_1 / (alpha ||B x||_1),
+ *   then left residuals ||A^H y - conj(lambda) B^H y||_1 / (alpha ||B^H y||_1),
+ *   alpha = |Emid| + r; spurious pairs (inside, with a residual above 0.1 from
+ *   the second loop on) have -1.
+ *   Convergence (fpm(6) = 1): both residuals of every pair inside below tol.
+ *   FP64 only (opts.precision = 1: info 140), normal mode only (opts.mode
+ *   != 0: info 114); opts.ne, integration and custom nodes are not used.
+ *   info as for feast_solve_*, plus 108 (ne_full), 117 (integration_full),
+ *   119 (angle), 200 (r <= 0 or not finite). */
+int feast_gsolve_z(int N, const feast_z *A, int lda, const feast_z *B, int ldb, feast_z Emid, double r, int *M0,
+                   const feast_opts *opts, feast_z *E, feast_z *X, int ldx, int *M, double *res, int *loop,
+                   double *epsout);
+int feast_gsolve_d(int N, const double *A, int lda, const double *B, int ldb, feast_z Emid, double r, int *M0,
+                   const feast_opts *opts, feast_z *E, feast_z *X, int ldx, int *M, double *res, int *loop,
+                   double *epsout);
 
 /* ---- batched: many independent problems in one call (the guide's first
  * level of parallelism, independent search intervals / problems).  Each job

@@ -37,6 +37,7 @@
 #include "rr.hpp"
 #include "solve.hpp"
 #include "bortho.hpp"
+#include "nonherm.hpp"
 
 namespace fx {
 
@@ -961,6 +962,338 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
     return info;
 }
 
+// ---------------------------------------------------------------- non-Hermitian
+// Full-contour nodes and weights (fpm(8) nodes; fpm(17) rule, fpm(18)
+// ellipse ratio, fpm(19) rotation).  The contour is z(t) = c + e^{i phi}
+// (r cos t + i a r sin t), t in [0, 2 pi); a node at t with step dt weighs
+// dz / (2 pi i) = (dt / 2 pi) e^{i phi} (a r cos t + i r sin t).
+// Trapezoidal: t_j = 2 pi (j + 1/2) / ne.  Gauss: one ne-point
+// Gauss-Legendre rule over [0, 2 pi].
+static Contour make_full_contour(double2 c, double r, int ne, int integration, int ellipse, int angle)
+{
+    std::vector<double> t(ne), f(ne);
+    if (integration == 1) {
+        for (int j = 0; j < ne; ++j) {
+            t[j] = 2.0 * M_PI * (j + 0.5) / ne;
+            f[j] = 1.0 / ne;
+        }
+    } else {
+        std::vector<double> x, om;
+        gauss_legendre(ne, x, om);
+        for (int j = 0; j < ne; ++j) {
+            t[j] = M_PI * (1.0 + x[j]);
+            f[j] = 0.5 * om[j];
+        }
+    }
+    const double a = ellipse / 100.0, phi = angle * M_PI / 180.0, cr = std::cos(phi), sr = std::sin(phi);
+    Contour ct;
+    ct.z.resize(ne);
+    ct.w.resize(ne);
+    for (int j = 0; j < ne; ++j) {
+        const double ct_ = std::cos(t[j]), st_ = std::sin(t[j]);
+        const double ur = r * ct_, ui = a * r * st_;            // point before rotation
+        const double vr = f[j] * a * r * ct_, vi = f[j] * r * st_;   // weight before rotation
+        ct.z[j] = make_double2(c.x + cr * ur - sr * ui, c.y + sr * ur + cr * ui);
+        ct.w[j] = make_double2(cr * vr - sr * vi, sr * vr + cr * vi);
+    }
+    return ct;
+}
+
+struct GProblem {
+    int n;
+    const double2 *A;   // device, complex
+    long lda;
+    const double2 *B;   // device or NULL
+    long ldb;
+    double2 emid;
+    double r;
+    int m0;
+    double2 *X;   // caller's device array, n x 2 m0: right, then left
+    long ldx;
+};
+
+struct GResult {
+    int M = 0, loop = 0, m0 = 0;
+    double epsout = 1.0;
+    std::vector<double2> E;
+    std::vector<double> res;   // 2 m0
+};
+
+static bool in_region(double2 lam, double2 c, double r, int ellipse, int angle)
+{
+    const double phi = angle * M_PI / 180.0, a = ellipse / 100.0;
+    const double dr = lam.x - c.x, di = lam.y - c.y;
+    const double ur = std::cos(phi) * dr + std::sin(phi) * di, ui = -std::sin(phi) * dr + std::cos(phi) * di;
+    return (ur / r) * (ur / r) + (ui / (a * r)) * (ui / (a * r)) <= 1.0;
+}
+
+// Non-Hermitian FEAST with dual subspaces, FP64 complex throughout:
+//   Q = sum_j w_j (z_j B - A)^{-1} B X,  Qh = sum_j conj(w_j) (z_j B - A)^{-H} B^H Xh,
+//   Aq = Qh^H A Q, Bq = Qh^H B Q, Aq W = Bq W Lambda, Wh^H Aq = Lambda Wh^H Bq,
+//   X = Q W, Xh = Qh Wh (unit columns); residuals of both sides.
+static int run_general(const GProblem &pb, const feast_opts &o, hipStream_t s, Workspace &ws, GResult &out,
+                       feast_stats &st_out)
+{
+    using T = double;
+    using V = cplx<T>;
+    using E = double2;
+    const int n = pb.n, ne = o.ne_full, m0 = pb.m0;
+    const double alpha = std::hypot(pb.emid.x, pb.emid.y) + pb.r;
+    const size_t nm = (size_t)n * m0, mm = (size_t)m0 * m0;
+    feast_stats st{};
+    StageTimer tm(s);
+    tm.start();
+
+    Contour ct = make_full_contour(pb.emid, pb.r, ne, o.integration_full, o.ellipse, o.angle);
+    double2 *dz = static_cast<double2 *>(ws.get("z", sizeof(double2) * ne));
+    double2 *dw = static_cast<double2 *>(ws.get("coef", sizeof(double2) * ne));
+    FX_CHECK(hipMemcpyAsync(dz, ct.z.data(), sizeof(double2) * ne, hipMemcpyHostToDevice, s));
+    FX_CHECK(hipMemcpyAsync(dw, ct.w.data(), sizeof(double2) * ne, hipMemcpyHostToDevice, s));
+
+    auto blk = [&](const char *name, size_t count) { return static_cast<E *>(ws.get(name, sizeof(E) * count)); };
+    E *X = blk("X", nm), *Xh = blk("Xh", nm), *R = blk("R", nm), *Rh = blk("Rh", nm);
+    E *Q = blk("Q", nm), *Qh = blk("Qh", nm), *AQ = blk("AQ", nm), *BQ = blk("BQ", nm);
+    E *AX = blk("AX", nm), *BX = blk("BX", nm), *AhX = blk("AhX", nm), *BhX = blk("BhX", nm);
+    E *Aq = blk("Aq", mm), *Bq = blk("Bq", mm), *Binv = blk("Binv", mm), *Cm = blk("Cm", mm);
+    E *Zs = blk("Zs", mm), *Ys = blk("Ys", mm), *Wm = blk("Wm", mm), *Wc = blk("Wc", mm), *Winv = blk("Winv", mm);
+    E *G = blk("G", mm), *Wh = blk("Wh", mm);
+    E *lam = blk("glam", m0);
+    double *res = static_cast<double *>(ws.get("gres", sizeof(double) * 2 * m0));
+    int *sel = static_cast<int *>(ws.get("sel", sizeof(int) * m0));
+    int *dstat = static_cast<int *>(ws.get("gstat", sizeof(int) * 4));
+    const long ldf = n, sF = (long)n * n;
+    V *F = static_cast<V *>(ws.get("F64", sizeof(V) * (size_t)ne * sF));
+    int *ipiv = static_cast<int *>(ws.get("ipiv", sizeof(int) * (size_t)ne * n));
+    int *perm = static_cast<int *>(ws.get("perm", sizeof(int) * (size_t)ne * n));
+    int *swapmap = static_cast<int *>(ws.get("swapmap", sizeof(int) * 2 * (size_t)ne * (1 + 4 * LU_NB)));
+    int *dinfo = static_cast<int *>(ws.get("info", sizeof(int) * ne));
+    const bool compose = solve_nb<T>() > TRI_INV_NB;
+    const long sI64 = compose ? tri_inv_stride(n) : 0, sInv = solve_inv_stride<T>(n);
+    const long sItmp = compose ? (long)ceil_div(n, solve_nb<T>()) * 64 * 64 : 0;
+    V *L64 = compose ? static_cast<V *>(ws.get("L64inv", sizeof(V) * (size_t)ne * sI64)) : nullptr;
+    V *U64 = compose ? static_cast<V *>(ws.get("U64inv", sizeof(V) * (size_t)ne * sI64)) : nullptr;
+    V *Itmp = compose ? static_cast<V *>(ws.get("Invtmp", sizeof(V) * (size_t)ne * sItmp)) : nullptr;
+    V *Wsv = static_cast<V *>(ws.get("Wsolve64", sizeof(V) * (size_t)ne * sF));
+    V *Linv = static_cast<V *>(ws.get("Linv64", sizeof(V) * (size_t)ne * sInv));
+    V *Uinv = static_cast<V *>(ws.get("Uinv64", sizeof(V) * (size_t)ne * sInv));
+    V *Ytmp = static_cast<V *>(ws.get("Yt64", sizeof(V) * (size_t)ne * nm));
+    V *Y = static_cast<V *>(ws.get("Y64", sizeof(V) * (size_t)ne * nm));
+    V *Yh = static_cast<V *>(ws.get("Yh64", sizeof(V) * (size_t)ne * nm));
+    V *Yh2 = static_cast<V *>(ws.get("Yg64", sizeof(V) * (size_t)ne * nm));
+    double2 *h_lam = static_cast<double2 *>(ws.pinned("h_glam", sizeof(double2) * m0));
+    double *h_res = static_cast<double *>(ws.pinned("h_gres", sizeof(double) * 2 * m0));
+    int *h_stat = static_cast<int *>(ws.pinned("h_gstat", sizeof(int) * 4));
+    int *h_info = static_cast<int *>(ws.pinned("h_info", sizeof(int) * ne));
+
+    // start subspaces: the caller's (right in columns 0..m0-1, left in m0..2m0-1) or seeded
+    if (o.x0) {
+        hipLaunchKernelGGL((copy_block_kernel<true>), grid1(nm), dim3(256), 0, s, n, m0, pb.X, pb.ldx, X, (long)n);
+        hipLaunchKernelGGL((copy_block_kernel<true>), grid1(nm), dim3(256), 0, s, n, m0, pb.X + (long)m0 * pb.ldx,
+                           pb.ldx, Xh, (long)n);
+    } else {
+        hipLaunchKernelGGL((random_start_kernel<true>), grid1(nm), dim3(256), 0, s, n, m0, o.seed, 0, X, (long)n);
+        hipLaunchKernelGGL((random_start_kernel<true>), grid1(nm), dim3(256), 0, s, n, m0, o.seed + 1, 0, Xh,
+                           (long)n);
+    }
+    FX_LAUNCH_CHECK();
+
+    // factor every shifted matrix once (the factors serve both sides)
+    shift_build<T>(s, true, n, reinterpret_cast<const double *>(pb.A), pb.lda,
+                   reinterpret_cast<const double *>(pb.B), pb.ldb, dz, ne, F, ldf, sF);
+    tm.mark(&st.t_shift);
+    FX_CHECK(hipMemsetAsync(dinfo, 0, sizeof(int) * ne, s));
+    getrf_batched<T>(s, nullptr, ws.ev_a, ws.ev_b, n, F, ldf, sF, ipiv, perm, n, swapmap, dinfo, ne);
+    solve_inverses<T>(s, n, F, ldf, sF, L64, U64, sI64, Linv, Uinv, sInv, Itmp, sItmp, ne);
+    build_w<T>(s, n, F, ldf, sF, Linv, Uinv, sInv, Wsv, ne);
+    FX_CHECK(hipMemcpyAsync(h_info, dinfo, sizeof(int) * ne, hipMemcpyDeviceToHost, s));
+    FX_CHECK(hipStreamSynchronize(s));
+    for (int j = 0; j < ne; ++j)
+        if (h_info[j] != 0) throw solver_error{-2};
+    st.factor_flops += ne * (8.0 / 3.0) * (double)n * n * n;
+    tm.mark(&st.t_factor);
+
+    const E *A = pb.A, *B = pb.B;
+    double trace_re = 0.0, trace_im = 0.0, epsout = 1.0;
+    int info = 0, k = 0, M = 0;
+    std::vector<char> ins(m0), spur(m0);
+    for (k = 0; k <= o.maxloop; ++k) {
+        // right-hand sides B X and B^H Xh
+        if (B) {
+            dgemm<true>(ws, s, false, n, m0, n, 1.0, B, pb.ldb, X, n, 0.0, R, n);
+            dgemm<true>(ws, s, true, n, m0, n, 1.0, B, pb.ldb, Xh, n, 0.0, Rh, n);
+        } else {
+            hipLaunchKernelGGL((copy_block_kernel<true>), grid1(nm), dim3(256), 0, s, n, m0, X, (long)n, R, (long)n);
+            hipLaunchKernelGGL((copy_block_kernel<true>), grid1(nm), dim3(256), 0, s, n, m0, Xh, (long)n, Rh,
+                               (long)n);
+            FX_LAUNCH_CHECK();
+        }
+        // solves at every node: (z_j B - A) Y = R and (z_j B - A)^H Yh = Rh
+        {
+            dim3 g((unsigned)((nm + 255) / 256), ne);
+            hipLaunchKernelGGL((gather_rows_kernel<T, true>), g, dim3(256), 0, s, n, m0, perm, (long)n,
+                               reinterpret_cast<const double *>(R), (long)n, Y, (long)n, (long)nm);
+            FX_LAUNCH_CHECK();
+            getrs_batched<T>(s, false, n, m0, F, Wsv, ldf, sF, Linv, Uinv, sInv, Y, Ytmp, n, (long)nm, ne);
+            hipLaunchKernelGGL((copy_rhs_kernel<T, true>), g, dim3(256), 0, s, n, m0,
+                               reinterpret_cast<const double *>(Rh), (long)n, Yh, (long)n, (long)nm);
+            FX_LAUNCH_CHECK();
+            getrs_batched<T>(s, true, n, m0, F, Wsv, ldf, sF, Linv, Uinv, sInv, Yh, Ytmp, n, (long)nm, ne);
+            hipLaunchKernelGGL((scatter_rows_kernel<T>), g, dim3(256), 0, s, n, m0, perm, (long)n, Yh, (long)n,
+                               (long)nm, Yh2, (long)n, (long)nm);
+            FX_LAUNCH_CHECK();
+            st.solve_flops += 2.0 * ne * 8.0 * (double)n * n * m0;
+        }
+        tm.mark(&st.t_solve);
+        hipLaunchKernelGGL(accumulate_general_kernel, grid1(nm), dim3(256), 0, s, n, m0, ne,
+                           reinterpret_cast<const double2 *>(Y), reinterpret_cast<const double2 *>(Yh2), (long)n,
+                           (long)nm, dw, Q, Qh, (long)n);
+        FX_LAUNCH_CHECK();
+        tm.mark(&st.t_accum);
+
+        // reduced pencil
+        dgemm<true>(ws, s, false, n, m0, n, 1.0, A, pb.lda, Q, n, 0.0, AQ, n);
+        if (B) dgemm<true>(ws, s, false, n, m0, n, 1.0, B, pb.ldb, Q, n, 0.0, BQ, n);
+        else {
+            hipLaunchKernelGGL((copy_block_kernel<true>), grid1(nm), dim3(256), 0, s, n, m0, Q, (long)n, BQ, (long)n);
+            FX_LAUNCH_CHECK();
+        }
+        dgemm<true>(ws, s, true, m0, m0, n, 1.0, Qh, n, AQ, n, 0.0, Aq, m0);
+        dgemm<true>(ws, s, true, m0, m0, n, 1.0, Qh, n, BQ, n, 0.0, Bq, m0);
+        tm.mark(&st.t_rr);
+
+        // reduced eigenproblem: C = Bq^{-1} Aq = W Lambda W^{-1}, Wh = (W^{-1} Bq^{-1})^H
+        hipLaunchKernelGGL(gj_inverse_kernel, dim3(1), dim3(NH_NT), 0, s, m0, Bq, Binv, dstat);
+        FX_LAUNCH_CHECK();
+        dgemm<true>(ws, s, false, m0, m0, m0, 1.0, Binv, m0, Aq, m0, 0.0, Cm, m0);
+        hipLaunchKernelGGL(eig_general_kernel, dim3(1), dim3(NH_NT), 0, s, m0, Cm, Zs, Ys, lam, dstat + 1);
+        FX_LAUNCH_CHECK();
+        dgemm<true>(ws, s, false, m0, m0, m0, 1.0, Zs, m0, Ys, m0, 0.0, Wm, m0);
+        hipLaunchKernelGGL((copy_block_kernel<true>), grid1(mm), dim3(256), 0, s, m0, m0, Wm, (long)m0, Wc,
+                           (long)m0);
+        hipLaunchKernelGGL(gj_inverse_kernel, dim3(1), dim3(NH_NT), 0, s, m0, Wc, Winv, dstat + 3);
+        FX_LAUNCH_CHECK();
+        dgemm<true>(ws, s, false, m0, m0, m0, 1.0, Winv, m0, Binv, m0, 0.0, G, m0);
+        hipLaunchKernelGGL(conj_transpose_kernel, grid1(mm), dim3(256), 0, s, m0, G, Wh);
+        FX_LAUNCH_CHECK();
+        FX_CHECK(hipMemcpyAsync(h_stat, dstat, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
+        FX_CHECK(hipStreamSynchronize(s));
+        if (h_stat[0] != 0 || h_stat[1] != 0 || h_stat[3] != 0) throw solver_error{-3};
+        st.eig_calls += 1;
+        st.eig_sweeps += h_stat[2];
+        tm.mark(&st.t_reduced);
+
+        // Ritz vectors of both sides, unit columns, residuals
+        dgemm<true>(ws, s, false, n, m0, m0, 1.0, Q, n, Wm, m0, 0.0, X, n);
+        dgemm<true>(ws, s, false, n, m0, m0, 1.0, Qh, n, Wh, m0, 0.0, Xh, n);
+        hipLaunchKernelGGL(normalize_cols_kernel, dim3(m0), dim3(256), 0, s, n, X, (long)n);
+        hipLaunchKernelGGL(normalize_cols_kernel, dim3(m0), dim3(256), 0, s, n, Xh, (long)n);
+        FX_LAUNCH_CHECK();
+        dgemm<true>(ws, s, false, n, m0, n, 1.0, A, pb.lda, X, n, 0.0, AX, n);
+        dgemm<true>(ws, s, true, n, m0, n, 1.0, A, pb.lda, Xh, n, 0.0, AhX, n);
+        if (B) {
+            dgemm<true>(ws, s, false, n, m0, n, 1.0, B, pb.ldb, X, n, 0.0, BX, n);
+            dgemm<true>(ws, s, true, n, m0, n, 1.0, B, pb.ldb, Xh, n, 0.0, BhX, n);
+        } else {
+            hipLaunchKernelGGL((copy_block_kernel<true>), grid1(nm), dim3(256), 0, s, n, m0, X, (long)n, BX, (long)n);
+            hipLaunchKernelGGL((copy_block_kernel<true>), grid1(nm), dim3(256), 0, s, n, m0, Xh, (long)n, BhX,
+                               (long)n);
+        }
+        hipLaunchKernelGGL(resid_general_kernel, dim3(m0), dim3(256), 0, s, n, AX, BX, (long)n, lam, 0, alpha, res);
+        hipLaunchKernelGGL(resid_general_kernel, dim3(m0), dim3(256), 0, s, n, AhX, BhX, (long)n, lam, 1, alpha,
+                           res + m0);
+        FX_LAUNCH_CHECK();
+        FX_CHECK(hipMemcpyAsync(h_lam, lam, sizeof(double2) * m0, hipMemcpyDeviceToHost, s));
+        FX_CHECK(hipMemcpyAsync(h_res, res, sizeof(double) * 2 * m0, hipMemcpyDeviceToHost, s));
+        FX_CHECK(hipStreamSynchronize(s));
+        tm.mark(&st.t_resid);
+
+        // count, spurious pairs (both residuals), trace, convergence
+        int bad = 0;
+        double tr = 0.0, ti = 0.0, maxres = 0.0;
+        M = 0;
+        int inside = 0;
+        for (int i = 0; i < m0; ++i) {
+            ins[i] = in_region(h_lam[i], pb.emid, pb.r, o.ellipse, o.angle);
+            const double ri = std::max(h_res[i], h_res[m0 + i]);
+            spur[i] = ins[i] && k >= 1 && ri > SPURIOUS_RES;
+            if (!ins[i]) continue;
+            ++inside;
+            if (spur[i]) continue;
+            ++M;
+            tr += h_lam[i].x;
+            ti += h_lam[i].y;
+            maxres = std::max(maxres, ri);
+            if (!(ri < o.tol)) ++bad;
+        }
+        epsout = (k == 0) ? 1.0 : std::hypot(tr - trace_re, ti - trace_im) / alpha;
+        trace_re = tr;
+        trace_im = ti;
+        if (o.verbose)
+            std::fprintf(stderr, "feastx loop %d: #eig %d  trace %.15e%+.15ei  eps %.3e  maxres %.3e\n", k, M, tr, ti,
+                         epsout, maxres);
+        const bool converged = (M > 0) && (o.conv == 1 ? bad == 0 : epsout < o.tol);
+        if (k == 0 && inside == 0) {
+            info = 1;
+            break;
+        }
+        if (converged) {
+            info = 0;
+            break;
+        }
+        if (M >= m0) {
+            info = 3;
+            break;
+        }
+        if (k == o.maxloop) {
+            info = 2;
+            break;
+        }
+    }
+    if (k > o.maxloop) k = o.maxloop;
+
+    // output order: counted pairs, pairs outside, spurious pairs; each by
+    // increasing real part, then imaginary part
+    std::vector<int> idx(m0);
+    for (int i = 0; i < m0; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+        if (h_lam[a].x != h_lam[b].x) return h_lam[a].x < h_lam[b].x;
+        return h_lam[a].y < h_lam[b].y;
+    });
+    std::vector<int> order;
+    order.reserve(m0);
+    for (int pass = 0; pass < 3; ++pass)
+        for (int i : idx) {
+            const int c = !ins[i] ? 1 : (spur[i] ? 2 : 0);
+            if (c == pass) order.push_back(i);
+        }
+    out.E.resize(m0);
+    out.res.assign(2 * (size_t)m0, 0.0);
+    for (int c = 0; c < m0; ++c) {
+        const int i = order[c];
+        const bool sp = ins[i] && spur[i];
+        out.E[c] = h_lam[i];
+        out.res[c] = sp ? -1.0 : h_res[i];
+        out.res[m0 + c] = sp ? -1.0 : h_res[m0 + i];
+    }
+    FX_CHECK(hipMemcpyAsync(sel, order.data(), sizeof(int) * m0, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL((gather_cols_kernel<true>), grid1(nm), dim3(256), 0, s, n, m0, sel, X, (long)n, pb.X, pb.ldx);
+    hipLaunchKernelGGL((gather_cols_kernel<true>), grid1(nm), dim3(256), 0, s, n, m0, sel, Xh, (long)n,
+                       pb.X + (long)m0 * pb.ldx, pb.ldx);
+    FX_LAUNCH_CHECK();
+    FX_CHECK(hipStreamSynchronize(s));
+    tm.mark(&st.t_total);
+    tm.flush();
+    out.M = M;
+    out.loop = k;
+    out.m0 = m0;
+    out.epsout = epsout;
+    st.loops = k + 1;
+    st.m0_final = m0;
+    st.t_total += st.t_shift + st.t_factor + st.t_solve + st.t_accum + st.t_rr + st.t_reduced + st.t_resid;
+    st_out = st;
+    return info;
+}
+
 // Validation shared by every entry point (Table "tab_info").
 static int validate(int n, int m0, double emin, double emax, const feast_opts &o)
 {
@@ -982,6 +1315,26 @@ static int validate(int n, int m0, double emin, double emax, const feast_opts &o
     if (m0 > 4096) return 201;
     if (o.precision == 1 && n > lu_max_n<float>()) return 202;
     if (o.precision == 0 && n > lu_max_n<double>()) return 202;
+    return 0;
+}
+
+// Validation of the non-Hermitian entry points.
+static int validate_general(int n, int m0, double2 emid, double r, const feast_opts &o)
+{
+    if (n < 1) return 202;
+    if (m0 < 1 || m0 > n || m0 > NH_MAXM) return 201;
+    if (!(r > 0.0) || !std::isfinite(r) || !std::isfinite(emid.x) || !std::isfinite(emid.y)) return 200;
+    if (o.ne_full < 1 || o.ne_full > 256) return 108;
+    if (!(o.tol > 0.0)) return 103;
+    if (o.maxloop < 0) return 104;
+    if (o.x0 != 0 && o.x0 != 1) return 105;
+    if (o.conv != 0 && o.conv != 1) return 106;
+    if (o.mode != 0) return 114;
+    if (o.precision != 0) return 140;
+    if (o.integration_full != 0 && o.integration_full != 1) return 117;
+    if (o.ellipse < 1) return 118;
+    if (o.angle < -180 || o.angle > 180) return 119;
+    if (n > lu_max_n<double>()) return 202;
     return 0;
 }
 
@@ -1311,6 +1664,9 @@ void feast_default_opts(feast_opts *o)
     o->ellipse = 100;
     o->Zne = nullptr;
     o->Wne = nullptr;
+    o->ne_full = 16;
+    o->integration_full = 1;
+    o->angle = 0;
 }
 
 const char *feast_version(void) { return "feastx 0.1 (gfx950)"; }
@@ -1528,6 +1884,103 @@ int feast_solve_batched_d(int njobs, feast_job *jobs, const feast_opts *opts, in
 int feast_solve_batched_z(int njobs, feast_job *jobs, const feast_opts *opts, int device, int concurrency)
 {
     return solve_batched(true, njobs, jobs, opts, device, concurrency);
+}
+
+// ---------------------------------------------------------------- non-Hermitian
+static int gsolve(bool real_in, int N, const void *A, int lda, const void *B, int ldb, feast_z Emid, double r,
+                  int *M0, const feast_opts *opts, feast_z *E, feast_z *X, int ldx, int *M, double *res, int *loop,
+                  double *epsout)
+{
+    if (!M0) return -108;
+    feast_opts o;
+    if (opts) o = *opts;
+    else feast_default_opts(&o);
+    const double2 emid = make_double2(Emid.re, Emid.im);
+    int v = fx::validate_general(N, *M0, emid, r, o);
+    if (v) return v;
+    if (!A) return -102;
+    if (lda < N) return -103;
+    if (B && ldb < N) return -105;
+    if (!E) return -110;
+    if (!X) return -111;
+    if (ldx < N) return -112;
+    if (!M) return -113;
+    if (!res) return -114;
+    const int m0 = *M0;
+    std::lock_guard<std::mutex> lk(fx::g_mu);
+    fx::Workspace &ws = fx::g_ws;
+    fx::GResult out;
+    feast_stats st{};
+    int info;
+    try {
+        ws.init();
+        hipStream_t s = ws.stream;
+        const size_t nn = (size_t)N * N, es = sizeof(double2);
+        double2 *dA = static_cast<double2 *>(ws.get("in_A", es * nn));
+        double2 *dB = B ? static_cast<double2 *>(ws.get("in_B", es * nn)) : nullptr;
+        double2 *dX = static_cast<double2 *>(ws.get("in_X", es * (size_t)N * 2 * m0));
+        if (real_in) {
+            // real input: widened to complex on the host (argument marshalling)
+            std::vector<double2> tmp(nn);
+            const double *Ar = static_cast<const double *>(A);
+            for (int j = 0; j < N; ++j)
+                for (int i = 0; i < N; ++i) tmp[i + (size_t)j * N] = make_double2(Ar[i + (size_t)j * lda], 0.0);
+            FX_CHECK(hipMemcpy(dA, tmp.data(), es * nn, hipMemcpyHostToDevice));
+            if (B) {
+                const double *Br = static_cast<const double *>(B);
+                for (int j = 0; j < N; ++j)
+                    for (int i = 0; i < N; ++i) tmp[i + (size_t)j * N] = make_double2(Br[i + (size_t)j * ldb], 0.0);
+                FX_CHECK(hipMemcpy(dB, tmp.data(), es * nn, hipMemcpyHostToDevice));
+            }
+        } else {
+            FX_CHECK(hipMemcpy2DAsync(dA, es * N, A, es * lda, es * N, N, hipMemcpyHostToDevice, s));
+            if (B) FX_CHECK(hipMemcpy2DAsync(dB, es * N, B, es * ldb, es * N, N, hipMemcpyHostToDevice, s));
+        }
+        if (o.x0) FX_CHECK(hipMemcpy2DAsync(dX, es * N, X, es * ldx, es * N, 2 * m0, hipMemcpyHostToDevice, s));
+        fx::GProblem pb{N, dA, N, dB, N, emid, r, m0, dX, N};
+        try {
+            info = fx::run_general(pb, o, s, ws, out, st);
+        } catch (const fx::solver_error &e) {
+            (void)hipStreamSynchronize(s);
+            info = e.info;
+        }
+        if (info >= 0 && info <= 3) {
+            FX_CHECK(hipMemcpy2DAsync(X, es * ldx, dX, es * N, es * N, 2 * m0, hipMemcpyDeviceToHost, s));
+            FX_CHECK(hipStreamSynchronize(s));
+        }
+    } catch (const fx::alloc_error &) {
+        info = -1;
+    } catch (const fx::hip_error &e) {
+        std::fprintf(stderr, "feastx: HIP error %s\n", hipGetErrorString(e.code));
+        info = -4;
+    }
+    fx::g_stats = st;
+    if (info >= 0 && info <= 3) {
+        for (int i = 0; i < m0; ++i) {
+            E[i].re = out.E[i].x;
+            E[i].im = out.E[i].y;
+            res[i] = out.res[i];
+            res[m0 + i] = out.res[m0 + i];
+        }
+        *M = out.M;
+        if (loop) *loop = out.loop;
+        if (epsout) *epsout = out.epsout;
+    }
+    return info;
+}
+
+int feast_gsolve_z(int N, const feast_z *A, int lda, const feast_z *B, int ldb, feast_z Emid, double r, int *M0,
+                   const feast_opts *opts, feast_z *E, feast_z *X, int ldx, int *M, double *res, int *loop,
+                   double *epsout)
+{
+    return gsolve(false, N, A, lda, B, ldb, Emid, r, M0, opts, E, X, ldx, M, res, loop, epsout);
+}
+
+int feast_gsolve_d(int N, const double *A, int lda, const double *B, int ldb, feast_z Emid, double r, int *M0,
+                   const feast_opts *opts, feast_z *E, feast_z *X, int ldx, int *M, double *res, int *loop,
+                   double *epsout)
+{
+    return gsolve(true, N, A, lda, B, ldb, Emid, r, M0, opts, E, X, ldx, M, res, loop, epsout);
 }
 
 // ---------------------------------------------------------------- slicing

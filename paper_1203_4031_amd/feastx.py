@@ -28,7 +28,8 @@ class feast_opts(C.Structure):
                 ("keep_factors", C.c_int), ("precision", C.c_int), ("refine", C.c_int),
                 ("mode", C.c_int), ("verbose", C.c_int), ("tol", C.c_double),
                 ("seed", C.c_ulonglong), ("integration", C.c_int), ("ellipse", C.c_int),
-                ("Zne", C.c_void_p), ("Wne", C.c_void_p)]
+                ("Zne", C.c_void_p), ("Wne", C.c_void_p), ("ne_full", C.c_int),
+                ("integration_full", C.c_int), ("angle", C.c_int)]
 
 
 class feast_stats(C.Structure):
@@ -102,6 +103,9 @@ def lib():
         for name in ("feast_solve_batched_d", "feast_solve_batched_z"):
             f = getattr(L, name)
             f.argtypes = [C.c_int, C.POINTER(feast_job), op, C.c_int, C.c_int]
+        for f in (L.feast_gsolve_d, L.feast_gsolve_z):
+            f.argtypes = [C.c_int, vp, C.c_int, vp, C.c_int, feast_z, C.c_double, ip, op, vp, vp, C.c_int, ip,
+                          dp, ip, dp]
         for f in (L.feast_solve_slices_d, L.feast_solve_slices_z):
             f.argtypes = [C.c_int, vp, C.c_int, vp, C.c_int, C.c_int, dp, C.POINTER(feast_job), op, C.c_int,
                           C.c_int, C.c_int]
@@ -322,6 +326,36 @@ def solve_batched(problems, concurrency=4, **kw) -> list[Result]:
         r.ms = j.ms
         out.append(r)
     return out
+
+
+def gsolve(A, B, emid, r, m0, X0=None, **kw) -> Result:
+    """Non-Hermitian FEAST (host arrays): A, B general real or complex (B may
+    be None); the search region is the ellipse centred at emid (complex) with
+    horizontal semi-axis r.  X0: optional (N, 2 M0) start subspaces (right,
+    then left).  Options as in make_opts plus ne_full (fpm(8)),
+    integration_full (fpm(17)) and angle (fpm(19)).  Returns E complex (M0),
+    X (N, 2 M0) with right then left eigenvectors, res (2 M0)."""
+    ne_full = kw.pop("ne_full", 16)
+    integration_full = kw.pop("integration_full", 1)
+    angle = kw.pop("angle", 0)
+    real = not (np.iscomplexobj(A) or (B is not None and np.iscomplexobj(B)))
+    dt = np.float64 if real else np.complex128
+    A = np.asfortranarray(A, dtype=dt)
+    n = A.shape[0]
+    Bf = None if B is None else np.asfortranarray(B, dtype=dt)
+    o = make_opts(x0=X0 is not None, **kw)
+    o.ne_full, o.integration_full, o.angle = ne_full, integration_full, angle
+    X = np.zeros((n, 2 * m0), dtype=np.complex128, order="F")
+    if X0 is not None:
+        X[:, :] = X0
+    E = np.zeros(m0, dtype=np.complex128)
+    res = np.zeros(2 * m0)
+    M, loop, eps, m0c = C.c_int(0), C.c_int(0), C.c_double(0), C.c_int(m0)
+    z = feast_z(float(np.real(emid)), float(np.imag(emid)))
+    f = lib().feast_gsolve_d if real else lib().feast_gsolve_z
+    info = f(n, A.ctypes.data, n, None if Bf is None else Bf.ctypes.data, n, z, float(r), C.byref(m0c),
+             C.byref(o), E.ctypes.data, X.ctypes.data, n, C.byref(M), _dp(res), C.byref(loop), C.byref(eps))
+    return Result(info, E, X, res, M.value, m0, loop.value, eps.value)
 
 
 def solve_slices(A, B, bounds, m0, X0=None, concurrency=4, auto_m0=False, **kw) -> list[Result]:

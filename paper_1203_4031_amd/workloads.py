@@ -267,3 +267,61 @@ def batched_real_generalized(nprob: int = 256, nmin: int = 256, nmax: int = 2048
         out.append(dense_real_generalized(n, count, ne=ne, tol=tol, seed=seed + 1 + i,
                                           x0_seed=seed + 100000 + i))
     return out
+
+
+def dense_general(n: int = 512, count: int = 24, m0: int | None = None, ne: int = 16, tol: float = 1e-10,
+                  seed: int = 6001, real: bool = False, generalized: bool = True,
+                  centre: complex = 0.2 + 0.1j) -> Problem:
+    """Dense non-Hermitian pencil with a known spectrum.
+
+    Eigenvalues: uniform in the square [-1, 1] x [-1, 1] (complex), or, for a
+    real pencil, real values uniform in [-1, 1] for a fifth of them and
+    conjugate pairs a +- i b for the rest.  A0 = S D S^{-1} with S = I + G /
+    (2 sqrt(n)) (G Gaussian; non-normal, well conditioned) and D the
+    eigenvalues (2 x 2 blocks [[a, b], [-b, a]] for real pairs).  With B =
+    I + H / (4 sqrt(n)) (H Gaussian) the pencil is (B A0, B), whose
+    eigenvalues are those of A0; without B it is A0.  The search region is
+    the circle about ``centre`` (on the real axis for a real pencil) through
+    the midpoint between the count-th and (count+1)-th nearest eigenvalues, so
+    ``count`` eigenvalues lie inside (one more when the count-th is half of a
+    conjugate pair; meta["count"] holds the number).  emin, emax of the returned Problem hold Emid (complex) and r;
+    spectrum holds the eigenvalues; X0 holds right and left start subspaces
+    (n x 2 M0, real uniform(-1, 1))."""
+    rng = _rng(seed)
+    if real:
+        centre = complex(centre.real, 0.0)
+        nreal = n // 5
+        npair = (n - nreal) // 2
+        nreal = n - 2 * npair
+        lr = rng.uniform(-1.0, 1.0, nreal)
+        a = rng.uniform(-1.0, 1.0, npair)
+        b = rng.uniform(0.05, 1.0, npair)
+        D = np.zeros((n, n))
+        D[np.arange(nreal), np.arange(nreal)] = lr
+        for k in range(npair):
+            i = nreal + 2 * k
+            D[i, i] = D[i + 1, i + 1] = a[k]
+            D[i, i + 1] = b[k]
+            D[i + 1, i] = -b[k]
+        lam = np.concatenate([lr + 0j, a + 1j * b, a - 1j * b])
+        S = np.eye(n) + rng.standard_normal((n, n)) / (2.0 * math.sqrt(n))
+        A0 = S @ D @ np.linalg.inv(S)
+        Bm = np.eye(n) + rng.standard_normal((n, n)) / (4.0 * math.sqrt(n)) if generalized else None
+    else:
+        lam = rng.uniform(-1.0, 1.0, n) + 1j * rng.uniform(-1.0, 1.0, n)
+        G = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / math.sqrt(2.0)
+        S = np.eye(n) + G / (2.0 * math.sqrt(n))
+        A0 = (S * lam) @ np.linalg.inv(S)
+        H = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / math.sqrt(2.0)
+        Bm = np.eye(n) + H / (4.0 * math.sqrt(n)) if generalized else None
+    A = A0 if Bm is None else Bm @ A0
+    d = np.sort(np.abs(lam - centre))
+    while count < n and d[count] - d[count - 1] < 1e-9:   # keep conjugate pairs together
+        count += 1
+    r = 0.5 * (d[count - 1] + d[count])
+    if m0 is None:
+        m0 = int(math.ceil(1.5 * count)) + 4
+    x0 = _rng(seed + 99).uniform(-1.0, 1.0, size=(n, 2 * m0))
+    return Problem(f"general{n}{'r' if real else 'c'}", np.asfortranarray(A),
+                   None if Bm is None else np.asfortranarray(Bm), centre, r, m0, ne, tol,
+                   np.asfortranarray(x0), not real, lam, {"seed": seed, "count": count})

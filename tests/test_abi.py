@@ -113,3 +113,28 @@ def test_slice_argument_errors_need_no_gpu(kw, code):
                                              args["nslices"], b.ctypes.data_as(C.POINTER(C.c_double)), jobs,
                                              C.byref(o), args["device"], 2, 0)
     assert info == code
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n=0), 202), (dict(m0=0), 201), (dict(m0=5), 201), (dict(r=0.0), 200), (dict(r=float("nan")), 200),
+    (dict(ne_full=0), 108), (dict(ne_full=257), 108), (dict(tol=0.0), 103), (dict(mode=1), 114),
+    (dict(precision=1), 140), (dict(integration_full=2), 117), (dict(ellipse=0), 118), (dict(angle=181), 119),
+    (dict(lda=2), -103),
+])
+def test_gsolve_argument_errors_need_no_gpu(kw, code):
+    """feast_gsolve checks its arguments before any device call."""
+    args = dict(n=4, m0=2, r=1.0, ne_full=16, tol=1e-10, mode=0, precision=0, integration_full=1, ellipse=100,
+                angle=0, lda=4)
+    args.update(kw)
+    n = max(args["n"], 1)
+    A = np.eye(n, order="F")
+    o = feastx.make_opts(tol=args["tol"], mode=args["mode"], precision=args["precision"], ellipse=args["ellipse"])
+    o.ne_full, o.integration_full, o.angle = args["ne_full"], args["integration_full"], args["angle"]
+    E = np.zeros(8, dtype=np.complex128)
+    X = np.zeros((n, 16), dtype=np.complex128, order="F")
+    res = np.zeros(16)
+    M, m0 = C.c_int(0), C.c_int(args["m0"])
+    info = feastx.lib().feast_gsolve_d(args["n"], A.ctypes.data, args["lda"], None, n, feastx.feast_z(0.0, 0.0),
+                                       args["r"], C.byref(m0), C.byref(o), E.ctypes.data, X.ctypes.data, n,
+                                       C.byref(M), res.ctypes.data_as(C.POINTER(C.c_double)), None, None)
+    assert info == code
