@@ -202,6 +202,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=None)
     ap.add_argument("--roofline-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the slicing, non-Hermitian and count-estimate measurements (profiler passes)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device-to-device 5 times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -325,14 +327,15 @@ def main():
                          "note": "update_*: the LU's complex64 product launches alone (8 flops per complex "
                                  "multiply-add); factor_*: Ne (8/3) N^3 over the whole factor stage, timed with "
                                  "per-launch events on (so slightly slow)"}
-    out["slicing"] = slicing(feastx, torch, W, A, B, p, expected, wall / args.steps * 1e3)
-    log(f"slicing: {out['slicing']['ms']:.1f} ms for {expected} eigenpairs in {out['slicing']['slices']} slices")
-    out["nonhermitian"] = nonhermitian(feastx, W)
-    log(f"non-Hermitian N=2048: {out['nonhermitian']['device_ms']:.1f} ms on the device, "
-        f"{out['nonhermitian']['loops']} loops")
-    out["count_estimate"] = count_estimate(feastx, torch, W, A, B, p, expected)
-    log(f"count estimate: {out['count_estimate']['estimate']} (count {expected}) in "
-        f"{out['count_estimate']['ms']:.1f} ms")
+    if not args.no_extras:
+        out["slicing"] = slicing(feastx, torch, W, A, B, p, expected, wall / args.steps * 1e3)
+        log(f"slicing: {out['slicing']['ms']:.1f} ms for {expected} eigenpairs in {out['slicing']['slices']} slices")
+        out["nonhermitian"] = nonhermitian(feastx, W)
+        log(f"non-Hermitian N=2048: {out['nonhermitian']['device_ms']:.1f} ms on the device, "
+            f"{out['nonhermitian']['loops']} loops")
+        out["count_estimate"] = count_estimate(feastx, torch, W, A, B, p, expected)
+        log(f"count estimate: {out['count_estimate']['estimate']} (count {expected}) in "
+            f"{out['count_estimate']['ms']:.1f} ms")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, loops)
     print(json.dumps(out), flush=True)
