@@ -34,7 +34,7 @@ N, COUNT, M0, NE, TOL, SEED = 4096, 200, 300, 8, 1e-10, 2001
 # launches it (the FP64 reduced-problem kernels in jacobi.hpp and
 # bortho.hpp do not): `traffic` is null when they differ.
 TRAFFIC_BYTES_PER_LAUNCH = 1.196e+08
-TRAFFIC_SOURCES_SHA256 = "d938117cc1a831c56c15d49a9cfc166e1f673610e8ef4e47eed245781a01fc8c"
+TRAFFIC_SOURCES_SHA256 = "4964836dbb625ccee6eaa050e5f5024daa124e0f8ac239ac1aad7253249b88a5"
 
 
 def kernel_sources_sha256():
