@@ -113,9 +113,10 @@ struct grid_sync {
     {
         // __syncthreads() orders every wave's stores before thread 0's
         // arrival, a release at agent scope.  The last arrival reads the end
-        // of the release sequence on `count`, acquires (so it has every
-        // block's data) and releases the generation word; the others poll it
-        // with relaxed loads and acquire once it has moved.  Polling with
+        // of the release sequence on `count`, resets it and releases the
+        // generation word, then acquires (so it has every block's data); the
+        // others poll the generation with relaxed loads and acquire once it
+        // has moved.  Polling with
         // acquire loads would invalidate the XCD's L2 on every poll and cost
         // the other workgroups there their cached lines.
         __syncthreads();
@@ -123,9 +124,12 @@ struct grid_sync {
             const unsigned g = local_gen;
             const unsigned prev = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             if (prev == nblocks - 1) {
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                // release the others first; this block's own acquire (which
+                // pairs with every arrival's release through the read of
+                // `count` above) can follow off their critical path
                 __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             } else {
                 while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g)
                     __builtin_amdgcn_s_sleep(1);
