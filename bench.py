@@ -202,6 +202,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=None)
     ap.add_argument("--roofline-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["nonhermitian"], default=None,
+                    help="run only this extra measurement and print its JSON object (profiler passes)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the slicing, non-Hermitian and count-estimate measurements (profiler passes)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -230,6 +232,10 @@ def main():
 
     feastx.lib()
     torch.cuda.set_device(0)
+    if args.only == "nonhermitian":
+        print(json.dumps(nonhermitian(feastx, W, steps=max(args.steps, 1))), flush=True)
+        feastx.release()
+        return
     t0 = time.perf_counter()
     p = W.dense_real_generalized(N, COUNT, m0=M0, ne=NE, tol=TOL, seed=SEED)
     expected = p.count_in_interval()

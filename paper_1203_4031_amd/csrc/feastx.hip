@@ -1179,15 +1179,25 @@ static int run_general(const GProblem &pb, const feast_opts &o, hipStream_t s, W
         tm.mark(&st.t_rr);
 
         // reduced eigenproblem: C = Bq^{-1} Aq = W Lambda W^{-1}, Wh = (W^{-1} Bq^{-1})^H
-        hipLaunchKernelGGL(gj_inverse_kernel, dim3(1), dim3(NH_NT), 0, s, m0, Bq, Binv, dstat);
+        auto gj_inverse = [&](E *Mx, E *Inv, int *stat) {
+            if (m0 <= 64)   // both matrices in LDS
+                hipLaunchKernelGGL((gj_inverse_kernel<NH_NT, 64>), dim3(1), dim3(NH_NT), 0, s, m0, Mx, Inv, stat);
+            else
+                hipLaunchKernelGGL((gj_inverse_kernel<NH_NT, 0>), dim3(1), dim3(NH_NT), 0, s, m0, Mx, Inv, stat);
+        };
+        gj_inverse(Bq, Binv, dstat);
         FX_LAUNCH_CHECK();
         dgemm<true>(ws, s, false, m0, m0, m0, 1.0, Binv, m0, Aq, m0, 0.0, Cm, m0);
-        hipLaunchKernelGGL(eig_general_kernel, dim3(1), dim3(NH_NT), 0, s, m0, Cm, Zs, Ys, lam, dstat + 1);
+        if (m0 <= 64)   // the Hessenberg matrix and the Schur vectors in LDS, one wave
+            hipLaunchKernelGGL((eig_general_kernel<64, 64>), dim3(1), dim3(64), 0, s, m0, Cm, Zs, Ys, lam, dstat + 1);
+        else
+            hipLaunchKernelGGL((eig_general_kernel<NH_NT, 0>), dim3(1), dim3(NH_NT), 0, s, m0, Cm, Zs, Ys, lam,
+                               dstat + 1);
         FX_LAUNCH_CHECK();
         dgemm<true>(ws, s, false, m0, m0, m0, 1.0, Zs, m0, Ys, m0, 0.0, Wm, m0);
         hipLaunchKernelGGL((copy_block_kernel<true>), grid1(mm), dim3(256), 0, s, m0, m0, Wm, (long)m0, Wc,
                            (long)m0);
-        hipLaunchKernelGGL(gj_inverse_kernel, dim3(1), dim3(NH_NT), 0, s, m0, Wc, Winv, dstat + 3);
+        gj_inverse(Wc, Winv, dstat + 3);
         FX_LAUNCH_CHECK();
         dgemm<true>(ws, s, false, m0, m0, m0, 1.0, Winv, m0, Binv, m0, 0.0, G, m0);
         hipLaunchKernelGGL(conj_transpose_kernel, grid1(mm), dim3(256), 0, s, m0, G, Wh);
@@ -1452,9 +1462,12 @@ static void solve_in(Workspace &ws, const feast_opts &o, const SolveArgs &a, Sol
         void *dA = ws.get("in_A", es * (size_t)N * N);
         void *dB = a.B ? ws.get("in_B", es * (size_t)N * N) : nullptr;
         void *dX = ws.get("in_X", es * (size_t)N * a.m0);
-        FX_CHECK(hipMemcpy2DAsync(dA, es * N, a.A, es * a.lda, es * N, N, hipMemcpyHostToDevice, s));
-        if (a.B) FX_CHECK(hipMemcpy2DAsync(dB, es * N, a.B, es * a.ldb, es * N, N, hipMemcpyHostToDevice, s));
-        if (o.x0) FX_CHECK(hipMemcpy2DAsync(dX, es * N, a.X, es * a.ldx, es * N, a.m0, hipMemcpyHostToDevice, s));
+        // blocking uploads: each has landed before any kernel of the solve is
+        // launched (an asynchronous copy from pageable memory was seen to be
+        // overtaken by the stream's kernels under a profiler)
+        FX_CHECK(hipMemcpy2D(dA, es * N, a.A, es * a.lda, es * N, N, hipMemcpyHostToDevice));
+        if (a.B) FX_CHECK(hipMemcpy2D(dB, es * N, a.B, es * a.ldb, es * N, N, hipMemcpyHostToDevice));
+        if (o.x0) FX_CHECK(hipMemcpy2D(dX, es * N, a.X, es * a.ldx, es * N, a.m0, hipMemcpyHostToDevice));
         Problem pb{N, static_cast<const double *>(dA), N, static_cast<const double *>(dB), N, a.emin, a.emax, a.m0,
                    static_cast<double *>(dX), N};
         info = dispatch(a.cplx, pb, o, s, ws, out, so.st);
@@ -1950,10 +1963,11 @@ static int gsolve(bool real_in, int N, const void *A, int lda, const void *B, in
                 FX_CHECK(hipMemcpy(dB, tmp.data(), es * nn, hipMemcpyHostToDevice));
             }
         } else {
-            FX_CHECK(hipMemcpy2DAsync(dA, es * N, A, es * lda, es * N, N, hipMemcpyHostToDevice, s));
-            if (B) FX_CHECK(hipMemcpy2DAsync(dB, es * N, B, es * ldb, es * N, N, hipMemcpyHostToDevice, s));
+            FX_CHECK(hipMemcpy2D(dA, es * N, A, es * lda, es * N, N, hipMemcpyHostToDevice));
+            if (B) FX_CHECK(hipMemcpy2D(dB, es * N, B, es * ldb, es * N, N, hipMemcpyHostToDevice));
         }
-        if (o.x0) FX_CHECK(hipMemcpy2DAsync(dX, es * N, X, es * ldx, es * N, 2 * m0, hipMemcpyHostToDevice, s));
+        // blocking upload, as in the Hermitian host path
+        if (o.x0) FX_CHECK(hipMemcpy2D(dX, es * N, X, es * ldx, es * N, 2 * m0, hipMemcpyHostToDevice));
         fx::GProblem pb{N, dA, N, dB, N, emid, r, m0, dX, N};
         try {
             info = fx::run_general(pb, o, s, ws, out, st);

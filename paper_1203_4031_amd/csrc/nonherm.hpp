@@ -72,111 +72,147 @@ constexpr int NH_NT = 256;   // threads of the single-workgroup dense kernels
 constexpr int NH_MAXM = 1024;
 
 // Inverse of an m x m matrix by Gauss-Jordan elimination with partial
-// pivoting (largest |re| + |im|, ties to the lowest row).  Mx is destroyed.
-// status = 0, or k + 1 when column k has no nonzero pivot.
-__global__ __launch_bounds__(NH_NT) void gj_inverse_kernel(int m, double2 *__restrict__ Mx, double2 *__restrict__ Inv,
-                                                           int *__restrict__ status)
+// pivoting (largest |re| + |im|, ties to the lowest row).  Mx is destroyed
+// (left as is when LDSM > 0).  status = 0, or k + 1 when column k has no
+// nonzero pivot.  NT threads; with LDSM > 0 (m <= LDSM) both matrices are
+// worked on in LDS (leading dimension LDSM + 1) and Inv is written at the end.
+template <int NT, int LDSM>
+__global__ __launch_bounds__(NT) void gj_inverse_kernel(int m, double2 *__restrict__ Mg, double2 *__restrict__ Ig,
+                                                        int *__restrict__ status)
 {
-    __shared__ double2 fcol[NH_MAXM];
-    __shared__ double s_v[NH_NT];
-    __shared__ int s_i[NH_NT];
-    const int tid = threadIdx.x;
-    for (long e = tid; e < (long)m * m; e += NH_NT) {
+    constexpr int HLD = LDSM > 0 ? LDSM + 1 : 1;
+    __shared__ double2 Ms[LDSM > 0 ? HLD * LDSM : 1];
+    __shared__ double2 Is[LDSM > 0 ? HLD * LDSM : 1];
+    __shared__ double2 fcol[LDSM > 0 ? LDSM : NH_MAXM];
+    __shared__ double s_v[NT / 64];
+    __shared__ int s_i[NT / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const long ld = LDSM > 0 ? HLD : m;
+    double2 *Mx = Mg, *Inv = Ig;
+    if constexpr (LDSM > 0) {
+        Mx = Ms;
+        Inv = Is;
+    }
+    for (long e = tid; e < (long)m * m; e += NT) {
         const int i = (int)(e % m), j = (int)(e / m);
-        Inv[e] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+        Inv[i + j * ld] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+        if constexpr (LDSM > 0) Mx[i + j * ld] = Mg[e];
     }
     int fail = 0;
     __syncthreads();
     for (int k = 0; k < m; ++k) {
         double best = -1.0;
         int bi = m;
-        for (int i = k + tid; i < m; i += NH_NT) {
-            const double v = zabs1(Mx[i + (long)k * m]);
+        for (int i = k + tid; i < m; i += NT) {
+            const double v = zabs1(Mx[i + (long)k * ld]);
             if (v > best) {
                 best = v;
                 bi = i;
             }
         }
-        s_v[tid] = best;
-        s_i[tid] = bi;
-        __syncthreads();
-        for (int h = NH_NT / 2; h > 0; h >>= 1) {
-            if (tid < h) {
-                const double v2 = s_v[tid + h];
-                const int i2 = s_i[tid + h];
-                if (v2 > s_v[tid] || (v2 == s_v[tid] && i2 < s_i[tid])) {
-                    s_v[tid] = v2;
-                    s_i[tid] = i2;
-                }
+        // argmax: within each wave by shuffles, then across the waves
+        for (int off = 32; off > 0; off >>= 1) {
+            const double v2 = __shfl_xor(best, off, 64);
+            const int i2 = __shfl_xor(bi, off, 64);
+            if (v2 > best || (v2 == best && i2 < bi)) {
+                best = v2;
+                bi = i2;
             }
-            __syncthreads();
         }
-        const double pv = s_v[0];
-        const int p = s_i[0];
+        if (lane == 0) {
+            s_v[wid] = best;
+            s_i[wid] = bi;
+        }
+        __syncthreads();
+        double pv = s_v[0];
+        int p = s_i[0];
+        for (int w = 1; w < NT / 64; ++w)
+            if (s_v[w] > pv || (s_v[w] == pv && s_i[w] < p)) {
+                pv = s_v[w];
+                p = s_i[w];
+            }
         __syncthreads();
         if (!(pv > 0.0)) {
             fail = k + 1;
             break;
         }
         if (p != k) {
-            for (int j = tid; j < m; j += NH_NT) {
-                const double2 a = Mx[k + (long)j * m], b = Mx[p + (long)j * m];
-                Mx[k + (long)j * m] = b;
-                Mx[p + (long)j * m] = a;
-                const double2 c = Inv[k + (long)j * m], d = Inv[p + (long)j * m];
-                Inv[k + (long)j * m] = d;
-                Inv[p + (long)j * m] = c;
+            for (int j = tid; j < m; j += NT) {
+                const double2 a = Mx[k + (long)j * ld], b = Mx[p + (long)j * ld];
+                Mx[k + (long)j * ld] = b;
+                Mx[p + (long)j * ld] = a;
+                const double2 c = Inv[k + (long)j * ld], d = Inv[p + (long)j * ld];
+                Inv[k + (long)j * ld] = d;
+                Inv[p + (long)j * ld] = c;
             }
         }
         __syncthreads();
-        const double2 pinv = zdiv(make_double2(1.0, 0.0), Mx[k + (long)k * m]);
+        const double2 pinv = zdiv(make_double2(1.0, 0.0), Mx[k + (long)k * ld]);
         __syncthreads();
-        for (int j = tid; j < m; j += NH_NT) {
-            if (j >= k) Mx[k + (long)j * m] = zmul(Mx[k + (long)j * m], pinv);
-            Inv[k + (long)j * m] = zmul(Inv[k + (long)j * m], pinv);
+        for (int j = tid; j < m; j += NT) {
+            if (j >= k) Mx[k + (long)j * ld] = zmul(Mx[k + (long)j * ld], pinv);
+            Inv[k + (long)j * ld] = zmul(Inv[k + (long)j * ld], pinv);
         }
         __syncthreads();
-        for (int i = tid; i < m; i += NH_NT) fcol[i] = (i == k) ? make_double2(0.0, 0.0) : Mx[i + (long)k * m];
+        for (int i = tid; i < m; i += NT) fcol[i] = (i == k) ? make_double2(0.0, 0.0) : Mx[i + (long)k * ld];
         __syncthreads();
-        for (long e = tid; e < (long)m * m; e += NH_NT) {
+        for (long e = tid; e < (long)m * m; e += NT) {
             const int i = (int)(e % m), j = (int)(e / m);
             const double2 f = fcol[i];
             if (i == k || (f.x == 0.0 && f.y == 0.0)) continue;
-            if (j >= k) Mx[e] = zsub(Mx[e], zmul(f, Mx[k + (long)j * m]));
-            Inv[e] = zsub(Inv[e], zmul(f, Inv[k + (long)j * m]));
+            if (j >= k) Mx[i + j * ld] = zsub(Mx[i + j * ld], zmul(f, Mx[k + (long)j * ld]));
+            Inv[i + j * ld] = zsub(Inv[i + j * ld], zmul(f, Inv[k + (long)j * ld]));
         }
         __syncthreads();
+    }
+    if constexpr (LDSM > 0) {
+        for (long e = tid; e < (long)m * m; e += NT) Ig[e] = Inv[(e % m) + (e / m) * ld];
     }
     if (tid == 0) status[0] = fail;
 }
 
 // Eigenvalues and eigenvectors of a general complex m x m matrix (m <=
-// NH_MAXM) held in H (destroyed: on return the Schur form T).  Z (m x m) gets
-// the unitary Schur vectors (C = Z T Z^H), Y (m x m) the eigenvectors of T
-// (upper triangular, Y[k][k] = 1), lam the eigenvalues T[k][k].  The
-// caller forms W = Z Y.  status[0] = 0, or -1 when the QR iteration did not
-// converge within 30 m sweeps; status[1] = sweeps.
-__global__ __launch_bounds__(NH_NT) void eig_general_kernel(int m, double2 *__restrict__ H, double2 *__restrict__ Z,
-                                                            double2 *__restrict__ Y, double2 *__restrict__ lam,
-                                                            int *__restrict__ status)
+// NH_MAXM) held in H (destroyed).  Z (m x m) gets the unitary Schur vectors
+// (C = Z T Z^H, T the Schur form), Y (m x m) the eigenvectors of T (upper
+// triangular, Y[k][k] = 1), lam the eigenvalues T[k][k].  The caller forms
+// W = Z Y.  status[0] = 0, or -1 when the QR iteration did not converge
+// within 30 m sweeps; status[1] = sweeps.
+// NT threads.  With LDSM > 0 (m <= LDSM) the working copy of H lives in LDS
+// (leading dimension LDSM + 1): each Givens rotation then costs a few LDS
+// accesses instead of dependent round trips to memory, which is what bounds
+// this kernel; so does Z, written out at the end.
+template <int NT, int LDSM>
+__global__ __launch_bounds__(NT) void eig_general_kernel(int m, double2 *__restrict__ H, double2 *__restrict__ Z,
+                                                         double2 *__restrict__ Y, double2 *__restrict__ lam,
+                                                         int *__restrict__ status)
 {
-    __shared__ double2 sv[NH_MAXM];
-    __shared__ double s_red[NH_NT / 64];
+    constexpr int HLD = LDSM > 0 ? LDSM + 1 : 1;
+    __shared__ double2 Hs[LDSM > 0 ? HLD * LDSM : 1];
+    __shared__ double2 Zs[LDSM > 0 ? HLD * LDSM : 1];
+    __shared__ double2 sv[LDSM > 0 ? LDSM : NH_MAXM];
+    __shared__ double s_red[NT / 64];
     const int tid = threadIdx.x;
     const double ulp = 2.220446049250313e-16, smlnum = 2.2250738585072014e-308 * ((double)m / ulp);
-    auto at = [&](int i, int j) -> double2 & { return H[i + (long)j * m]; };
+    const long ldh = LDSM > 0 ? HLD : m;   // leading dimension of the working H and Z
+    double2 *Hw = H, *Zw = Z;
+    if constexpr (LDSM > 0) {
+        for (long e = tid; e < (long)m * m; e += NT) Hs[(e % m) + (e / m) * HLD] = H[e];
+        Hw = Hs;
+        Zw = Zs;
+    }
+    auto at = [&](int i, int j) -> double2 & { return Hw[i + (long)j * ldh]; };
     auto block_sum = [&](double v) {
         v = wave_sum(v);
         if ((tid & 63) == 0) s_red[tid >> 6] = v;
         __syncthreads();
         double t = 0.0;
-        for (int q = 0; q < NH_NT / 64; ++q) t += s_red[q];
+        for (int q = 0; q < NT / 64; ++q) t += s_red[q];
         __syncthreads();
         return t;
     };
-    for (long e = tid; e < (long)m * m; e += NH_NT) {
+    for (long e = tid; e < (long)m * m; e += NT) {
         const int i = (int)(e % m), j = (int)(e / m);
-        Z[e] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+        Zw[i + j * ldh] = make_double2(i == j ? 1.0 : 0.0, 0.0);
     }
     __syncthreads();
 
@@ -184,7 +220,7 @@ __global__ __launch_bounds__(NH_NT) void eig_general_kernel(int m, double2 *__re
     for (int k = 0; k + 2 < m; ++k) {
         const int L = m - k - 1;   // rows k+1 .. m-1 of column k
         double part = 0.0;
-        for (int t = 1 + tid; t < L; t += NH_NT) {
+        for (int t = 1 + tid; t < L; t += NT) {
             const double2 x = at(k + 1 + t, k);
             part += x.x * x.x + x.y * x.y;
         }
@@ -195,45 +231,46 @@ __global__ __launch_bounds__(NH_NT) void eig_general_kernel(int m, double2 *__re
         const double2 ph = a0 > 0.0 ? zscale(1.0 / a0, x0) : make_double2(1.0, 0.0);
         const double2 alpha = zscale(-xnorm, ph);
         const double beta = 1.0 / (xnorm * (xnorm + a0));   // 2 / ||v||^2
-        for (int t = tid; t < L; t += NH_NT) sv[t] = t == 0 ? zsub(x0, alpha) : at(k + 1 + t, k);
+        for (int t = tid; t < L; t += NT) sv[t] = t == 0 ? zsub(x0, alpha) : at(k + 1 + t, k);
         __syncthreads();
         // left: columns k+1 .. m-1
-        for (int j = k + 1 + tid; j < m; j += NH_NT) {
+        for (int j = k + 1 + tid; j < m; j += NT) {
             double2 d = make_double2(0.0, 0.0);
             for (int t = 0; t < L; ++t) d = zadd(d, zmul(zconj(sv[t]), at(k + 1 + t, j)));
             d = zscale(beta, d);
             for (int t = 0; t < L; ++t) at(k + 1 + t, j) = zsub(at(k + 1 + t, j), zmul(sv[t], d));
         }
-        for (int t = tid; t < L; t += NH_NT) at(k + 1 + t, k) = t == 0 ? alpha : make_double2(0.0, 0.0);
+        for (int t = tid; t < L; t += NT) at(k + 1 + t, k) = t == 0 ? alpha : make_double2(0.0, 0.0);
         __syncthreads();
         // right: rows 0 .. m-1 of H, and of Z
-        for (int i = tid; i < 2 * m; i += NH_NT) {
-            double2 *Mx = i < m ? H : Z;
+        for (int i = tid; i < 2 * m; i += NT) {
+            double2 *Mx = i < m ? Hw : Zw;
+            const long ld = ldh;
             const int r = i < m ? i : i - m;
             double2 d = make_double2(0.0, 0.0);
-            for (int t = 0; t < L; ++t) d = zadd(d, zmul(Mx[r + (long)(k + 1 + t) * m], sv[t]));
+            for (int t = 0; t < L; ++t) d = zadd(d, zmul(Mx[r + (long)(k + 1 + t) * ld], sv[t]));
             d = zscale(beta, d);
             for (int t = 0; t < L; ++t)
-                Mx[r + (long)(k + 1 + t) * m] = zsub(Mx[r + (long)(k + 1 + t) * m], zmul(d, zconj(sv[t])));
+                Mx[r + (long)(k + 1 + t) * ld] = zsub(Mx[r + (long)(k + 1 + t) * ld], zmul(d, zconj(sv[t])));
         }
         __syncthreads();
     }
 
     // a norm for the deflation test of zero diagonals
     double part = 0.0;
-    for (long e = tid; e < (long)m * m; e += NH_NT) part = fmax(part, zabs1(H[e]));
+    for (long e = tid; e < (long)m * m; e += NT) part = fmax(part, zabs1(at((int)(e % m), (int)(e / m))));
     s_red[0] = 0.0;
     __syncthreads();
     {
         // max over the block through the wave maxima
         double v = part;
         for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
-        __shared__ double s_max[NH_NT / 64];
+        __shared__ double s_max[NT / 64];
         if ((tid & 63) == 0) s_max[tid >> 6] = v;
         __syncthreads();
         if (tid == 0) {
             double t = 0.0;
-            for (int q = 0; q < NH_NT / 64; ++q) t = fmax(t, s_max[q]);
+            for (int q = 0; q < NT / 64; ++q) t = fmax(t, s_max[q]);
             s_red[0] = t;
         }
         __syncthreads();
@@ -304,19 +341,20 @@ __global__ __launch_bounds__(NH_NT) void eig_general_kernel(int m, double2 *__re
             }
             __syncthreads();   // every thread has read x and y
             const int j0 = k == l ? l : k - 1;
-            for (int j = j0 + tid; j < m; j += NH_NT) {
+            for (int j = j0 + tid; j < m; j += NT) {
                 const double2 h1 = at(k, j), h2 = at(k + 1, j);
                 at(k, j) = zadd(zscale(c, h1), zmul(sg, h2));
                 at(k + 1, j) = zsub(zscale(c, h2), zmul(zconj(sg), h1));
             }
             __syncthreads();
             const int iend = min(k + 2, hi);
-            for (int i = tid; i < (iend + 1) + m; i += NH_NT) {
-                double2 *Mx = i <= iend ? H : Z;
+            for (int i = tid; i < (iend + 1) + m; i += NT) {
+                double2 *Mx = i <= iend ? Hw : Zw;
+                const long ld = ldh;
                 const int r = i <= iend ? i : i - (iend + 1);
-                const double2 h1 = Mx[r + (long)k * m], h2 = Mx[r + (long)(k + 1) * m];
-                Mx[r + (long)k * m] = zadd(zscale(c, h1), zmul(h2, zconj(sg)));
-                Mx[r + (long)(k + 1) * m] = zsub(zscale(c, h2), zmul(h1, sg));
+                const double2 h1 = Mx[r + (long)k * ld], h2 = Mx[r + (long)(k + 1) * ld];
+                Mx[r + (long)k * ld] = zadd(zscale(c, h1), zmul(h2, zconj(sg)));
+                Mx[r + (long)(k + 1) * ld] = zsub(zscale(c, h2), zmul(h1, sg));
             }
             __syncthreads();
             if (k > l && tid == 0) at(k + 1, k - 1) = make_double2(0.0, 0.0);
@@ -329,7 +367,7 @@ __global__ __launch_bounds__(NH_NT) void eig_general_kernel(int m, double2 *__re
 
     // ---- eigenvalues, and eigenvectors of the triangular T by back
     //      substitution (one column per thread): (T - t_kk) y = 0, y_k = 1
-    for (int k = tid; k < m; k += NH_NT) {
+    for (int k = tid; k < m; k += NT) {
         const double2 tk = at(k, k);
         lam[k] = tk;
         const double smin = fmax(ulp * zabs1(tk), smlnum);
@@ -342,6 +380,9 @@ __global__ __launch_bounds__(NH_NT) void eig_general_kernel(int m, double2 *__re
             if (zabs1(d) < smin) d = make_double2(smin, 0.0);
             Y[i + (long)k * m] = zdiv(make_double2(-sum.x, -sum.y), d);
         }
+    }
+    if constexpr (LDSM > 0) {
+        for (long e = tid; e < (long)m * m; e += NT) Z[e] = Zw[(e % m) + (e / m) * ldh];
     }
     if (tid == 0) {
         status[0] = fail ? -1 : 0;

@@ -82,3 +82,13 @@ def test_gsolve_library_start_finds_the_spectrum():
     alpha = abs(p.emin) + p.emax
     for l in ref:
         assert np.abs(r.E[:r.M] - l).min() <= 1e-10 * max(abs(l), alpha)
+
+
+def test_gsolve_matches_oracle_beyond_lds_size():
+    """M0 = 76 > 64: the reduced eigensolver and inverses work in memory
+    instead of LDS."""
+    p = W.dense_general(300, count=48, seed=6131)
+    assert p.m0 > 64
+    ref = NH.feast(p.A, p.B, p.emin, p.emax, p.m0, p.ne, p.tol, p.X0)
+    r = feastx.gsolve(p.A, p.B, p.emin, p.emax, p.m0, X0=p.X0, tol=p.tol, ne_full=p.ne)
+    _check(p, r, ref)
