@@ -167,6 +167,15 @@ int feast_gsolve_z(int N, const feast_z *A, int lda, const feast_z *B, int ldb, 
 int feast_gsolve_d(int N, const double *A, int lda, const double *B, int ldb, feast_z Emid, double r, int *M0,
                    const feast_opts *opts, feast_z *E, feast_z *X, int ldx, int *M, double *res, int *loop,
                    double *epsout);
+/* The same on device arrays (complex; a real pencil is passed with zero
+ * imaginary parts): dA, dB (or NULL), dX (N x 2 M0, start subspaces on entry
+ * if opts.x0 = 1, eigenvectors on exit) in HBM, column-major with leading
+ * dimensions lda, ldb, ldx >= N; E, res, M, loop, epsout on the host.  Runs
+ * on `stream` (a hipStream_t; NULL: the library's own) and returns when the
+ * results are ready. */
+int feast_gsolve_z_dev(int N, const feast_z *dA, int lda, const feast_z *dB, int ldb, feast_z Emid, double r,
+                       int *M0, const feast_opts *opts, feast_z *E, feast_z *dX, int ldx, int *M, double *res,
+                       int *loop, double *epsout, void *stream);
 
 /* ---- batched: many independent problems in one call (the guide's first
  * level of parallelism, independent search intervals / problems).  Each job

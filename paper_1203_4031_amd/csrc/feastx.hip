@@ -1919,7 +1919,7 @@ int feast_solve_batched_z(int njobs, feast_job *jobs, const feast_opts *opts, in
 // ---------------------------------------------------------------- non-Hermitian
 static int gsolve(bool real_in, int N, const void *A, int lda, const void *B, int ldb, feast_z Emid, double r,
                   int *M0, const feast_opts *opts, feast_z *E, feast_z *X, int ldx, int *M, double *res, int *loop,
-                  double *epsout)
+                  double *epsout, bool device = false, void *stream = nullptr)
 {
     if (!M0) return -108;
     feast_opts o;
@@ -1944,6 +1944,17 @@ static int gsolve(bool real_in, int N, const void *A, int lda, const void *B, in
     int info;
     try {
         ws.init();
+        if (device) {   // A, B, X already in HBM, on the caller's stream
+            hipStream_t s = stream ? static_cast<hipStream_t>(stream) : ws.stream;
+            fx::GProblem pb{N, reinterpret_cast<const double2 *>(A), lda, reinterpret_cast<const double2 *>(B), ldb,
+                            emid, r, m0, reinterpret_cast<double2 *>(X), ldx};
+            try {
+                info = fx::run_general(pb, o, s, ws, out, st);
+            } catch (const fx::solver_error &e) {
+                (void)hipStreamSynchronize(s);
+                info = e.info;
+            }
+        } else {
         hipStream_t s = ws.stream;
         const size_t nn = (size_t)N * N, es = sizeof(double2);
         double2 *dA = static_cast<double2 *>(ws.get("in_A", es * nn));
@@ -1979,6 +1990,7 @@ static int gsolve(bool real_in, int N, const void *A, int lda, const void *B, in
             FX_CHECK(hipMemcpy2DAsync(X, es * ldx, dX, es * N, es * N, 2 * m0, hipMemcpyDeviceToHost, s));
             FX_CHECK(hipStreamSynchronize(s));
         }
+        }
     } catch (const fx::alloc_error &) {
         info = -1;
     } catch (const fx::hip_error &e) {
@@ -2005,6 +2017,13 @@ int feast_gsolve_z(int N, const feast_z *A, int lda, const feast_z *B, int ldb, 
                    double *epsout)
 {
     return gsolve(false, N, A, lda, B, ldb, Emid, r, M0, opts, E, X, ldx, M, res, loop, epsout);
+}
+
+int feast_gsolve_z_dev(int N, const feast_z *dA, int lda, const feast_z *dB, int ldb, feast_z Emid, double r,
+                       int *M0, const feast_opts *opts, feast_z *E, feast_z *dX, int ldx, int *M, double *res,
+                       int *loop, double *epsout, void *stream)
+{
+    return gsolve(false, N, dA, lda, dB, ldb, Emid, r, M0, opts, E, dX, ldx, M, res, loop, epsout, true, stream);
 }
 
 int feast_gsolve_d(int N, const double *A, int lda, const double *B, int ldb, feast_z Emid, double r, int *M0,

@@ -106,6 +106,8 @@ def lib():
         for f in (L.feast_gsolve_d, L.feast_gsolve_z):
             f.argtypes = [C.c_int, vp, C.c_int, vp, C.c_int, feast_z, C.c_double, ip, op, vp, vp, C.c_int, ip,
                           dp, ip, dp]
+        L.feast_gsolve_z_dev.argtypes = [C.c_int, vp, C.c_int, vp, C.c_int, feast_z, C.c_double, ip, op, vp, vp,
+                                         C.c_int, ip, dp, ip, dp, vp]
         for f in (L.feast_solve_slices_d, L.feast_solve_slices_z):
             f.argtypes = [C.c_int, vp, C.c_int, vp, C.c_int, C.c_int, dp, C.POINTER(feast_job), op, C.c_int,
                           C.c_int, C.c_int]
@@ -355,6 +357,35 @@ def gsolve(A, B, emid, r, m0, X0=None, **kw) -> Result:
     f = lib().feast_gsolve_d if real else lib().feast_gsolve_z
     info = f(n, A.ctypes.data, n, None if Bf is None else Bf.ctypes.data, n, z, float(r), C.byref(m0c),
              C.byref(o), E.ctypes.data, X.ctypes.data, n, C.byref(M), _dp(res), C.byref(loop), C.byref(eps))
+    return Result(info, E, X, res, M.value, m0, loop.value, eps.value)
+
+
+def gsolve_device(A, B, emid, r, m0, X, stream=None, **kw) -> Result:
+    """Non-Hermitian FEAST on device arrays: A, B (or None), X complex128
+    column-major torch CUDA tensors (see fortran_tensor), X of shape (N, 2 M0)
+    holding the start subspaces if x0=True and receiving right then left
+    eigenvectors.  Options as in gsolve."""
+    import torch
+
+    ne_full = kw.pop("ne_full", 16)
+    integration_full = kw.pop("integration_full", 1)
+    angle = kw.pop("angle", 0)
+    n = A.shape[0]
+    for t in (A, B, X):
+        if t is not None and (t.stride(0) != 1 or not t.is_cuda or t.dtype != torch.complex128):
+            raise ValueError("device arrays must be column-major complex128 CUDA tensors")
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    o = make_opts(**kw)
+    o.ne_full, o.integration_full, o.angle = ne_full, integration_full, angle
+    E = np.zeros(m0, dtype=np.complex128)
+    res = np.zeros(2 * m0)
+    M, loop, eps, m0c = C.c_int(0), C.c_int(0), C.c_double(0), C.c_int(m0)
+    z = feast_z(float(np.real(emid)), float(np.imag(emid)))
+    info = lib().feast_gsolve_z_dev(n, A.data_ptr(), A.stride(1), None if B is None else B.data_ptr(),
+                                    n if B is None else B.stride(1), z, float(r), C.byref(m0c), C.byref(o),
+                                    E.ctypes.data, X.data_ptr(), X.stride(1), C.byref(M), _dp(res), C.byref(loop),
+                                    C.byref(eps), C.c_void_p(stream.cuda_stream))
     return Result(info, E, X, res, M.value, m0, loop.value, eps.value)
 
 

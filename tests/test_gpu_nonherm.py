@@ -92,3 +92,19 @@ def test_gsolve_matches_oracle_beyond_lds_size():
     ref = NH.feast(p.A, p.B, p.emin, p.emax, p.m0, p.ne, p.tol, p.X0)
     r = feastx.gsolve(p.A, p.B, p.emin, p.emax, p.m0, X0=p.X0, tol=p.tol, ne_full=p.ne)
     _check(p, r, ref)
+
+
+def test_gsolve_device_arrays_match_host_arrays():
+    """feast_gsolve_z_dev (A, B, X in HBM, caller's stream) returns what the
+    host-array entry point returns."""
+    p = W.dense_general(200, count=12, seed=6141)
+    host = feastx.gsolve(p.A, p.B, p.emin, p.emax, p.m0, X0=p.X0, tol=p.tol, ne_full=16)
+    A = feastx.fortran_tensor(p.A.astype(np.complex128))
+    B = feastx.fortran_tensor(p.B.astype(np.complex128))
+    X = feastx.fortran_tensor(p.X0.astype(np.complex128))
+    dev = feastx.gsolve_device(A, B, p.emin, p.emax, p.m0, X, x0=True, tol=p.tol, ne_full=16)
+    torch.cuda.synchronize()
+    assert dev.info == host.info == 0 and dev.M == host.M and dev.loop == host.loop
+    assert np.array_equal(dev.E, host.E)
+    assert np.array_equal(dev.res, host.res)
+    assert np.array_equal(X.cpu().numpy(), host.X)
