@@ -139,36 +139,40 @@ def slicing(feastx, torch, W, A, B, p, expected, single_ms, steps=3):
 
 def nonhermitian(feastx, W, steps=3):
     """Non-Hermitian FEAST (dual subspaces, full contour of 16 trapezoidal
-    nodes, FP64) on a dense complex generalized pencil, N = 2048, 40
-    eigenvalues in the region, M0 = 64.  `ms`: the device-array entry point
-    with A, B, X resident in HBM; `host_arrays_ms`: one host-array call,
-    including the PCIe upload of A and B."""
+    nodes) on a dense complex generalized pencil, N = 2048, 40 eigenvalues in
+    the region, M0 = 64.  `ms` (FP64) and `mixed_ms`: the device-array entry
+    point with A, B, X resident in HBM; `host_arrays_ms`: one FP64 host-array
+    call, including the PCIe upload of A and B."""
     import torch
 
     p = W.dense_general(2048, count=40, m0=64, seed=6201)
     A, B = feastx.fortran_tensor(p.A), feastx.fortran_tensor(p.B)
     X0 = feastx.fortran_tensor(p.X0.astype(np.complex128))
     X = X0.clone(memory_format=torch.contiguous_format).t().contiguous().t()
-    wall, r = [], None
-    for i in range(steps + 1):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        X.copy_(X0)
-        r = feastx.gsolve_device(A, B, p.emin, p.emax, p.m0, X, x0=True, tol=p.tol, ne_full=16)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        if r.info != 0 or r.M != p.meta["count"]:
-            raise SystemExit(f"non-Hermitian solve failed: info {r.info}, M {r.M} of {p.meta['count']}")
-        if i:
-            wall.append(t1 - t0)
+    times, r = {}, None
+    for prec in ("fp64", "mixed"):
+        wall = []
+        for i in range(steps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            X.copy_(X0)
+            r = feastx.gsolve_device(A, B, p.emin, p.emax, p.m0, X, x0=True, tol=p.tol, ne_full=16, precision=prec)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            if r.info != 0 or r.M != p.meta["count"]:
+                raise SystemExit(f"non-Hermitian {prec} solve failed: info {r.info}, M {r.M} of {p.meta['count']}")
+            if i:
+                wall.append(t1 - t0)
+        times[prec] = (float(np.mean(wall)) * 1e3, r.loop + 1, float(max(r.res[:r.M].max(), r.res[p.m0:p.m0 + r.M].max())))
     t0 = time.perf_counter()
     rh = feastx.gsolve(p.A, p.B, p.emin, p.emax, p.m0, X0=p.X0, tol=p.tol, ne_full=16)
     host_ms = (time.perf_counter() - t0) * 1e3
     if rh.info != 0 or rh.M != r.M:
         raise SystemExit("non-Hermitian host-array solve disagrees")
-    return {"n": p.n, "count": p.meta["count"], "m0": p.m0, "ne_full": 16, "precision": "fp64",
-            "loops": r.loop + 1, "ms": float(np.mean(wall)) * 1e3, "host_arrays_ms": host_ms,
-            "max_res": float(max(r.res[:r.M].max(), r.res[p.m0:p.m0 + r.M].max()))}
+    return {"n": p.n, "count": p.meta["count"], "m0": p.m0, "ne_full": 16,
+            "ms": times["fp64"][0], "loops": times["fp64"][1], "max_res": times["fp64"][2],
+            "mixed_ms": times["mixed"][0], "mixed_loops": times["mixed"][1], "mixed_max_res": times["mixed"][2],
+            "host_arrays_ms": host_ms}
 
 
 def check(results, p, expected_m):

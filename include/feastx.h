@@ -157,8 +157,10 @@ int feast_solve_z_dev(int N, const feast_z *dA, int lda, const feast_z *dB, int 
  *   alpha = |Emid| + r; spurious pairs (inside, with a residual above 0.1 from
  *   the second loop on) have -1.
  *   Convergence (fpm(6) = 1): both residuals of every pair inside below tol.
- *   FP64 only (opts.precision = 1: info 140), normal mode only (opts.mode
- *   != 0: info 114); opts.ne, integration and custom nodes are not used.
+ *   opts.precision: 0 FP64; 1 mixed (complex64 factors and solves, and
+ *   from the second loop on they act only on the FP64 right and left Ritz
+ *   residuals; everything else FP64).  Normal mode only (opts.mode != 0:
+ *   info 114); opts.ne, integration and custom nodes are not used.
  *   info as for feast_solve_*, plus 108 (ne_full), 117 (integration_full),
  *   119 (angle), 200 (r <= 0 or not finite). */
 int feast_gsolve_z(int N, const feast_z *A, int lda, const feast_z *B, int ldb, feast_z Emid, double r, int *M0,

@@ -1044,16 +1044,26 @@ static bool in_region(double2 lam, double2 c, double r, int ellipse, int angle)
     return (ur / r) * (ur / r) + (ui / (a * r)) * (ui / (a * r)) <= 1.0;
 }
 
-// Non-Hermitian FEAST with dual subspaces, FP64 complex throughout:
+// Non-Hermitian FEAST with dual subspaces:
 //   Q = sum_j w_j (z_j B - A)^{-1} B X,  Qh = sum_j conj(w_j) (z_j B - A)^{-H} B^H Xh,
 //   Aq = Qh^H A Q, Bq = Qh^H B Q, Aq W = Bq W Lambda, Wh^H Aq = Lambda Wh^H Bq,
 //   X = Q W, Xh = Qh Wh (unit columns); residuals of both sides.
+// T is the precision of the factors and solves; everything else is FP64.
+// In complex64 (T = float) the loops after the first use the correction
+// form on both sides: with R = A X - B X Lambda and Rh = A^H Xh - B^H Xh
+// conj(Lambda) (FP64), (z B - A)^{-1} B X = (X + (z B - A)^{-1} R)
+// diag(1 / (z - lambda)) and the same for the adjoint, so
+//   Q  = X diag(rho) + sum_j w_j (z_j B - A)^{-1} R diag(1 / (z_j - lambda)),
+//   Qh = Xh diag(conj rho) + sum_j conj(w_j) (z_j B - A)^{-H} Rh diag(1 / conj(z_j - lambda)),
+// rho(lambda) = sum_j w_j / (z_j - lambda): the single-precision error then
+// scales with the residuals, not with X.
+template <typename T>
 static int run_general(const GProblem &pb, const feast_opts &o, hipStream_t s, Workspace &ws, GResult &out,
                        feast_stats &st_out)
 {
-    using T = double;
     using V = cplx<T>;
     using E = double2;
+    const bool mixed = std::is_same<T, float>::value;
     const int n = pb.n, ne = o.ne_full, m0 = pb.m0;
     const double alpha = std::hypot(pb.emid.x, pb.emid.y) + pb.r;
     const size_t nm = (size_t)n * m0, mm = (size_t)m0 * m0;
@@ -1063,9 +1073,11 @@ static int run_general(const GProblem &pb, const feast_opts &o, hipStream_t s, W
 
     Contour ct = make_full_contour(pb.emid, pb.r, ne, o.integration_full, o.ellipse, o.angle);
     double2 *dz = static_cast<double2 *>(ws.get("z", sizeof(double2) * ne));
-    double2 *dw = static_cast<double2 *>(ws.get("coef", sizeof(double2) * ne));
+    double2 *dcoef = static_cast<double2 *>(ws.get("coef", sizeof(double2) * ne * m0));
+    double2 *drho = static_cast<double2 *>(ws.get("grho", sizeof(double2) * m0));
+    double2 *h_coef = static_cast<double2 *>(ws.pinned("h_gcoef", sizeof(double2) * ne * m0));
+    double2 *h_rho = static_cast<double2 *>(ws.pinned("h_grho", sizeof(double2) * m0));
     FX_CHECK(hipMemcpyAsync(dz, ct.z.data(), sizeof(double2) * ne, hipMemcpyHostToDevice, s));
-    FX_CHECK(hipMemcpyAsync(dw, ct.w.data(), sizeof(double2) * ne, hipMemcpyHostToDevice, s));
 
     auto blk = [&](const char *name, size_t count) { return static_cast<E *>(ws.get(name, sizeof(E) * count)); };
     E *X = blk("X", nm), *Xh = blk("Xh", nm), *R = blk("R", nm), *Rh = blk("Rh", nm);
@@ -1079,7 +1091,7 @@ static int run_general(const GProblem &pb, const feast_opts &o, hipStream_t s, W
     int *sel = static_cast<int *>(ws.get("sel", sizeof(int) * m0));
     int *dstat = static_cast<int *>(ws.get("gstat", sizeof(int) * 4));
     const long ldf = n, sF = (long)n * n;
-    V *F = static_cast<V *>(ws.get("F64", sizeof(V) * (size_t)ne * sF));
+    V *F = static_cast<V *>(ws.get(mixed ? "F32" : "F64", sizeof(V) * (size_t)ne * sF));
     int *ipiv = static_cast<int *>(ws.get("ipiv", sizeof(int) * (size_t)ne * n));
     int *perm = static_cast<int *>(ws.get("perm", sizeof(int) * (size_t)ne * n));
     int *swapmap = static_cast<int *>(ws.get("swapmap", sizeof(int) * 2 * (size_t)ne * (1 + 4 * LU_NB)));
@@ -1090,13 +1102,13 @@ static int run_general(const GProblem &pb, const feast_opts &o, hipStream_t s, W
     V *L64 = compose ? static_cast<V *>(ws.get("L64inv", sizeof(V) * (size_t)ne * sI64)) : nullptr;
     V *U64 = compose ? static_cast<V *>(ws.get("U64inv", sizeof(V) * (size_t)ne * sI64)) : nullptr;
     V *Itmp = compose ? static_cast<V *>(ws.get("Invtmp", sizeof(V) * (size_t)ne * sItmp)) : nullptr;
-    V *Wsv = static_cast<V *>(ws.get("Wsolve64", sizeof(V) * (size_t)ne * sF));
-    V *Linv = static_cast<V *>(ws.get("Linv64", sizeof(V) * (size_t)ne * sInv));
-    V *Uinv = static_cast<V *>(ws.get("Uinv64", sizeof(V) * (size_t)ne * sInv));
-    V *Ytmp = static_cast<V *>(ws.get("Yt64", sizeof(V) * (size_t)ne * nm));
-    V *Y = static_cast<V *>(ws.get("Y64", sizeof(V) * (size_t)ne * nm));
-    V *Yh = static_cast<V *>(ws.get("Yh64", sizeof(V) * (size_t)ne * nm));
-    V *Yh2 = static_cast<V *>(ws.get("Yg64", sizeof(V) * (size_t)ne * nm));
+    V *Wsv = static_cast<V *>(ws.get(mixed ? "Wsolve32" : "Wsolve64", sizeof(V) * (size_t)ne * sF));
+    V *Linv = static_cast<V *>(ws.get(mixed ? "Linv32" : "Linv64", sizeof(V) * (size_t)ne * sInv));
+    V *Uinv = static_cast<V *>(ws.get(mixed ? "Uinv32" : "Uinv64", sizeof(V) * (size_t)ne * sInv));
+    V *Ytmp = static_cast<V *>(ws.get(mixed ? "Yt32" : "Yt64", sizeof(V) * (size_t)ne * nm));
+    V *Y = static_cast<V *>(ws.get(mixed ? "Y32" : "Y64", sizeof(V) * (size_t)ne * nm));
+    V *Yh = static_cast<V *>(ws.get(mixed ? "Yh32" : "Yh64", sizeof(V) * (size_t)ne * nm));
+    V *Yh2 = static_cast<V *>(ws.get(mixed ? "Yg32" : "Yg64", sizeof(V) * (size_t)ne * nm));
     double2 *h_lam = static_cast<double2 *>(ws.pinned("h_glam", sizeof(double2) * m0));
     double *h_res = static_cast<double *>(ws.pinned("h_gres", sizeof(double) * 2 * m0));
     int *h_stat = static_cast<int *>(ws.pinned("h_gstat", sizeof(int) * 4));
@@ -1134,8 +1146,16 @@ static int run_general(const GProblem &pb, const feast_opts &o, hipStream_t s, W
     int info = 0, k = 0, M = 0;
     std::vector<char> ins(m0), spur(m0);
     for (k = 0; k <= o.maxloop; ++k) {
-        // right-hand sides B X and B^H Xh
-        if (B) {
+        const bool corr = mixed && k >= 1;
+        // right-hand sides: B X and B^H Xh, or (correction form) the Ritz
+        // residual blocks of the previous loop
+        if (corr) {
+            hipLaunchKernelGGL(ritz_residual_general_kernel, grid1(nm), dim3(256), 0, s, n, m0, AX, BX, (long)n, lam,
+                               0, R);
+            hipLaunchKernelGGL(ritz_residual_general_kernel, grid1(nm), dim3(256), 0, s, n, m0, AhX, BhX, (long)n,
+                               lam, 1, Rh);
+            FX_LAUNCH_CHECK();
+        } else if (B) {
             dgemm<true>(ws, s, false, n, m0, n, 1.0, B, pb.ldb, X, n, 0.0, R, n);
             dgemm<true>(ws, s, true, n, m0, n, 1.0, B, pb.ldb, Xh, n, 0.0, Rh, n);
         } else {
@@ -1161,9 +1181,26 @@ static int run_general(const GProblem &pb, const feast_opts &o, hipStream_t s, W
             st.solve_flops += 2.0 * ne * 8.0 * (double)n * n * m0;
         }
         tm.mark(&st.t_solve);
-        hipLaunchKernelGGL(accumulate_general_kernel, grid1(nm), dim3(256), 0, s, n, m0, ne,
-                           reinterpret_cast<const double2 *>(Y), reinterpret_cast<const double2 *>(Yh2), (long)n,
-                           (long)nm, dw, Q, Qh, (long)n);
+        // quadrature coefficients: w_j, or w_j / (z_j - lambda_c) and rho_c
+        for (int c = 0; c < m0; ++c) {
+            double2 rc = make_double2(0.0, 0.0);
+            for (int j = 0; j < ne; ++j) {
+                double2 w = ct.w[j];
+                if (corr) {
+                    const double dr = ct.z[j].x - h_lam[c].x, di = ct.z[j].y - h_lam[c].y;
+                    const double den = dr * dr + di * di;
+                    w = make_double2((w.x * dr + w.y * di) / den, (w.y * dr - w.x * di) / den);
+                    rc.x += w.x;
+                    rc.y += w.y;
+                }
+                h_coef[(size_t)j * m0 + c] = w;
+            }
+            h_rho[c] = rc;
+        }
+        FX_CHECK(hipMemcpyAsync(dcoef, h_coef, sizeof(double2) * ne * m0, hipMemcpyHostToDevice, s));
+        if (corr) FX_CHECK(hipMemcpyAsync(drho, h_rho, sizeof(double2) * m0, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL((accumulate_general_kernel<T>), grid1(nm), dim3(256), 0, s, n, m0, ne, Y, Yh2, (long)n,
+                           (long)nm, dcoef, corr ? drho : nullptr, X, Xh, (long)n, Q, Qh, (long)n);
         FX_LAUNCH_CHECK();
         tm.mark(&st.t_accum);
 
@@ -1357,11 +1394,11 @@ static int validate_general(int n, int m0, double2 emid, double r, const feast_o
     if (o.x0 != 0 && o.x0 != 1) return 105;
     if (o.conv != 0 && o.conv != 1) return 106;
     if (o.mode != 0) return 114;
-    if (o.precision != 0) return 140;
+    if (o.precision != 0 && o.precision != 1) return 140;
     if (o.integration_full != 0 && o.integration_full != 1) return 117;
     if (o.ellipse < 1) return 118;
     if (o.angle < -180 || o.angle > 180) return 119;
-    if (n > lu_max_n<double>()) return 202;
+    if (n > (o.precision == 1 ? lu_max_n<float>() : lu_max_n<double>())) return 202;
     return 0;
 }
 
@@ -1949,7 +1986,8 @@ static int gsolve(bool real_in, int N, const void *A, int lda, const void *B, in
             fx::GProblem pb{N, reinterpret_cast<const double2 *>(A), lda, reinterpret_cast<const double2 *>(B), ldb,
                             emid, r, m0, reinterpret_cast<double2 *>(X), ldx};
             try {
-                info = fx::run_general(pb, o, s, ws, out, st);
+                info = o.precision == 1 ? fx::run_general<float>(pb, o, s, ws, out, st)
+                                    : fx::run_general<double>(pb, o, s, ws, out, st);
             } catch (const fx::solver_error &e) {
                 (void)hipStreamSynchronize(s);
                 info = e.info;
@@ -1981,7 +2019,8 @@ static int gsolve(bool real_in, int N, const void *A, int lda, const void *B, in
         if (o.x0) FX_CHECK(hipMemcpy2D(dX, es * N, X, es * ldx, es * N, 2 * m0, hipMemcpyHostToDevice));
         fx::GProblem pb{N, dA, N, dB, N, emid, r, m0, dX, N};
         try {
-            info = fx::run_general(pb, o, s, ws, out, st);
+            info = o.precision == 1 ? fx::run_general<float>(pb, o, s, ws, out, st)
+                                    : fx::run_general<double>(pb, o, s, ws, out, st);
         } catch (const fx::solver_error &e) {
             (void)hipStreamSynchronize(s);
             info = e.info;

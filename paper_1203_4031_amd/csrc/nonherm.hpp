@@ -46,26 +46,55 @@ __device__ inline double2 zsqrt(double2 a)
     return make_double2(re, im);
 }
 
-// Q = sum_j w_j Y_j and Qh = sum_j conj(w_j) Yh_j over the nodes of the full
-// contour, in node order (Y_j = (z_j B - A)^{-1} B X, Yh_j = (z_j B -
-// A)^{-H} B^H Xh, both n x ncols with leading dimension ldy, stride sY).
-__global__ __launch_bounds__(256) void accumulate_general_kernel(int n, int ncols, int ne,
-                                                                 const double2 *__restrict__ Y,
-                                                                 const double2 *__restrict__ Yh, long ldy, long sY,
-                                                                 const double2 *__restrict__ w, double2 *__restrict__ Q,
-                                                                 double2 *__restrict__ Qh, long ldq)
+// Quadrature of the full contour, right and left subspaces, in node order:
+//   Q[:, c]  = rho_c X[:, c]        + sum_j coef[j][c]       Y_j[:, c]
+//   Qh[:, c] = conj(rho_c) Xh[:, c] + sum_j conj(coef[j][c]) Yh_j[:, c]
+// Plain form: coef[j][c] = w_j and no X term (rho = NULL); Y_j = (z_j B -
+// A)^{-1} B X, Yh_j = (z_j B - A)^{-H} B^H Xh.  Correction form (mixed
+// precision): Y_j, Yh_j solve against the Ritz residuals, coef[j][c] =
+// w_j / (z_j - lambda_c) and rho_c = sum_j coef[j][c].  Y, Yh in the solve
+// precision T (n x ncols, leading dimension ldy, stride sY); sums in FP64.
+template <typename T>
+__global__ __launch_bounds__(256) void accumulate_general_kernel(int n, int ncols, int ne, const cplx<T> *__restrict__ Y,
+                                                                 const cplx<T> *__restrict__ Yh, long ldy, long sY,
+                                                                 const double2 *__restrict__ coef,
+                                                                 const double2 *__restrict__ rho,
+                                                                 const double2 *__restrict__ X,
+                                                                 const double2 *__restrict__ Xh, long ldx,
+                                                                 double2 *__restrict__ Q, double2 *__restrict__ Qh,
+                                                                 long ldq)
 {
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long)n * ncols) return;
     const int i = (int)(idx % n), c = (int)(idx / n);
     double2 q = make_double2(0.0, 0.0), qh = make_double2(0.0, 0.0);
     for (int j = 0; j < ne; ++j) {
-        const double2 wj = w[j];
-        q = zadd(q, zmul(wj, Y[j * sY + i + (long)c * ldy]));
-        qh = zadd(qh, zmul(zconj(wj), Yh[j * sY + i + (long)c * ldy]));
+        const double2 w = coef[(long)j * ncols + c];
+        const cplx<T> y = Y[j * sY + i + (long)c * ldy], yh = Yh[j * sY + i + (long)c * ldy];
+        q = zadd(q, zmul(w, make_double2(y.x, y.y)));
+        qh = zadd(qh, zmul(zconj(w), make_double2(yh.x, yh.y)));
+    }
+    if (rho) {
+        const double2 r = rho[c];
+        q = zadd(q, zmul(r, X[i + (long)c * ldx]));
+        qh = zadd(qh, zmul(zconj(r), Xh[i + (long)c * ldx]));
     }
     Q[i + (long)c * ldq] = q;
     Qh[i + (long)c * ldq] = qh;
+}
+
+// R[:, c] = AX[:, c] - mu_c BX[:, c], mu_c = lam[c] or conj(lam[c]) (the
+// right or left Ritz residual block of the correction form), FP64.
+__global__ __launch_bounds__(256) void ritz_residual_general_kernel(int n, int ncols, const double2 *__restrict__ AX,
+                                                                   const double2 *__restrict__ BX, long ld,
+                                                                   const double2 *__restrict__ lam, int conj_lam,
+                                                                   double2 *__restrict__ R)
+{
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)n * ncols) return;
+    const int i = (int)(idx % n), c = (int)(idx / n);
+    const double2 l = conj_lam ? zconj(lam[c]) : lam[c];
+    R[i + (long)c * ld] = zsub(AX[i + (long)c * ld], zmul(l, BX[i + (long)c * ld]));
 }
 
 constexpr int NH_NT = 256;   // threads of the single-workgroup dense kernels

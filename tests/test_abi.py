@@ -118,7 +118,7 @@ def test_slice_argument_errors_need_no_gpu(kw, code):
 @pytest.mark.parametrize("kw,code", [
     (dict(n=0), 202), (dict(m0=0), 201), (dict(m0=5), 201), (dict(r=0.0), 200), (dict(r=float("nan")), 200),
     (dict(ne_full=0), 108), (dict(ne_full=257), 108), (dict(tol=0.0), 103), (dict(mode=1), 114),
-    (dict(precision=1), 140), (dict(integration_full=2), 117), (dict(ellipse=0), 118), (dict(angle=181), 119),
+    (dict(precision=2), 140), (dict(integration_full=2), 117), (dict(ellipse=0), 118), (dict(angle=181), 119),
     (dict(lda=2), -103),
 ])
 def test_gsolve_argument_errors_need_no_gpu(kw, code):

@@ -51,12 +51,16 @@ def _check(p, r, ref, ellipse=100, angle=0):
     assert np.allclose(r.res[:M], _resid(p.A, B, X, got, alpha), rtol=1e-6, atol=1e-13)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("real,generalized", [(False, True), (True, False), (True, True), (False, False)])
-def test_gsolve_matches_oracle(real, generalized):
+def test_gsolve_matches_oracle(real, generalized, precision):
+    """Both precisions reach the FP64 oracle's eigenpairs: in mixed
+    precision the complex64 solves act on the FP64 Ritz residuals after the
+    first loop."""
     p = W.dense_general(200, count=12, seed=6101 + 2 * real + generalized, real=real, generalized=generalized)
-    print(f"gsolve real {real} generalized {generalized} n {p.n} m0 {p.m0}", flush=True)
+    print(f"gsolve real {real} generalized {generalized} {precision} n {p.n} m0 {p.m0}", flush=True)
     ref = NH.feast(p.A, p.B, p.emin, p.emax, p.m0, p.ne, p.tol, p.X0)
-    r = feastx.gsolve(p.A, p.B, p.emin, p.emax, p.m0, X0=p.X0, tol=p.tol, ne_full=p.ne)
+    r = feastx.gsolve(p.A, p.B, p.emin, p.emax, p.m0, X0=p.X0, tol=p.tol, ne_full=p.ne, precision=precision)
     _check(p, r, ref)
 
 
@@ -84,13 +88,14 @@ def test_gsolve_library_start_finds_the_spectrum():
         assert np.abs(r.E[:r.M] - l).min() <= 1e-10 * max(abs(l), alpha)
 
 
-def test_gsolve_matches_oracle_beyond_lds_size():
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_gsolve_matches_oracle_beyond_lds_size(precision):
     """M0 = 76 > 64: the reduced eigensolver and inverses work in memory
     instead of LDS."""
     p = W.dense_general(300, count=48, seed=6131)
     assert p.m0 > 64
     ref = NH.feast(p.A, p.B, p.emin, p.emax, p.m0, p.ne, p.tol, p.X0)
-    r = feastx.gsolve(p.A, p.B, p.emin, p.emax, p.m0, X0=p.X0, tol=p.tol, ne_full=p.ne)
+    r = feastx.gsolve(p.A, p.B, p.emin, p.emax, p.m0, X0=p.X0, tol=p.tol, ne_full=p.ne, precision=precision)
     _check(p, r, ref)
 
 
