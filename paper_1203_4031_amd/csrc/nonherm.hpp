@@ -312,11 +312,24 @@ __global__ __launch_bounds__(NT) void eig_general_kernel(int m, double2 *__restr
     //      the full Schur form and Z accumulates them
     int hi = m - 1, its = 0, total = 0, fail = 0;
     while (hi >= 1) {
+        // l: the last negligible subdiagonal entry at or below hi (0: none)
         int l = hi;
-        for (; l >= 1; --l) {
-            double tst = zabs1(at(l - 1, l - 1)) + zabs1(at(l, l));
-            if (tst == 0.0) tst = hnorm;
-            if (zabs1(at(l, l - 1)) <= fmax(ulp * tst, smlnum)) break;
+        if constexpr (NT == 64 && LDSM > 0 && LDSM <= 64) {
+            // one wave: lane t tests position t, a ballot picks the largest
+            bool small = false;
+            if (tid >= 1 && tid <= hi) {
+                double tst = zabs1(at(tid - 1, tid - 1)) + zabs1(at(tid, tid));
+                if (tst == 0.0) tst = hnorm;
+                small = zabs1(at(tid, tid - 1)) <= fmax(ulp * tst, smlnum);
+            }
+            const unsigned long long bal = __ballot(small);
+            l = bal ? 63 - __clzll(bal) : 0;
+        } else {
+            for (; l >= 1; --l) {
+                double tst = zabs1(at(l - 1, l - 1)) + zabs1(at(l, l));
+                if (tst == 0.0) tst = hnorm;
+                if (zabs1(at(l, l - 1)) <= fmax(ulp * tst, smlnum)) break;
+            }
         }
         __syncthreads();
         if (l >= 1 && tid == 0) at(l, l - 1) = make_double2(0.0, 0.0);
@@ -356,17 +369,19 @@ __global__ __launch_bounds__(NT) void eig_general_kernel(int m, double2 *__restr
             // rotation G = [[c, s], [-conj(s), c]] with G [x; y] = [r; 0]
             double c;
             double2 sg;
-            const double ax = zabs(x), ay = zabs(y);
-            if (ay == 0.0) {
+            // moduli by plain square roots: the entries are of the order of
+            // the matrix norm, far from overflow
+            const double ax2 = x.x * x.x + x.y * x.y, ay2 = y.x * y.x + y.y * y.y;
+            if (ay2 == 0.0) {
                 c = 1.0;
                 sg = make_double2(0.0, 0.0);
-            } else if (ax == 0.0) {
+            } else if (ax2 == 0.0) {
                 c = 0.0;
-                sg = zscale(1.0 / ay, zconj(y));
+                sg = zscale(1.0 / sqrt(ay2), zconj(y));
             } else {
-                const double nr = hypot(ax, ay);
-                c = ax / nr;
-                sg = zscale(1.0 / (ax * nr), zmul(x, zconj(y)));
+                const double ax = sqrt(ax2), inv = 1.0 / (ax * sqrt(ax2 + ay2));
+                c = ax2 * inv;
+                sg = zscale(inv, zmul(x, zconj(y)));
             }
             __syncthreads();   // every thread has read x and y
             const int j0 = k == l ? l : k - 1;
