@@ -34,7 +34,7 @@ N, COUNT, M0, NE, TOL, SEED = 4096, 200, 300, 8, 1e-10, 2001
 # launches it (the FP64 reduced-problem kernels in jacobi.hpp and
 # bortho.hpp do not): `traffic` is null when they differ.
 TRAFFIC_BYTES_PER_LAUNCH = 1.196e+08
-TRAFFIC_SOURCES_SHA256 = "26ee7290182167aba1817e6719cd04652bc310c75b07d31844f6b6809b7fd7d5"
+TRAFFIC_SOURCES_SHA256 = "ba63631afd37f8bc40d54c07744d3e0306fd1ad9a1bf62cc5284ea6550d0421c"
 
 
 def kernel_sources_sha256():
