@@ -409,38 +409,80 @@ __global__ __launch_bounds__(BJ_NT) void bjacobi_kernel(int n, typename jelem<CP
                     L1[a][b] = RQ[a + b * BJ_W];
                 }
                 __syncthreads();
-                // T = X R_Q, 4 entries per thread
-                E tv[BJ_W * BJ_W / BJ_NT];
+                // T = X R_Q.  Real matrices: each of the 4 waves forms one
+                // 16 x 16 block of T with FP64 matrix-core steps (lane l holds
+                // rows acc_row(l, r) and column l % 16 of its block); complex
+                // matrices: 4 entries per thread.  (ta, tb) = tile position of tv.
+                constexpr int NV = BJ_W * BJ_W / BJ_NT;
+                static_assert(CPLX || (NV == 4 && BJ_W == 32 && BJ_NT == 256), "one 16 x 16 block per wave");
+                E tv[NV];
+                int ta[NV], tb[NV];
+                const int wv = tid >> 6, bi16 = (wv & 1) * 16, bj16 = (wv >> 1) * 16, l16 = lane & 15, l4 = lane >> 4;
+                if constexpr (!CPLX) {
+                    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int u = 0; u < BJ_W * BJ_W / BJ_NT; ++u) {
-                    const int e = tid + u * BJ_NT;
-                    const int a = e % BJ_W, b = e / BJ_W;
-                    E sum = jzero<E>();
+                    for (int kk = 0; kk < BJ_W / 4; ++kk)
+                        acc = mfma16<double>::step(L0[bi16 + l16][kk * 4 + l4], L1[kk * 4 + l4][bj16 + l16], acc);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        tv[r] = acc[r];
+                        ta[r] = bi16 + mfma16<double>::acc_row(lane, r);
+                        tb[r] = bj16 + l16;
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < NV; ++u) {
+                        const int e = tid + u * BJ_NT;
+                        const int a = e % BJ_W, b = e / BJ_W;
+                        E sum = jzero<E>();
 #pragma unroll 8
-                    for (int k = 0; k < BJ_W; ++k) sum = jadd(sum, jmul(L0[a][k], L1[k][b]));
-                    tv[u] = sum;
+                        for (int k = 0; k < BJ_W; ++k) sum = jadd(sum, jmul(L0[a][k], L1[k][b]));
+                        tv[u] = sum;
+                        ta[u] = a;
+                        tb[u] = b;
+                    }
                 }
                 __syncthreads();
                 if (is_c) {
                     const E *RP = Rprev + (long)P * BJ_W * BJ_W;
 #pragma unroll
-                    for (int u = 0; u < BJ_W * BJ_W / BJ_NT; ++u) {
-                        const int e = tid + u * BJ_NT;
-                        L0[e % BJ_W][e / BJ_W] = tv[u];
-                    }
+                    for (int u = 0; u < NV; ++u) L0[ta[u]][tb[u]] = tv[u];
                     for (int e = tid; e < BJ_W * BJ_W; e += BJ_NT) {
                         const int a = e % BJ_W, b = e / BJ_W;
                         L1[a][b] = RP[a + b * BJ_W];
                     }
                     __syncthreads();
+                    // C tile = R_P^H T
+                    E ov[NV];
+                    int oa[NV], ob[NV];
+                    if constexpr (!CPLX) {
+                        f64x4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                    for (int u = 0; u < BJ_W * BJ_W / BJ_NT; ++u) {
-                        const int e = tid + u * BJ_NT;
-                        const int a = e % BJ_W, b = e / BJ_W;
-                        E sum = jzero<E>();
+                        for (int kk = 0; kk < BJ_W / 4; ++kk)
+                            acc = mfma16<double>::step(L1[kk * 4 + l4][bi16 + l16], L0[kk * 4 + l4][bj16 + l16], acc);
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            ov[r] = acc[r];
+                            oa[r] = bi16 + mfma16<double>::acc_row(lane, r);
+                            ob[r] = bj16 + l16;
+                        }
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < NV; ++u) {
+                            const int e = tid + u * BJ_NT;
+                            const int a = e % BJ_W, b = e / BJ_W;
+                            E sum = jzero<E>();
 #pragma unroll 8
-                        for (int k = 0; k < BJ_W; ++k) sum = jadd(sum, jmul(jconj(L1[k][a]), L0[k][b]));
-                        const int ia = s_iP[a], ib = s_iQ[b];
+                            for (int k = 0; k < BJ_W; ++k) sum = jadd(sum, jmul(jconj(L1[k][a]), L0[k][b]));
+                            ov[u] = sum;
+                            oa[u] = a;
+                            ob[u] = b;
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < NV; ++u) {
+                        E sum = ov[u];
+                        const int ia = s_iP[oa[u]], ib = s_iQ[ob[u]];
                         if (ia >= 0 && ib >= 0) {
                             if (ia == ib) sum = jreal<E>(jre(sum));
                             Cnext[ia + (long)ib * ldc] = sum;
@@ -450,10 +492,8 @@ __global__ __launch_bounds__(BJ_NT) void bjacobi_kernel(int n, typename jelem<CP
                     }
                 } else {
 #pragma unroll
-                    for (int u = 0; u < BJ_W * BJ_W / BJ_NT; ++u) {
-                        const int e = tid + u * BJ_NT;
-                        const int a = e % BJ_W, b = e / BJ_W;
-                        const int ia = s_iP[a], ib = s_iQ[b];
+                    for (int u = 0; u < NV; ++u) {
+                        const int ia = s_iP[ta[u]], ib = s_iQ[tb[u]];
                         if (ia >= 0 && ib >= 0) V[ia + (long)ib * ldv] = tv[u];
                     }
                 }
