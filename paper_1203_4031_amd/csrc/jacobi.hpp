@@ -409,38 +409,48 @@ __global__ __launch_bounds__(BJ_NT) void bjacobi_kernel(int n, typename jelem<CP
                     L1[a][b] = RQ[a + b * BJ_W];
                 }
                 __syncthreads();
-                // T = X R_Q.  Real matrices: each of the 4 waves forms one
-                // 16 x 16 block of T with FP64 matrix-core steps (lane l holds
-                // rows acc_row(l, r) and column l % 16 of its block); complex
-                // matrices: 4 entries per thread.  (ta, tb) = tile position of tv.
+                // T = X R_Q: each of the 4 waves forms one 16 x 16 block of T
+                // with FP64 matrix-core steps (lane l holds rows acc_row(l, r)
+                // and column l % 16 of its block; a complex product takes four
+                // real ones).  (ta, tb) = tile position of tv.
                 constexpr int NV = BJ_W * BJ_W / BJ_NT;
-                static_assert(CPLX || (NV == 4 && BJ_W == 32 && BJ_NT == 256), "one 16 x 16 block per wave");
+                static_assert(NV == 4 && BJ_W == 32 && BJ_NT == 256, "one 16 x 16 block per wave");
                 E tv[NV];
                 int ta[NV], tb[NV];
                 const int wv = tid >> 6, bi16 = (wv & 1) * 16, bj16 = (wv >> 1) * 16, l16 = lane & 15, l4 = lane >> 4;
-                if constexpr (!CPLX) {
-                    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+                // 16 x 16 block (bi16, bj16) of op(Lx) Ly over the 32-deep tile:
+                // op = identity, Lx[row][k]; or op = ^H, conj(Lx[k][row])
+                auto block_product = [&](E (*Lx)[BJ_W + 1], E (*Ly)[BJ_W + 1], bool adj, E *outv) {
+                    if constexpr (!CPLX) {
+                        f64x4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                    for (int kk = 0; kk < BJ_W / 4; ++kk)
-                        acc = mfma16<double>::step(L0[bi16 + l16][kk * 4 + l4], L1[kk * 4 + l4][bj16 + l16], acc);
+                        for (int kk = 0; kk < BJ_W / 4; ++kk) {
+                            const double xa = adj ? Lx[kk * 4 + l4][bi16 + l16] : Lx[bi16 + l16][kk * 4 + l4];
+                            acc = mfma16<double>::step(xa, Ly[kk * 4 + l4][bj16 + l16], acc);
+                        }
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        tv[r] = acc[r];
-                        ta[r] = bi16 + mfma16<double>::acc_row(lane, r);
-                        tb[r] = bj16 + l16;
+                        for (int r = 0; r < 4; ++r) outv[r] = acc[r];
+                    } else {
+                        f64x4 re = {0.0, 0.0, 0.0, 0.0}, im = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                        for (int kk = 0; kk < BJ_W / 4; ++kk) {
+                            double2 xa = adj ? Lx[kk * 4 + l4][bi16 + l16] : Lx[bi16 + l16][kk * 4 + l4];
+                            if (adj) xa.y = -xa.y;
+                            const double2 yb = Ly[kk * 4 + l4][bj16 + l16];
+                            re = mfma16<double>::step(xa.x, yb.x, re);
+                            re = mfma16<double>::step(-xa.y, yb.y, re);
+                            im = mfma16<double>::step(xa.x, yb.y, im);
+                            im = mfma16<double>::step(xa.y, yb.x, im);
+                        }
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) outv[r] = make_double2(re[r], im[r]);
                     }
-                } else {
+                };
+                block_product(L0, L1, false, tv);
 #pragma unroll
-                    for (int u = 0; u < NV; ++u) {
-                        const int e = tid + u * BJ_NT;
-                        const int a = e % BJ_W, b = e / BJ_W;
-                        E sum = jzero<E>();
-#pragma unroll 8
-                        for (int k = 0; k < BJ_W; ++k) sum = jadd(sum, jmul(L0[a][k], L1[k][b]));
-                        tv[u] = sum;
-                        ta[u] = a;
-                        tb[u] = b;
-                    }
+                for (int r = 0; r < 4; ++r) {
+                    ta[r] = bi16 + mfma16<double>::acc_row(lane, r);
+                    tb[r] = bj16 + l16;
                 }
                 __syncthreads();
                 if (is_c) {
@@ -455,29 +465,11 @@ __global__ __launch_bounds__(BJ_NT) void bjacobi_kernel(int n, typename jelem<CP
                     // C tile = R_P^H T
                     E ov[NV];
                     int oa[NV], ob[NV];
-                    if constexpr (!CPLX) {
-                        f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+                    block_product(L1, L0, true, ov);
 #pragma unroll
-                        for (int kk = 0; kk < BJ_W / 4; ++kk)
-                            acc = mfma16<double>::step(L1[kk * 4 + l4][bi16 + l16], L0[kk * 4 + l4][bj16 + l16], acc);
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            ov[r] = acc[r];
-                            oa[r] = bi16 + mfma16<double>::acc_row(lane, r);
-                            ob[r] = bj16 + l16;
-                        }
-                    } else {
-#pragma unroll
-                        for (int u = 0; u < NV; ++u) {
-                            const int e = tid + u * BJ_NT;
-                            const int a = e % BJ_W, b = e / BJ_W;
-                            E sum = jzero<E>();
-#pragma unroll 8
-                            for (int k = 0; k < BJ_W; ++k) sum = jadd(sum, jmul(jconj(L1[k][a]), L0[k][b]));
-                            ov[u] = sum;
-                            oa[u] = a;
-                            ob[u] = b;
-                        }
+                    for (int r = 0; r < 4; ++r) {
+                        oa[r] = bi16 + mfma16<double>::acc_row(lane, r);
+                        ob[r] = bj16 + l16;
                     }
 #pragma unroll
                     for (int u = 0; u < NV; ++u) {
