@@ -142,3 +142,26 @@ def test_other_contours_match_oracle(orc, precision, integration, ellipse, custo
                      integration=0 if custom else integration, ellipse=100 if custom else ellipse,
                      zne=zne, wne=wne)
     _check_pairs(p, r, ref)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_spurious_pairs_in_a_spectral_gap(orc, precision):
+    """An interval inside a spectral gap: Ritz values that land in it are
+    counted at the first loop and flagged spurious (res = -1, last, not in
+    M) from the second loop on, as the oracle does (its pin derives the flag
+    from the residual bound of the gap)."""
+    from test_oracle_pins import _gap_problem
+
+    A, X0, m0 = _gap_problem()
+    for maxloop in (0, 1):
+        ref = orc.feast(A, None, -0.2, 0.2, m0, 8, 1e-10, X0, maxloop=maxloop)
+        r = feastx.solve(A, None, -0.2, 0.2, m0, X0=X0, ne=8, tol=1e-10, precision=precision, maxloop=maxloop)
+        assert r.info == ref.info == 2
+        assert r.M == ref.M
+        ins = (r.E >= -0.2) & (r.E <= 0.2)
+        ins_ref = (ref.E >= -0.2) & (ref.E <= 0.2)
+        assert ins.sum() == ins_ref.sum()
+        if maxloop == 1:
+            assert r.M == 0 and (r.res[ins] == -1.0).all()
+        else:
+            assert (r.res[ins] > 0.1).all()

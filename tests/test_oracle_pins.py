@@ -592,6 +592,48 @@ def test_output_order(orc):
     assert ((outside < p.emin) | (outside > p.emax)).all()
 
 
+def _gap_problem():
+    """Real symmetric A (B = I) whose spectrum avoids [-0.5, 0.5]: the
+    search interval [-0.2, 0.2] holds no eigenvalue and every point of it is
+    at least 0.3 from the spectrum."""
+    rng = np.random.default_rng(21)
+    n, m0 = 40, 12
+    lam = np.concatenate([rng.uniform(-1, -0.5, n // 2), rng.uniform(0.5, 1, n - n // 2)])
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A = (Q * lam) @ Q.T
+    return 0.5 * (A + A.T), rng.uniform(-1, 1, (n, m0)), m0
+
+
+def test_spurious_pairs_in_a_spectral_gap(orc):
+    """The spurious flag (section "The FEAST Algorithm" reading R11) pinned
+    by a bound: for a Ritz pair (theta, x) with theta in the interval,
+    ||A x - theta x||_2 >= 0.3 ||x||_2 (the distance to the spectrum), so
+    its residual ||A x - theta x||_1 / (alpha ||x||_1) >= 0.3 / (alpha sqrt(n))
+    = 0.24 > 0.1: every such pair is spurious from the second loop on, and
+    none counts towards M.  At the first loop nothing is flagged."""
+    A, X0, m0 = _gap_problem()
+    n = A.shape[0]
+    emin, emax = -0.2, 0.2
+    alpha = max(abs(emin), abs(emax))
+    assert 0.3 / (alpha * math.sqrt(n)) > 0.1
+    out0 = orc.feast(A, None, emin, emax, m0, 8, 1e-10, X0, maxloop=0)
+    in0 = (out0.E >= emin) & (out0.E <= emax)
+    assert in0.any(), "the random start should leave Ritz values in the gap at the first loop"
+    assert out0.M == in0.sum() and (out0.res[in0] > 0.1).all()   # counted, not flagged
+    out1 = orc.feast(A, None, emin, emax, m0, 8, 1e-10, X0, maxloop=1)
+    in1 = (out1.E >= emin) & (out1.E <= emax)
+    assert out1.M == 0 and out1.info == 2
+    assert (out1.res[in1] == -1.0).all()
+    # spurious pairs come last
+    k = int(in1.sum())
+    if k:
+        assert in1[m0 - k:].all()
+        X = out1.X[:, m0 - k:]
+        th = out1.E[m0 - k:]
+        r = np.abs(A @ X - X * th).sum(0) / (alpha * np.abs(X).sum(0))
+        assert (r > 0.1).all()
+
+
 def test_oracle_is_not_used_by_the_product():
     """The oracle is test infrastructure: the package and headers never name it."""
     root = os.path.dirname(HERE)
