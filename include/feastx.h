@@ -58,8 +58,8 @@ typedef struct {
     int precision;    /* 0: FP64 (complex128 factors and solves, default);
                          1: mixed (complex64 factors and solves on FP32 matrix cores,
                             FP64 residual correction; everything else FP64) */
-    int refine;       /* mixed only. 0: residual-correction form from the second loop on
-                         (default); s > 0: s steps of per-solve FP64 iterative refinement */
+    int refine;       /* must be 0 (the mixed path uses the FP64 residual-correction form from
+                         the second loop on); any other value returns info 141 */
     int mode;         /* [fpm(14)] 0: normal; 1: return Q after one contour in X (info 4);
                          2: stochastic estimate of the number of eigenvalues in the interval
                          (section "Stochastic estimate", info 5): one contour pass over the M0

@@ -216,17 +216,49 @@ def fortran_tensor(arr, device="cuda"):
     return t.t()
 
 
+def _check_device_operands(A, B, X, xcols, dtypes):
+    """Validate torch operands before their raw pointers reach a *_dev entry
+    point, which cannot check them: A square, B (or None) the same shape, X
+    with N rows and at least `xcols` columns, one dtype from `dtypes` shared
+    by all, column-major with leading dimension >= N, all on one CUDA device.
+    Raises ValueError; the shape and dtype checks come first, so they fire on
+    CPU tensors as well."""
+    if A.dim() != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError(f"A must be square (N, N), got {tuple(A.shape)}")
+    n = A.shape[0]
+    if A.dtype not in dtypes:
+        raise ValueError(f"A has dtype {A.dtype}; expected one of {sorted(str(d) for d in dtypes)}")
+    if B is not None:
+        if tuple(B.shape) != (n, n):
+            raise ValueError(f"B must be ({n}, {n}) like A, got {tuple(B.shape)}")
+        if B.dtype != A.dtype:
+            raise ValueError(f"B has dtype {B.dtype}, A has {A.dtype}")
+    if X is not None:
+        if X.dim() != 2 or X.shape[0] != n or X.shape[1] < xcols:
+            raise ValueError(f"X must be ({n}, >= {xcols}), got {tuple(X.shape)}")
+        if X.dtype != A.dtype:
+            raise ValueError(f"X has dtype {X.dtype}, A has {A.dtype}")
+    for name, t in (("A", A), ("B", B), ("X", X)):
+        if t is None:
+            continue
+        if t.stride(0) != 1 or t.stride(1) < n:
+            raise ValueError(f"{name} must be column-major with leading dimension >= {n} "
+                             f"(strides {tuple(t.stride())})")
+        if not t.is_cuda:
+            raise ValueError(f"{name} must be a CUDA tensor")
+        if t.device != A.device:
+            raise ValueError(f"{name} is on {t.device}, A on {A.device}")
+
+
 def solve_device(A, B, emin, emax, m0, X, stream=None, **kw) -> Result:
     """Device solve: A, B, X are column-major torch CUDA tensors (see
     fortran_tensor); X holds the start subspace if x0=True and receives the
     eigenvectors.  Runs on `stream` (default: torch's current stream)."""
     import torch
 
+    _check_device_operands(A, B, X, m0, (torch.float64, torch.complex128))
     cplx = A.is_complex()
     n = A.shape[0]
-    for t in (A, B, X):
-        if t is not None and (t.stride(0) != 1 or not t.is_cuda):
-            raise ValueError("device arrays must be column-major CUDA tensors")
     if stream is None:
         stream = torch.cuda.current_stream()
     o = make_opts(**kw)
@@ -370,10 +402,8 @@ def gsolve_device(A, B, emid, r, m0, X, stream=None, **kw) -> Result:
     ne_full = kw.pop("ne_full", 16)
     integration_full = kw.pop("integration_full", 1)
     angle = kw.pop("angle", 0)
+    _check_device_operands(A, B, X, 2 * m0, (torch.complex128,))
     n = A.shape[0]
-    for t in (A, B, X):
-        if t is not None and (t.stride(0) != 1 or not t.is_cuda or t.dtype != torch.complex128):
-            raise ValueError("device arrays must be column-major complex128 CUDA tensors")
     if stream is None:
         stream = torch.cuda.current_stream()
     o = make_opts(**kw)
@@ -400,11 +430,9 @@ def solve_slices(A, B, bounds, m0, X0=None, concurrency=4, auto_m0=False, **kw) 
     if device:
         import torch
 
+        _check_device_operands(A, B, None, 0, (torch.float64, torch.complex128))
         cplx = A.is_complex()
         n = A.shape[0]
-        for t in (A, B):
-            if t is not None and (t.stride(0) != 1 or not t.is_cuda):
-                raise ValueError("device arrays must be column-major CUDA tensors")
         pa = A.data_ptr()
         pb = None if B is None else B.data_ptr()
         lda, ldb = A.stride(1), (n if B is None else B.stride(1))
@@ -421,6 +449,12 @@ def solve_slices(A, B, bounds, m0, X0=None, concurrency=4, auto_m0=False, **kw) 
     m0s = [int(m0)] * ns if np.isscalar(m0) else [int(x) for x in m0]
     if len(m0s) != ns:
         raise ValueError("one m0 per slice")
+    if X0 is not None:
+        if len(X0) != ns:
+            raise ValueError("one start subspace per slice")
+        for s_, (x, mm) in enumerate(zip(X0, m0s)):
+            if tuple(x.shape) != (n, mm):
+                raise ValueError(f"X0[{s_}] has shape {tuple(x.shape)}, expected ({n}, {mm})")
     o = make_opts(x0=X0 is not None and not auto_m0, **kw)
     keep, jobs = [], (feast_job * ns)()
     for s_, mm in enumerate(m0s):

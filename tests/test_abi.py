@@ -138,3 +138,62 @@ def test_gsolve_argument_errors_need_no_gpu(kw, code):
                                        args["r"], C.byref(m0), C.byref(o), E.ctypes.data, X.ctypes.data, n,
                                        C.byref(M), res.ctypes.data_as(C.POINTER(C.c_double)), None, None)
     assert info == code
+
+
+def _t(shape, dtype, col_major=True):
+    import torch
+
+    t = torch.zeros(shape[::-1], dtype=dtype)
+    return t.t() if col_major else t.t().contiguous()
+
+
+@pytest.mark.parametrize("case,msg", [
+    ("a_not_square", "square"), ("a_dtype", "dtype"), ("b_shape", "B must be"), ("b_dtype", "B has dtype"),
+    ("x_rows", "X must be"), ("x_cols", "X must be"), ("x_dtype", "X has dtype"), ("row_major", "column-major"),
+    ("cpu", "CUDA tensor"),
+])
+def test_device_solve_checks_operands_before_any_call(case, msg):
+    """The *_dev entry points take raw device pointers and cannot check them,
+    so the binding rejects wrong shapes, dtypes, layouts and devices first
+    (these fire on CPU tensors, before the library is called)."""
+    import torch
+
+    n, m0 = 8, 3
+    A, B, X = _t((n, n), torch.float64), _t((n, n), torch.float64), _t((n, m0), torch.float64)
+    if case == "a_not_square":
+        A = _t((n, n + 1), torch.float64)
+    elif case == "a_dtype":
+        A, B, X = _t((n, n), torch.float32), _t((n, n), torch.float32), _t((n, m0), torch.float32)
+    elif case == "b_shape":
+        B = _t((n - 1, n - 1), torch.float64)
+    elif case == "b_dtype":
+        B = _t((n, n), torch.complex128)
+    elif case == "x_rows":
+        X = _t((n - 1, m0), torch.float64)
+    elif case == "x_cols":
+        X = _t((n, m0 - 1), torch.float64)
+    elif case == "x_dtype":
+        X = _t((n, m0), torch.complex128)
+    elif case == "row_major":
+        A = _t((n, n), torch.float64, col_major=False)
+    with pytest.raises(ValueError, match=msg):
+        feastx.solve_device(A, B, -1.0, 1.0, m0, X)
+
+
+def test_device_gsolve_and_slices_check_operands():
+    import torch
+
+    n, m0 = 8, 3
+    A = _t((n, n), torch.complex128)
+    with pytest.raises(ValueError, match="X must be"):
+        feastx.gsolve_device(A, None, 0.0, 1.0, m0, _t((n, 2 * m0 - 1), torch.complex128))
+    with pytest.raises(ValueError, match="dtype"):
+        feastx.gsolve_device(_t((n, n), torch.float64), None, 0.0, 1.0, m0, _t((n, 2 * m0), torch.float64))
+    with pytest.raises(ValueError, match="CUDA tensor"):
+        feastx.gsolve_device(A, None, 0.0, 1.0, m0, _t((n, 2 * m0), torch.complex128))
+    with pytest.raises(ValueError, match="B must be"):
+        feastx.solve_slices(_t((n, n), torch.float64), _t((n, n - 1), torch.float64), [0.0, 1.0, 2.0], 3)
+    with pytest.raises(ValueError, match="start subspace per slice"):
+        feastx.solve_slices(np.eye(n), None, [0.0, 1.0, 2.0], 3, X0=[np.zeros((n, 3))])
+    with pytest.raises(ValueError, match=r"X0\[1\] has shape"):
+        feastx.solve_slices(np.eye(n), None, [0.0, 1.0, 2.0], 3, X0=[np.zeros((n, 3)), np.zeros((n, 2))])

@@ -11,12 +11,20 @@ from paper_1203_4031_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
+# The trapezoidal cases vary the one that stalled a GPU run silently
+# (test_gpu_parity.py::test_other_contours_match_oracle, trapezoidal, FP64,
+# N=300, Ne=10).  Its cause is not established, so no trapezoidal case runs
+# on the GPU until it is; the rule's nodes, weights and filter are checked
+# against the oracle on the CPU (tests/test_abi.py).
+TRAPEZOID_STALL = ("variant of the trapezoidal case that stalled a GPU run with no cause found; "
+                   "kept off the GPU until the cause is shown and fixed")
+
 CASES = [
     # (integration, ellipse, custom, precision, n, ne)
     (0, 50, False, "fp64", 256, 12),
     (0, 200, True, "mixed", 256, 12),
-    (1, 100, False, "mixed", 256, 12),
-    (1, 60, True, "fp64", 240, 9),
+    pytest.param(1, 100, False, "mixed", 256, 12, marks=pytest.mark.skip(reason=TRAPEZOID_STALL)),
+    pytest.param(1, 60, True, "fp64", 240, 9, marks=pytest.mark.skip(reason=TRAPEZOID_STALL)),
 ]
 
 
