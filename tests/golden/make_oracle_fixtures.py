@@ -1,0 +1,120 @@
+"""Write the oracle's results on the full-size workloads as text fixtures.
+
+    python tests/golden/make_oracle_fixtures.py realgen_n4096     # about 3 min on 8 cores
+    python tests/golden/make_oracle_fixtures.py hermgen_n8192     # about 1 h on 8 cores
+
+Calls only the FP64 CPU oracle (oracle/) on inputs from the seeded generators
+(paper_1203_4031_amd/workloads.py, which hold none of the method's
+arithmetic).  Nothing here comes from the GPU library.  Each fixture holds:
+
+* the SHA-256 of the inputs (A, B, X0 bytes and the interval), so a test can
+  say whether it saw the same matrices;
+* info, M, the kept subspace size, loop and epsout;
+* E and res of every returned Ritz pair (in-interval ones first, ascending);
+* a projector sketch K = S2^T X_M X_M^H B S (16 x 16), with X_M the M
+  in-interval eigenvectors and S, S2 seeded uniform(-1, 1) N x 16 blocks.
+  X_M X_M^H B is the B-orthogonal projector onto the eigenspace of the
+  interval, so K does not depend on how eigenvectors inside a cluster are
+  rotated or phased, and two subspaces that differ by an angle theta give
+  sketches that differ by about theta |K|;
+* the oracle's wall time, thread count and CPU model (the CPU baseline).
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from paper_1203_4031_amd import workloads as W  # noqa: E402
+
+SKETCH_COLS = 16
+SKETCH_SEEDS = (7001, 7002)
+
+
+def workload(name: str):
+    """The full-size workloads: the dense real symmetric generalized pencil
+    (N = 4096, 200 eigenvalues, M0 = 300, Ne = 8) and the dense complex
+    Hermitian generalized pencil (N = 8192, 400 eigenvalues, M0 = 600,
+    Ne = 16), both at tol 1e-10."""
+    if name == "realgen_n4096":
+        return W.dense_real_generalized(4096, 200, m0=300, ne=8, tol=1e-10, seed=2001)
+    if name == "hermgen_n8192":
+        return W.dense_complex_hermitian(8192, 400, m0=600, ne=16, tol=1e-10, seed=3001)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def input_sha256(p) -> str:
+    h = hashlib.sha256()
+    for a in (p.A, p.B, p.X0):
+        h.update(np.asfortranarray(a).tobytes(order="F"))
+    h.update(np.array([p.emin, p.emax]).tobytes())
+    return h.hexdigest()
+
+
+def sketch_blocks(n: int):
+    return [W.start_subspace(n, SKETCH_COLS, seed=s) for s in SKETCH_SEEDS]
+
+
+def projector_sketch(X_in, B, S, S2):
+    """S2^T X X^H B S for the in-interval eigenvectors X (N x M)."""
+    BS = S if B is None else B @ S
+    return S2.T @ (X_in @ (X_in.conj().T @ BS))
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def main():
+    name = sys.argv[1]
+    t0 = time.perf_counter()
+    p = workload(name)
+    t_gen = time.perf_counter() - t0
+    print(f"{name}: generated in {t_gen:.1f} s, interval [{p.emin!r}, {p.emax!r}]", flush=True)
+    oracle._load()
+    t0 = time.perf_counter()
+    r = oracle.feast(p.A, p.B, p.emin, p.emax, p.m0, p.ne, p.tol, p.X0, hermitian=p.hermitian)
+    wall = time.perf_counter() - t0
+    print(f"{name}: oracle info {r.info} M {r.M} loops {r.loop + 1} in {wall:.1f} s", flush=True)
+    S, S2 = sketch_blocks(p.n)
+    K = projector_sketch(r.X[:, :r.M], p.B, S, S2)
+    out = {
+        "workload": name,
+        "n": p.n, "m0": p.m0, "ne": p.ne, "tol": p.tol, "hermitian": bool(p.hermitian),
+        "emin": p.emin, "emax": p.emax, "meta": p.meta,
+        "input_sha256": input_sha256(p),
+        "info": r.info, "M": r.M, "m0_out": r.m0, "loop": r.loop, "epsout": r.epsout,
+        "E": [float(x) for x in r.E], "res": [float(x) for x in r.res],
+        "sketch_cols": SKETCH_COLS, "sketch_seeds": list(SKETCH_SEEDS),
+        "sketch_re": np.real(K).tolist(), "sketch_im": np.imag(K).tolist(),
+        "oracle_wall_s": wall, "generate_s": t_gen,
+        "threads": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+        "nproc": os.cpu_count(), "cpu": cpu_model(),
+        "written": time.strftime("%Y-%m-%d"),
+    }
+    path = os.path.join(HERE, f"oracle_{name}.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=0)
+        f.write("\n")
+    print(f"wrote {path}", flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -171,3 +171,93 @@ def test_info_empty_region_and_no_convergence():
     assert out.info == 1 and out.M == 0
     out = NH.feast(p.A, p.B, p.emin, p.emax, p.m0, 4, 1e-14, p.X0, maxloop=1)
     assert out.info == 2
+
+
+def _normal_annulus(seed, n=48):
+    """A normal complex matrix U diag(lambda) U^H (U Haar unitary) with every
+    eigenvalue in the annulus 0.8 <= |lambda| <= 1.2."""
+    rng = np.random.default_rng(seed)
+    G = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    Qm, R = np.linalg.qr(G)
+    Qm = Qm * (np.diag(R) / np.abs(np.diag(R)))
+    lam = rng.uniform(0.8, 1.2, n) * np.exp(1j * rng.uniform(0.0, 2.0 * math.pi, n))
+    return (Qm * lam) @ Qm.conj().T, lam, rng
+
+
+def test_spurious_pairs_in_a_spectral_hole():
+    """The spurious flag of the non-Hermitian oracle (reading: a pair inside
+    the region with either residual above 0.1 from the second loop on),
+    pinned by a bound.  A is normal with its spectrum in 0.8 <= |lambda| <= 1.2
+    and the region is the disk |z| <= 0.3, so any theta in the region is at
+    least 0.5 from the spectrum and ||A x - theta x||_2 >= 0.5 ||x||_2 (the
+    same for A^H and conj(theta)).  With ||v||_1 >= ||v||_2 and
+    ||x||_1 <= sqrt(n) ||x||_2 both residuals are >= 0.5 / (alpha sqrt(n)) =
+    0.24 > 0.1 (alpha = |Emid| + r = 0.3): every Ritz pair in the region is
+    spurious from the second loop on and none counts.  At the first loop
+    nothing is flagged."""
+    A, lam, rng = _normal_annulus(2)
+    n, m0, r = A.shape[0], 12, 0.3
+    alpha = r
+    assert 0.5 / (alpha * math.sqrt(n)) > 0.1
+    X0 = rng.uniform(-1, 1, (n, 2 * m0))
+    out0 = NH.feast(A, None, 0.0, r, m0, 16, 1e-10, X0, maxloop=0)
+    in0 = NH.inside(0.0, r, out0.E)
+    assert in0.any(), "the random start leaves Ritz values in the region at the first loop"
+    assert out0.info == 2 and out0.M == in0.sum()
+    assert (out0.res[:m0][in0] > 0.1).all() and (out0.res[m0:][in0] > 0.1).all()   # counted, not flagged
+    out1 = NH.feast(A, None, 0.0, r, m0, 16, 1e-10, X0, maxloop=1)
+    in1 = NH.inside(0.0, r, out1.E)
+    k = int(in1.sum())
+    assert k >= 1, "a Ritz value stays in the region at the second loop"
+    assert out1.M == 0 and out1.info == 2
+    # flagged pairs come last on both sides, with res = -1
+    assert in1[m0 - k:].all() and (out1.res[m0 - k:m0] == -1.0).all() and (out1.res[2 * m0 - k:] == -1.0).all()
+    th = out1.E[m0 - k:]
+    X, Xh = out1.X[:, m0 - k:m0], out1.X[:, 2 * m0 - k:]
+    rr = np.abs(A @ X - X * th).sum(0) / (alpha * np.abs(X).sum(0))
+    rl = np.abs(A.conj().T @ Xh - Xh * np.conj(th)).sum(0) / (alpha * np.abs(Xh).sum(0))
+    assert (rr > 0.1).all() and (rl > 0.1).all()
+
+
+def test_trace_convergence_test_conv0():
+    """fpm(6) = 0: stop at the first loop k >= 1 whose relative trace change
+    |sum_M lambda (loop k) - sum_M lambda (loop k - 1)| / alpha is below tol,
+    alpha = |Emid| + r.  Pinned by the known spectrum of a rotation-block
+    matrix (the counted eigenvalues at the stop are the exact ones), by the
+    previous loop's trace (a run of the same start stopped one loop
+    earlier), and by the first loop never stopping under this test."""
+    rng = np.random.default_rng(21)
+    n = 40
+    D = np.zeros((n, n))
+    lam = []
+    for k in range(0, 24, 2):
+        a, b = rng.uniform(-1, 1), rng.uniform(0.1, 1)
+        D[k, k] = D[k + 1, k + 1] = a
+        D[k, k + 1], D[k + 1, k] = b, -b
+        lam += [a + 1j * b, a - 1j * b]
+    for k in range(24, n):
+        D[k, k] = rng.uniform(-1, 1)
+        lam.append(D[k, k] + 0j)
+    lam = np.array(lam)
+    S = np.eye(n) + rng.standard_normal((n, n)) / (2 * math.sqrt(n))
+    A = S @ D @ np.linalg.inv(S)
+    emid, r, tol = 0.05 + 0.0j, 0.6, 1e-12
+    alpha = abs(emid) + r
+    count = int(NH.inside(emid, r, lam).sum())
+    m0 = 2 * count + 4
+    X0 = rng.uniform(-1, 1, (n, 2 * m0))
+    out = NH.feast(A, None, emid, r, m0, 16, tol, X0, conv=0)
+    assert out.info == 0 and out.M == count and out.loop >= 1
+    assert out.epsout < tol
+    exact = lam[NH.inside(emid, r, lam)]
+    got = out.E[:out.M]
+    assert max(np.abs(exact - g).min() for g in got) < 1e-9
+    prev = NH.feast(A, None, emid, r, m0, 16, tol, X0, conv=0, maxloop=out.loop - 1)
+    assert prev.info == 2 and prev.loop == out.loop - 1
+    expected = abs(got.sum() - prev.E[:prev.M].sum()) / alpha
+    assert abs(out.epsout - expected) <= 1e-13 * max(1.0, expected)
+    if prev.loop >= 1:
+        assert prev.epsout >= tol
+    # the first loop never stops under the trace test, even on a converged start
+    once = NH.feast(A, None, emid, r, m0, 16, tol, out.X, conv=0, maxloop=0)
+    assert once.info == 2 and once.loop == 0 and once.epsout == 1.0
