@@ -32,8 +32,11 @@
  *     remaining Ritz pairs outside the interval, ascending; spurious pairs
  *     (inside the interval but with residual > 0.1) come last with res = -1
  *     (Table "tab_common", remark on E, X and res).
- *   - The library keeps device workspace (factors, subspaces) between calls
- *     and frees it in feast_release().  Calls are serialised internally; the
+ *   - Each host thread has its own context for the single-problem entry
+ *     points: device workspace (factors, subspaces) and streams, created at
+ *     the thread's first call, kept between its calls and freed by
+ *     feast_release() from that thread.  Threads may call concurrently; the
+ *     batched entry points and the server run their own executor.  The
  *     library never frees caller memory.
  */
 #ifndef FEASTX_H
@@ -301,12 +304,12 @@ int feast_rational(double Emin, double Emax, int fpm2, int fpm16, int fpm18, con
 /* The same filter for custom nodes and weights (tool "[sd]feast_rationalx"). */
 int feast_rationalx(const feast_z *Zne, const feast_z *Wne, int fpm2, const double *eig, int m, double *f);
 
-/* Statistics of the last solve on this process; 0 on success. */
+/* Statistics of the calling thread's last solve; 0 on success. */
 int feast_last_stats(feast_stats *stats);
 /* Enable (1) or disable (0) per-launch HIP-event timing of the complex64
  * matrix-product kernel (reported in feast_stats). */
 void feast_set_timing(int on);
-/* Free the library's device workspace. */
+/* Free the calling thread's context (device workspace and streams). */
 void feast_release(void);
 /* Library version string. */
 const char *feast_version(void);

@@ -1,6 +1,6 @@
 // Shared device helpers for the FEAST library: complex arithmetic on
-// interleaved {re, im} pairs, matrix-core (MFMA) wrappers for gfx950, a
-// grid-wide barrier for cooperative launches, and error plumbing.
+// interleaved {re, im} pairs, matrix-core (MFMA) wrappers for gfx950, and
+// error plumbing.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -92,54 +92,6 @@ template <typename T> __device__ inline T wave_sum(T v)
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
 }
-
-// ------------------------------------------------------- grid barrier
-// Sense-counting barrier for cooperative launches (all blocks co-resident).
-// `count` returns to zero after every barrier; `gen` only grows, so each
-// launch reads its starting generation once at entry.
-struct grid_sync {
-    unsigned *count, *gen;
-    unsigned nblocks;
-    unsigned local_gen;
-
-    __device__ void init(unsigned *c, unsigned *g, unsigned nb)
-    {
-        count = c;
-        gen = g;
-        nblocks = nb;
-        local_gen = __hip_atomic_load(g, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __device__ void sync()
-    {
-        // __syncthreads() orders every wave's stores before thread 0's
-        // arrival, a release at agent scope.  The last arrival reads the end
-        // of the release sequence on `count`, resets it and releases the
-        // generation word, then acquires (so it has every block's data); the
-        // others poll the generation with relaxed loads and acquire once it
-        // has moved.  Polling with
-        // acquire loads would invalidate the XCD's L2 on every poll and cost
-        // the other workgroups there their cached lines.
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const unsigned g = local_gen;
-            const unsigned prev = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            if (prev == nblocks - 1) {
-                // release the others first; this block's own acquire (which
-                // pairs with every arrival's release through the read of
-                // `count` above) can follow off their critical path
-                __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            } else {
-                while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g)
-                    __builtin_amdgcn_s_sleep(1);
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            }
-        }
-        local_gen += 1;
-        __syncthreads();
-    }
-};
 
 inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
 

@@ -12,6 +12,7 @@
 //                     eigenproblem by GPU Jacobi, Ritz vectors, residuals
 // The host only decides convergence from a few scalars per loop.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -69,10 +70,9 @@ struct Workspace {
     int fres = 0;
     hipStream_t fmain = nullptr, fside = nullptr;
     hipEvent_t ev_c = nullptr, ev_d = nullptr;
-    unsigned *bar = nullptr;
+    hipEvent_t ev_j[2] = {nullptr, nullptr};   // reduced eigensolve: stop words read back per sweep
     int device = -1;
     int num_cu = 0;
-    int jac_max_blocks = 0;
 
     void *get(const std::string &name, size_t bytes)
     {
@@ -116,13 +116,8 @@ struct Workspace {
         hipDeviceProp_t prop;
         FX_CHECK(hipGetDeviceProperties(&prop, device));
         num_cu = prop.multiProcessorCount;
-        int per_cu = 0;
-        FX_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bjacobi_kernel<true>, BJ_NT, 0));
-        int per_cu_r = 0;
-        FX_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_r, bjacobi_kernel<false>, BJ_NT, 0));
-        jac_max_blocks = std::max(1, std::min(per_cu, per_cu_r)) * num_cu;
-        bar = static_cast<unsigned *>(get("grid_barrier", 2 * sizeof(unsigned)));
-        FX_CHECK(hipMemset(bar, 0, 2 * sizeof(unsigned)));
+        FX_CHECK(hipEventCreateWithFlags(&ev_j[0], hipEventDisableTiming));
+        FX_CHECK(hipEventCreateWithFlags(&ev_j[1], hipEventDisableTiming));
         FX_CHECK(hipDeviceSynchronize());
     }
     void drop_split()
@@ -169,11 +164,11 @@ struct Workspace {
         for (auto &kv : dev) b += (double)kv.second.second;
         return b;
     }
-    // free the device buffers except the grid-barrier words
+    // free the device buffers
     void trim()
     {
         for (auto &kv : dev)
-            if (kv.first != "grid_barrier" && kv.second.first) {
+            if (kv.second.first) {
                 (void)hipFree(kv.second.first);
                 kv.second.first = nullptr;
                 kv.second.second = 0;
@@ -191,18 +186,27 @@ struct Workspace {
         if (side) (void)hipStreamDestroy(side);
         if (ev_a) (void)hipEventDestroy(ev_a);
         if (ev_b) (void)hipEventDestroy(ev_b);
+        for (auto &e : ev_j)
+            if (e) (void)hipEventDestroy(e);
         drop_split();
         stream = side = nullptr;
         ev_a = ev_b = nullptr;
-        bar = nullptr;
+        ev_j[0] = ev_j[1] = nullptr;
     }
 };
 
-static Workspace g_ws;
-static std::mutex g_mu;
-static std::mutex g_coop_mu;   // cooperative launches take turns (see the executor)
-static feast_stats g_stats;
-static bool g_timing = false;
+// One context per host thread for the single-problem entry points: its
+// workspace (device buffers, streams) is created at the thread's first call
+// and freed by feast_release() from that thread; its statistics are those of
+// the thread's last solve.
+static thread_local Workspace *t_ws = nullptr;
+static thread_local feast_stats t_stats;
+static Workspace &thread_ws()
+{
+    if (!t_ws) t_ws = new Workspace();
+    return *t_ws;
+}
+static std::atomic<bool> g_timing{false};
 static const bool g_debug = std::getenv("FEASTX_DEBUG") != nullptr;
 static const bool g_no_lookahead = std::getenv("FEASTX_NO_LOOKAHEAD") != nullptr;   // tuning knob
 
@@ -444,7 +448,10 @@ static void dgemm(Workspace &ws, hipStream_t s, bool opa_h, int m, int n, int k,
 static dim3 grid1(long count) { return dim3((unsigned)((count + 255) / 256)); }
 
 // Reduced Hermitian eigenproblem on the device: C (m x m, overwritten) ->
-// ascending eigenvalues w (device) and eigenvectors Vout (m x m).
+// ascending eigenvalues w (device) and eigenvectors Vout (m x m).  One
+// launch per Jacobi round on stream s; the host reads each sweep's stopping
+// decision back while the next sweep is already queued behind it (a stopped
+// iteration's queued launches return at once).
 template <bool CPLX>
 static void device_eigh(Workspace &ws, hipStream_t s, int m, F64<CPLX> *C, F64<CPLX> *Vout, double *w,
                         feast_stats &st, double tol = 1e-13)
@@ -452,28 +459,42 @@ static void device_eigh(Workspace &ws, hipStream_t s, int m, F64<CPLX> *C, F64<C
     using E = F64<CPLX>;
     E *V = static_cast<E *>(ws.get("jac_v", sizeof(E) * (size_t)m * m));
     E *C1 = static_cast<E *>(ws.get("jac_c1", sizeof(E) * (size_t)m * m));
-    const int nb = (m + BJ_BS - 1) / BJ_BS, nbp = nb + (nb & 1), npairs = nbp / 2;
+    const int nb = (m + BJ_BS - 1) / BJ_BS, nbp = nb + (nb & 1), npairs = nbp / 2, rounds = nbp - 1;
     E *Rbuf = static_cast<E *>(ws.get("jac_r", sizeof(E) * 2 * (size_t)npairs * BJ_W * BJ_W));
     E *Dbuf = static_cast<E *>(ws.get("jac_d", sizeof(E) * (size_t)nbp * BJ_BS * BJ_BS));
     double *dout = static_cast<double *>(ws.get("jac_diag", sizeof(double) * m));
     const int nrc = (m + BJ_W - 1) / BJ_W;
     const int nitems = npairs * (npairs + 1) / 2 + nrc * npairs;
-    // one workgroup per block pair plus about two tile updates per other
-    // workgroup, few enough to keep grid barriers cheap
-    int G = std::max(npairs + 1, std::min(npairs + (nitems + 1) / 2, 96));
-    G = std::min(G, ws.jac_max_blocks);
-    // two halves of per-workgroup off-norm partials (by sweep parity), then the Frobenius partials
-    double *partial = static_cast<double *>(ws.get("jac_partial", sizeof(double) * 3 * (size_t)G));
+    const int g_init = std::min(ceil_div((long)m * m, BJ_NT), 256);
+    double *partial = static_cast<double *>(ws.get("jac_partial", sizeof(double) * (size_t)std::max(nitems, g_init)));
+    jac_state *jst = static_cast<jac_state *>(ws.get("jac_state", sizeof(jac_state)));
     int *status = static_cast<int *>(ws.get("jac_status", sizeof(int) * 2));
     double *hist = static_cast<double *>(ws.get("jac_hist", sizeof(double) * 64));
     int *rank = static_cast<int *>(ws.get("jac_rank", sizeof(int) * m));
-    long ld = m;
-    int max_sweeps = 40;
-    unsigned *bar = ws.bar;
-    void *args[] = {&m, &C, &C1, &ld, &V, &ld, &Rbuf, &Dbuf, &partial, &bar, &max_sweeps, &tol, &status, &hist, &dout};
-    std::lock_guard<std::mutex> coop(g_coop_mu);
-    FX_CHECK(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(bjacobi_kernel<CPLX>), dim3(G),
-                                        dim3(BJ_NT), args, 0, s));
+    constexpr int max_sweeps = 40;
+    int *h_stop = static_cast<int *>(ws.pinned("jac_stop_h", sizeof(int) * (max_sweeps + 1)));
+    const long ld = m;
+    hipLaunchKernelGGL(jacobi_reset_kernel, dim3(1), dim3(1), 0, s, jst);
+    hipLaunchKernelGGL((jacobi_init_kernel<CPLX>), dim3(g_init), dim3(BJ_NT), 0, s, m, C, ld, V, ld, partial, jst);
+    FX_LAUNCH_CHECK();
+    int t = 0;
+    for (int sw = 1; sw <= max_sweeps; ++sw) {
+        // rounds up to the launch that forms the matrix after sweep sw and decides
+        for (; t <= rounds * sw; ++t) {
+            const unsigned g = (unsigned)(npairs + (t > 0 ? nitems : 0));
+            hipLaunchKernelGGL((bjacobi_round_kernel<CPLX>), dim3(g), dim3(BJ_NT), 0, s, t, m, C, C1, ld, V, ld, Rbuf,
+                               Dbuf, partial, jst, max_sweeps, tol, hist);
+        }
+        FX_LAUNCH_CHECK();
+        FX_CHECK(hipMemcpyAsync(h_stop + sw, &jst->stop, sizeof(int), hipMemcpyDeviceToHost, s));
+        FX_CHECK(hipEventRecord(ws.ev_j[sw & 1], s));
+        if (sw >= 2) {
+            FX_CHECK(hipEventSynchronize(ws.ev_j[(sw - 1) & 1]));
+            if (h_stop[sw - 1]) break;
+        }
+    }
+    hipLaunchKernelGGL((jacobi_final_kernel<CPLX>), dim3(ceil_div(m, 256)), dim3(256), 0, s, m, C, C1, ld, jst, dout,
+                       status);
     hipLaunchKernelGGL((jacobi_sort_kernel<CPLX>), dim3(1), dim3(1024), 0, s, m, dout, V, ld, w, Vout, ld, rank);
     FX_LAUNCH_CHECK();
     int *hst = static_cast<int *>(ws.pinned("jac_status_h", sizeof(int) * 2));
@@ -484,7 +505,7 @@ static void device_eigh(Workspace &ws, hipStream_t s, int m, F64<CPLX> *C, F64<C
     if (g_debug) {
         double hh[64];
         FX_CHECK(hipMemcpy(hh, hist, sizeof(double) * std::min(hst[1], 64), hipMemcpyDeviceToHost));
-        std::fprintf(stderr, "feastx eigh n=%d G=%d sweeps=%d off/fro:", m, G, hst[1]);
+        std::fprintf(stderr, "feastx eigh n=%d rounds=%d launches=%d sweeps=%d off/fro:", m, rounds, t, hst[1]);
         for (int i = 0; i < std::min(hst[1], 40); ++i) std::fprintf(stderr, " %.1e", hh[i]);
         std::fprintf(stderr, "\n");
     }
@@ -1577,14 +1598,14 @@ void gemm_timing_reset() { t_event_next = 0; }
 // ======================================================================
 namespace fx {
 
-// The reduced eigensolve is a cooperative launch with grid barriers; two of
-// them in flight on different streams could each hold part of the device
-// while waiting for the rest, so slots take turns for that launch
-// (g_coop_mu, held from launch to completion in device_eigh).
+// Slots share nothing on the device: each has its own stream and workspace,
+// and no kernel of the library waits for another workgroup, so their work
+// interleaves freely.
 
 // Most concurrent slots of one executor.  Runs of 256 uneven problems have
-// completed with 8 slots in both precisions; one FP64 run with 16 slots
-// stalled without a cause found, so larger requests are clamped to 8.
+// completed with 8 slots in both precisions.  One FP64 run with 16 slots
+// stalled, with the earlier grid-barrier eigensolver, and no cause was
+// established, so larger requests are clamped to 8.
 constexpr int MAX_SLOTS = 8;
 
 struct Job {
@@ -1828,11 +1849,11 @@ static int solve_single(bool cplx, int device, int N, const void *A, int lda, co
     fx::SolveArgs a{cplx, N, A, lda, B, ldb, Emin, Emax, *M0, X, ldx, E, res, device,
                     static_cast<hipStream_t>(stream)};
     fx::SolveOut so;
-    std::lock_guard<std::mutex> lk(fx::g_mu);
-    fx::g_ws.want_split = true;
-    fx::g_ws.lookahead = true;
-    fx::solve_in(fx::g_ws, o, a, so);
-    fx::g_stats = so.st;
+    fx::Workspace &ws = fx::thread_ws();
+    ws.want_split = true;
+    ws.lookahead = true;
+    fx::solve_in(ws, o, a, so);
+    fx::t_stats = so.st;
     if (so.info == 0 || so.info == 1 || so.info == 2 || so.info == 3 || so.info == 4 || so.info == 5) {
         *M = so.M;
         *M0 = so.m0;
@@ -1974,8 +1995,7 @@ static int gsolve(bool real_in, int N, const void *A, int lda, const void *B, in
     if (!M) return -113;
     if (!res) return -114;
     const int m0 = *M0;
-    std::lock_guard<std::mutex> lk(fx::g_mu);
-    fx::Workspace &ws = fx::g_ws;
+    fx::Workspace &ws = fx::thread_ws();
     fx::GResult out;
     feast_stats st{};
     int info;
@@ -2036,7 +2056,7 @@ static int gsolve(bool real_in, int N, const void *A, int lda, const void *B, in
         std::fprintf(stderr, "feastx: HIP error %s\n", hipGetErrorString(e.code));
         info = -4;
     }
-    fx::g_stats = st;
+    fx::t_stats = st;
     if (info >= 0 && info <= 3) {
         for (int i = 0; i < m0; ++i) {
             E[i].re = out.E[i].x;
@@ -2372,21 +2392,21 @@ void feast_server_destroy(feast_server *srv)
 int feast_last_stats(feast_stats *st)
 {
     if (!st) return -101;
-    std::lock_guard<std::mutex> lk(fx::g_mu);
-    *st = fx::g_stats;
+    *st = fx::t_stats;
     return 0;
 }
 
 void feast_set_timing(int on)
 {
-    std::lock_guard<std::mutex> lk(fx::g_mu);
     fx::g_timing = on != 0;
 }
 
 void feast_release(void)
 {
-    std::lock_guard<std::mutex> lk(fx::g_mu);
-    fx::g_ws.release();
+    if (!fx::t_ws) return;
+    fx::t_ws->release();
+    delete fx::t_ws;
+    fx::t_ws = nullptr;
 }
 
 }  // extern "C"

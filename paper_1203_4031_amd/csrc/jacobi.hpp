@@ -64,18 +64,20 @@ __device__ inline void rr_pair(int s, int i, int p, int &a, int &b)
 // t-1's results directly -- its diagonal blocks are the diagonal blocks of
 // round t-1's rotated pair submatrices (kept in Dbuf), its off-diagonal
 // block is R_{t-1,P1}^H C_{t-1}[P1, P2] R_{t-1,P2} restricted to blocks I
-// and J (P1, P2 the round t-1 pairs holding I and J) -- so the inner sweeps
-// of round t run while other workgroups form C_t, and each round costs one
-// grid barrier.  C is double-buffered (C_t read, C_{t+1} written) and so is
-// R; only the tiles P <= Q are formed (C is Hermitian), the others are
-// written as their mirror.  The off-diagonal norm is summed from
-// per-workgroup partials in a fixed order, so every workgroup takes the
-// same stopping decision.  The partials alternate between two halves by
-// sweep parity: with a single round per sweep (m <= 2 BS) a workgroup
-// writes the next sweep's partial before the next grid barrier, and a
-// shared half could change under a slower workgroup still summing the
-// current one, which would then take a different decision and leave the
-// others waiting at a barrier it never reaches.
+// and J (P1, P2 the round t-1 pairs holding I and J) -- so one launch runs
+// the inner sweeps of round t in some workgroups and forms C_t, V_t (the
+// tile updates of round t-1) in the others.  C is double-buffered (C_t
+// read, C_{t+1} written) and so is R; only the tiles P <= Q are formed (C
+// is Hermitian), the others are written as their mirror.
+//
+// One launch per round, and no workgroup ever waits for another: the
+// kernel boundary orders the rounds.  At the end of a sweep, the tile
+// workgroups of that launch write off-norm partials; the last of them to
+// finish (an atomic arrival count, which nobody waits on) sums them in a
+// fixed order and takes the stopping decision alone, into a state word that
+// every later launch reads at entry (a stopped iteration's remaining
+// launches return at once).  The host enqueues one sweep ahead of the
+// decision it has read back.
 //
 // Rotation for a pair (a < b), c_ab = |c_ab| e^{i phi}, d = c_bb - c_aa:
 //   t = sign(d) 2|c_ab| / (|d| + sqrt(d^2 + 4 |c_ab|^2))  (tan of the angle),
@@ -153,18 +155,97 @@ __device__ __forceinline__ void jrot(typename jelem<CPLX>::type cab, double aa, 
     }
 }
 
+// Iteration state of one reduced eigensolve, in device memory.  `stop` and
+// `t_final` are written only by the workgroup that takes a sweep's stopping
+// decision; every launch reads `stop` at entry.
+struct jac_state {
+    double fro;        // Frobenius norm of the start matrix
+    double off_prev;   // off-diagonal norm after the previous sweep
+    int sweep;         // sweeps completed
+    int stop;          // 1: no further round runs
+    int conv;          // 1: stopped by the tolerance (0 with stop: sweep limit)
+    int t_final;       // round whose launch formed the final C (in buffer t_final & 1)
+    unsigned count;    // arrivals of the current launch's partial writers
+    unsigned pad;
+};
+
+// Last of `total` arriving workgroups (called by one thread after its partial
+// store).  The arrival is a release/acquire RMW, so the last arrival sees
+// every earlier workgroup's partial; it also returns the count to zero for
+// the next launch.  Nothing waits on the count.
+__device__ inline bool jac_last_arrival(unsigned *count, unsigned total)
+{
+    const unsigned prev = __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (prev != total - 1) return false;
+    __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return true;
+}
+
+__global__ void jacobi_reset_kernel(jac_state *st)
+{
+    st->fro = 0.0;
+    st->off_prev = 1e300;
+    st->sweep = 0;
+    st->stop = 0;
+    st->conv = 0;
+    st->t_final = 0;
+    st->count = 0;
+    st->pad = 0;
+}
+
+// V = I and the Frobenius norm of C0 (per-workgroup partials, summed by the
+// last workgroup in index order).
 template <bool CPLX>
-__global__ __launch_bounds__(BJ_NT) void bjacobi_kernel(int n, typename jelem<CPLX>::type *C0,
-                                                        typename jelem<CPLX>::type *C1, long ldc,
-                                                        typename jelem<CPLX>::type *V, long ldv,
-                                                        typename jelem<CPLX>::type *Rbuf,
-                                                        typename jelem<CPLX>::type *Dbuf, double *partial,
-                                                        unsigned *bar, int max_sweeps, double tol, int *status,
-                                                        double *hist, double *dout)
+__global__ __launch_bounds__(BJ_NT) void jacobi_init_kernel(int n, const typename jelem<CPLX>::type *C0, long ldc,
+                                                            typename jelem<CPLX>::type *V, long ldv, double *partial,
+                                                            jac_state *st)
+{
+    using E = typename jelem<CPLX>::type;
+    __shared__ double s_red[BJ_NT / 64];
+    __shared__ int s_last;
+    const int tid = threadIdx.x, bid = blockIdx.x, G = gridDim.x;
+    const long gtid = (long)bid * BJ_NT + tid, gthreads = (long)G * BJ_NT;
+    double acc = 0.0;
+    for (long e = gtid; e < (long)n * n; e += gthreads) {
+        const int i = (int)(e % n), j = (int)(e / n);
+        V[i + j * ldv] = jreal<E>(i == j ? 1.0 : 0.0);
+        acc += jabs2(C0[i + j * ldc]);
+    }
+    acc = wave_sum(acc);
+    if ((tid & 63) == 0) s_red[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        double b = 0.0;
+        for (int q = 0; q < BJ_NT / 64; ++q) b += s_red[q];
+        partial[bid] = b;
+        s_last = jac_last_arrival(&st->count, (unsigned)G) ? 1 : 0;
+        if (s_last) {
+            double f2 = 0.0;
+            for (int q = 0; q < G; ++q) f2 += __hip_atomic_load(partial + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            st->fro = sqrt(f2);
+        }
+    }
+}
+
+// One round t of the block Jacobi: workgroups [0, npairs) run the inner
+// sweeps of round t on the block pairs; workgroups [npairs, npairs + nitems)
+// (present for t >= 1) form C_t = R^H C_{t-1} R and V_t = V_{t-1} R, one
+// C tile or V tile each.  When round t-1 ends a sweep, the tile workgroups
+// also write the squared off-diagonal norm of their tiles of C_t, and the
+// last of them takes the stopping decision.
+template <bool CPLX>
+__global__ __launch_bounds__(BJ_NT) void bjacobi_round_kernel(int t, int n, typename jelem<CPLX>::type *C0,
+                                                              typename jelem<CPLX>::type *C1, long ldc,
+                                                              typename jelem<CPLX>::type *V, long ldv,
+                                                              typename jelem<CPLX>::type *Rbuf,
+                                                              typename jelem<CPLX>::type *Dbuf, double *partial,
+                                                              jac_state *st, int max_sweeps, double tol,
+                                                              double *hist)
 {
     using E = typename jelem<CPLX>::type;
     static_assert(BJ_NT == BJ_BS * BJ_BS, "one thread per 2x2 block of rotation pairs");
     static_assert((BJ_BS & (BJ_BS - 1)) == 0, "across-block pairing uses a power-of-two block");
+    if (st->stop) return;   // written by an earlier launch: the same for every workgroup
     __shared__ E L0[BJ_W][BJ_W + 1];
     __shared__ E L0b[BJ_W][BJ_W + 1];
     __shared__ E L1[BJ_W][BJ_W + 1];
@@ -172,353 +253,339 @@ __global__ __launch_bounds__(BJ_NT) void bjacobi_kernel(int n, typename jelem<CP
     __shared__ int s_iP[BJ_W], s_iQ[BJ_W];
     __shared__ double s_red[BJ_NT / 64];
 
-    grid_sync gs;
-    gs.init(bar, bar + 1, gridDim.x);
-    const int G = gridDim.x, tid = threadIdx.x, bid = blockIdx.x, lane = tid & 63;
-    const long gtid = (long)bid * BJ_NT + tid, gthreads = (long)G * BJ_NT;
+    const int tid = threadIdx.x, bid = blockIdx.x, lane = tid & 63;
     const int nb = (n + BJ_BS - 1) / BJ_BS;
     const int nbp = nb + (nb & 1), npairs = nbp / 2, rounds = nbp - 1;
     const int nrc = (n + BJ_W - 1) / BJ_W;   // row chunks of V
     const long RS = (long)npairs * BJ_W * BJ_W;
     const int n_ctiles = npairs * (npairs + 1) / 2, nitems = n_ctiles + nrc * npairs;
     E *Cb[2] = {C0, C1};
+    const int s = t % rounds;
+    E *Rcur = Rbuf + (long)(t & 1) * RS;
+    const E *Rprev = Rbuf + (long)((t + 1) & 1) * RS;
+    const E *Cprev = Cb[(t + 1) & 1];
 
-    auto block_reduce = [&](double v) {
-        v = wave_sum(v);
-        if ((tid & 63) == 0) s_red[tid >> 6] = v;
-        __syncthreads();
-        double t = 0.0;
-        for (int q = 0; q < BJ_NT / 64; ++q) t += s_red[q];
-        __syncthreads();
-        return t;
-    };
     // indices of the 2 BS rows of block pair P of pairing s (-1 = padding)
-    auto pair_idx = [&](int s, int P, int *dst) {
+    auto pair_idx = [&](int sq, int P, int *dst) {
+        int I, J;
+        rr_pair(sq, P, nbp, I, J);
+        for (int u = tid; u < BJ_W; u += BJ_NT) {
+            const int g = (u < BJ_BS) ? I * BJ_BS + u : J * BJ_BS + (u - BJ_BS);
+            dst[u] = g < n ? g : -1;
+        }
+    };
+
+    if (bid < npairs) {
+        // ---------------- round t: inner Jacobi on block pair P
+        const int P = bid;
         int I, J;
         rr_pair(s, P, nbp, I, J);
-        for (int t = tid; t < BJ_W; t += BJ_NT) {
-            const int g = (t < BJ_BS) ? I * BJ_BS + t : J * BJ_BS + (t - BJ_BS);
-            dst[t] = g < n ? g : -1;
-        }
-    };
-
-    double acc = 0.0;
-    for (long e = gtid; e < (long)n * n; e += gthreads) {
-        const int i = (int)(e % n), j = (int)(e / n);
-        V[i + j * ldv] = jreal<E>(i == j ? 1.0 : 0.0);
-        acc += jabs2(C0[i + j * ldc]);
-    }
-    double bs = block_reduce(acc);
-    if (tid == 0) partial[2 * G + bid] = bs;
-    gs.sync();
-    double fro2 = 0.0;
-    for (int q = 0; q < G; ++q) fro2 += partial[2 * G + q];
-    const double fro = sqrt(fro2);
-
-    int sweep = 0, conv = 0, t = 0;
-    double off_prev = 1e300;
-    for (;; ++t) {
-        const int s = t % rounds;
-        E *Rcur = Rbuf + (long)(t & 1) * RS;
-        const E *Rprev = Rbuf + (long)((t + 1) & 1) * RS;
-        const E *Cprev = Cb[(t + 1) & 1];
-        // ---------------- phase 1 of round t: inner Jacobi on each block pair
-        for (int P = bid; P < npairs; P += G) {
-            int I, J;
-            rr_pair(s, P, nbp, I, J);
+        pair_idx(s, P, s_iP);
+        __syncthreads();
+        if (t == 0) {
+            for (int e = tid; e < BJ_W * BJ_W; e += BJ_NT) {
+                const int a = e % BJ_W, b = e / BJ_W;
+                const int ia = s_iP[a], ib = s_iP[b];
+                L0[a][b] = (ia >= 0 && ib >= 0) ? C0[ia + (long)ib * ldc] : jzero<E>();
+            }
+        } else {
+            // off-diagonal block C_t[I, J] from round t-1; every input
+            // (the C tile, both rotations, the diagonal blocks) is
+            // fetched at once
+            const int sp = (t - 1) % rounds;
+            int P1, h1, P2, h2;
+            rr_locate(sp, I, nbp, P1, h1);
+            rr_locate(sp, J, nbp, P2, h2);
+            pair_idx(sp, P1, s_iQ);        // rows: pair P1 of round t-1
+            pair_idx(sp, P2, s_iP);        // columns: pair P2 (s_iP rebuilt below)
+            __syncthreads();
+            const E *R1 = Rprev + (long)P1 * BJ_W * BJ_W, *R2 = Rprev + (long)P2 * BJ_W * BJ_W;
+            for (int e = tid; e < BJ_W * BJ_W; e += BJ_NT) {
+                const int a = e % BJ_W, b = e / BJ_W;
+                const int ia = s_iQ[a], ib = s_iP[b];
+                L0[a][b] = (ia >= 0 && ib >= 0) ? Cprev[ia + (long)ib * ldc] : jzero<E>();
+                L1[a][b] = R2[a + b * BJ_W];
+                L0b[a][b] = R1[a + b * BJ_W];
+            }
+            const E *DI = Dbuf + (long)I * BJ_BS * BJ_BS, *DJ = Dbuf + (long)J * BJ_BS * BJ_BS;
+            const E di = DI[tid], dj = DJ[tid];   // BJ_NT == BJ_BS^2: one entry each
+            __syncthreads();
+            // Y = C_{t-1}[P1, P2] R_{t-1,P2}[:, J part]   (W x BS)
+            for (int e = tid; e < BJ_W * BJ_BS; e += BJ_NT) {
+                const int a = e % BJ_W, j = e / BJ_W;
+                E sum = jzero<E>();
+#pragma unroll 8
+                for (int k = 0; k < BJ_W; ++k) sum = jadd(sum, jmul(L0[a][k], L1[k][h2 * BJ_BS + j]));
+                Ys[a][j] = sum;
+            }
+            __syncthreads();
+            // X = R_{t-1,P1}[:, I part]^H Y   (BS x BS, one entry per thread)
+            E xv = jzero<E>();
+            const int xi = tid % BJ_BS, xj = tid / BJ_BS;
+#pragma unroll 8
+            for (int k = 0; k < BJ_W; ++k) xv = jadd(xv, jmul(jconj(L0b[k][h1 * BJ_BS + xi]), Ys[k][xj]));
             pair_idx(s, P, s_iP);
             __syncthreads();
-            if (t == 0) {
-                for (int e = tid; e < BJ_W * BJ_W; e += BJ_NT) {
-                    const int a = e % BJ_W, b = e / BJ_W;
-                    const int ia = s_iP[a], ib = s_iP[b];
-                    L0[a][b] = (ia >= 0 && ib >= 0) ? C0[ia + (long)ib * ldc] : jzero<E>();
+            // diagonal blocks from round t-1's rotated pairs
+            L0[xi][xj] = di;
+            L0[BJ_BS + xi][BJ_BS + xj] = dj;
+            L0[xi][BJ_BS + xj] = xv;
+            L0[BJ_BS + xj][xi] = jconj(xv);
+        }
+        for (int e = tid; e < BJ_W * BJ_W; e += BJ_NT) {
+            const int a = e % BJ_W, b = e / BJ_W;
+            L1[a][b] = jreal<E>(a == b ? 1.0 : 0.0);
+        }
+        __syncthreads();
+        // one inner sweep: thread (p, q) = (tid mod BS, tid / BS) owns the
+        // 2x2 block of rotation pairs p and q and rows p, p + BS of the
+        // accumulated rotation's column pair q.  Every thread forms the
+        // two rotations it needs itself from the current matrix; the
+        // matrix alternates between two LDS copies, so an inner round
+        // takes one barrier.  The first round of a sweep runs all pairs
+        // (circle method over 2 BS indices); the others only the pairs
+        // across the two blocks: in inner round r, pair p is
+        // (p, BS + (p + r) mod BS).
+        {
+            const int p = tid % BJ_BS, q = tid / BJ_BS;
+            unsigned vmask = 0;
+            for (int u = 0; u < BJ_W; ++u) vmask |= (s_iP[u] >= 0 ? 1u : 0u) << u;
+            E(*A)[BJ_W + 1] = L0;
+            E(*B)[BJ_W + 1] = L0b;
+            const bool across = s != 0;
+            const int inner_rounds = across ? BJ_BS : BJ_W - 1;
+            for (int r = 0; r < inner_rounds; ++r) {
+                int ra, rb, ca, cb;
+                if (across) {
+                    ra = p;
+                    rb = BJ_BS + ((p + r) & (BJ_BS - 1));
+                    ca = q;
+                    cb = BJ_BS + ((q + r) & (BJ_BS - 1));
+                } else {
+                    rr_pair(r, p, BJ_W, ra, rb);
+                    rr_pair(r, q, BJ_W, ca, cb);
                 }
+                // accumulated-rotation entries first: their loads overlap the rotation math
+                E va[2], vb[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    va[h] = L1[p + h * BJ_BS][ca];
+                    vb[h] = L1[p + h * BJ_BS][cb];
+                }
+                double cp, cq;
+                E spe, spc, sqe, sqc;
+                jrot<CPLX>(A[ra][rb], jre(A[ra][ra]), jre(A[rb][rb]), ((vmask >> ra) & (vmask >> rb) & 1u) != 0,
+                           cp, spe, spc);
+                jrot<CPLX>(A[ca][cb], jre(A[ca][ca]), jre(A[cb][cb]), ((vmask >> ca) & (vmask >> cb) & 1u) != 0,
+                           cq, sqe, sqc);
+                const E x00 = A[ra][ca], x01 = A[ra][cb], x10 = A[rb][ca], x11 = A[rb][cb];
+                // M = X J_q,  J = [[c, s e^{i phi}], [-s e^{-i phi}, c]]
+                const E m00 = jsub(jscale(x00, cq), jmul(sqc, x01));
+                const E m01 = jadd(jmul(sqe, x00), jscale(x01, cq));
+                const E m10 = jsub(jscale(x10, cq), jmul(sqc, x11));
+                const E m11 = jadd(jmul(sqe, x10), jscale(x11, cq));
+                // C' = J_p^H M
+                E y00 = jsub(jscale(m00, cp), jmul(spe, m10));
+                E y01 = jsub(jscale(m01, cp), jmul(spe, m11));
+                E y10 = jadd(jmul(spc, m00), jscale(m10, cp));
+                E y11 = jadd(jmul(spc, m01), jscale(m11, cp));
+                if (p == q) {
+                    y01 = jzero<E>();
+                    y10 = jzero<E>();
+                    y00 = jreal<E>(jre(y00));
+                    y11 = jreal<E>(jre(y11));
+                }
+                B[ra][ca] = y00;
+                B[ra][cb] = y01;
+                B[rb][ca] = y10;
+                B[rb][cb] = y11;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int x = p + h * BJ_BS;
+                    L1[x][ca] = jsub(jscale(va[h], cq), jmul(sqc, vb[h]));
+                    L1[x][cb] = jadd(jmul(sqe, va[h]), jscale(vb[h], cq));
+                }
+                __syncthreads();
+                E(*T)[BJ_W + 1] = A;
+                A = B;
+                B = T;
+            }
+            // the rotated pair matrix is in A
+            if (A != L0)
+                for (int e = tid; e < BJ_W * BJ_W; e += BJ_NT) L0[e % BJ_W][e / BJ_W] = A[e % BJ_W][e / BJ_W];
+        }
+        __syncthreads();
+        E *R = Rcur + (long)P * BJ_W * BJ_W;
+        for (int e = tid; e < BJ_W * BJ_W; e += BJ_NT) {
+            const int a = e % BJ_W, b = e / BJ_W;
+            R[a + b * BJ_W] = L1[a][b];
+        }
+        E *DI = Dbuf + (long)I * BJ_BS * BJ_BS, *DJ = Dbuf + (long)J * BJ_BS * BJ_BS;
+        for (int e = tid; e < BJ_BS * BJ_BS; e += BJ_NT) {
+            const int a = e % BJ_BS, b = e / BJ_BS;
+            DI[a + b * BJ_BS] = L0[a][b];
+            DJ[a + b * BJ_BS] = L0[BJ_BS + a][BJ_BS + b];
+        }
+        return;
+    }
+
+    // ---------------- round t-1's tile updates: C_t = R^H C_{t-1} R, V_t = V_{t-1} R
+    const int it = bid - npairs;
+    if (t == 0 || it >= nitems) return;
+    const int sp = (t - 1) % rounds;
+    const bool lastp = sp == rounds - 1;
+    double offacc = 0.0;
+    {
+        E *Cnext = Cb[t & 1];
+        const bool is_c = it < n_ctiles;
+        int P = 0, Q = 0, rc = 0;
+        if (is_c) {
+            Q = (int)((sqrt(8.0 * it + 1.0) - 1.0) * 0.5);
+            while ((Q + 1) * (Q + 2) / 2 <= it) ++Q;
+            while (Q * (Q + 1) / 2 > it) --Q;
+            P = it - Q * (Q + 1) / 2;
+        } else {
+            Q = (it - n_ctiles) / nrc;
+            rc = (it - n_ctiles) % nrc;
+        }
+        pair_idx(sp, Q, s_iQ);
+        if (is_c) pair_idx(sp, P, s_iP);
+        else
+            for (int u = tid; u < BJ_W; u += BJ_NT) s_iP[u] = (rc * BJ_W + u < n) ? rc * BJ_W + u : -1;
+        __syncthreads();
+        const E *RQ = Rprev + (long)Q * BJ_W * BJ_W;
+        const E *src = is_c ? Cprev : V;
+        const long lds = is_c ? ldc : ldv;
+        for (int e = tid; e < BJ_W * BJ_W; e += BJ_NT) {
+            const int a = e % BJ_W, b = e / BJ_W;
+            const int ia = s_iP[a], ib = s_iQ[b];
+            L0[a][b] = (ia >= 0 && ib >= 0) ? src[ia + (long)ib * lds] : jzero<E>();
+            L1[a][b] = RQ[a + b * BJ_W];
+        }
+        __syncthreads();
+        // T = X R_Q: each of the 4 waves forms one 16 x 16 block of T
+        // with FP64 matrix-core steps (lane l holds rows acc_row(l, r)
+        // and column l % 16 of its block; a complex product takes four
+        // real ones).  (ta, tb) = tile position of tv.
+        constexpr int NV = BJ_W * BJ_W / BJ_NT;
+        static_assert(NV == 4 && BJ_W == 32 && BJ_NT == 256, "one 16 x 16 block per wave");
+        E tv[NV];
+        int ta[NV], tb[NV];
+        const int wv = tid >> 6, bi16 = (wv & 1) * 16, bj16 = (wv >> 1) * 16, l16 = lane & 15, l4 = lane >> 4;
+        // 16 x 16 block (bi16, bj16) of op(Lx) Ly over the 32-deep tile:
+        // op = identity, Lx[row][k]; or op = ^H, conj(Lx[k][row])
+        auto block_product = [&](E (*Lx)[BJ_W + 1], E (*Ly)[BJ_W + 1], bool adj, E *outv) {
+            if constexpr (!CPLX) {
+                f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int kk = 0; kk < BJ_W / 4; ++kk) {
+                    const double xa = adj ? Lx[kk * 4 + l4][bi16 + l16] : Lx[bi16 + l16][kk * 4 + l4];
+                    acc = mfma16<double>::step(xa, Ly[kk * 4 + l4][bj16 + l16], acc);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) outv[r] = acc[r];
             } else {
-                // off-diagonal block C_t[I, J] from round t-1; every input
-                // (the C tile, both rotations, the diagonal blocks) is
-                // fetched at once
-                const int sp = (t - 1) % rounds;
-                int P1, h1, P2, h2;
-                rr_locate(sp, I, nbp, P1, h1);
-                rr_locate(sp, J, nbp, P2, h2);
-                pair_idx(sp, P1, s_iQ);        // rows: pair P1 of round t-1
-                pair_idx(sp, P2, s_iP);        // columns: pair P2 (s_iP rebuilt below)
-                __syncthreads();
-                const E *R1 = Rprev + (long)P1 * BJ_W * BJ_W, *R2 = Rprev + (long)P2 * BJ_W * BJ_W;
-                for (int e = tid; e < BJ_W * BJ_W; e += BJ_NT) {
-                    const int a = e % BJ_W, b = e / BJ_W;
-                    const int ia = s_iQ[a], ib = s_iP[b];
-                    L0[a][b] = (ia >= 0 && ib >= 0) ? Cprev[ia + (long)ib * ldc] : jzero<E>();
-                    L1[a][b] = R2[a + b * BJ_W];
-                    L0b[a][b] = R1[a + b * BJ_W];
+                f64x4 re = {0.0, 0.0, 0.0, 0.0}, im = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int kk = 0; kk < BJ_W / 4; ++kk) {
+                    double2 xa = adj ? Lx[kk * 4 + l4][bi16 + l16] : Lx[bi16 + l16][kk * 4 + l4];
+                    if (adj) xa.y = -xa.y;
+                    const double2 yb = Ly[kk * 4 + l4][bj16 + l16];
+                    re = mfma16<double>::step(xa.x, yb.x, re);
+                    re = mfma16<double>::step(-xa.y, yb.y, re);
+                    im = mfma16<double>::step(xa.x, yb.y, im);
+                    im = mfma16<double>::step(xa.y, yb.x, im);
                 }
-                const E *DI = Dbuf + (long)I * BJ_BS * BJ_BS, *DJ = Dbuf + (long)J * BJ_BS * BJ_BS;
-                const E di = DI[tid], dj = DJ[tid];   // BJ_NT == BJ_BS^2: one entry each
-                __syncthreads();
-                // Y = C_{t-1}[P1, P2] R_{t-1,P2}[:, J part]   (W x BS)
-                for (int e = tid; e < BJ_W * BJ_BS; e += BJ_NT) {
-                    const int a = e % BJ_W, j = e / BJ_W;
-                    E sum = jzero<E>();
-#pragma unroll 8
-                    for (int k = 0; k < BJ_W; ++k) sum = jadd(sum, jmul(L0[a][k], L1[k][h2 * BJ_BS + j]));
-                    Ys[a][j] = sum;
-                }
-                __syncthreads();
-                // X = R_{t-1,P1}[:, I part]^H Y   (BS x BS, one entry per thread)
-                E xv = jzero<E>();
-                const int xi = tid % BJ_BS, xj = tid / BJ_BS;
-#pragma unroll 8
-                for (int k = 0; k < BJ_W; ++k) xv = jadd(xv, jmul(jconj(L0b[k][h1 * BJ_BS + xi]), Ys[k][xj]));
-                pair_idx(s, P, s_iP);
-                __syncthreads();
-                // diagonal blocks from round t-1's rotated pairs
-                L0[xi][xj] = di;
-                L0[BJ_BS + xi][BJ_BS + xj] = dj;
-                L0[xi][BJ_BS + xj] = xv;
-                L0[BJ_BS + xj][xi] = jconj(xv);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) outv[r] = make_double2(re[r], im[r]);
             }
+        };
+        block_product(L0, L1, false, tv);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            ta[r] = bi16 + mfma16<double>::acc_row(lane, r);
+            tb[r] = bj16 + l16;
+        }
+        __syncthreads();
+        if (is_c) {
+            const E *RP = Rprev + (long)P * BJ_W * BJ_W;
+#pragma unroll
+            for (int u = 0; u < NV; ++u) L0[ta[u]][tb[u]] = tv[u];
             for (int e = tid; e < BJ_W * BJ_W; e += BJ_NT) {
                 const int a = e % BJ_W, b = e / BJ_W;
-                L1[a][b] = jreal<E>(a == b ? 1.0 : 0.0);
+                L1[a][b] = RP[a + b * BJ_W];
             }
             __syncthreads();
-            // one inner sweep: thread (p, q) = (tid mod BS, tid / BS) owns the
-            // 2x2 block of rotation pairs p and q and rows p, p + BS of the
-            // accumulated rotation's column pair q.  Every thread forms the
-            // two rotations it needs itself from the current matrix; the
-            // matrix alternates between two LDS copies, so an inner round
-            // takes one barrier.  The first round of a sweep runs all pairs
-            // (circle method over 2 BS indices); the others only the pairs
-            // across the two blocks: in inner round r, pair p is
-            // (p, BS + (p + r) mod BS).
-            {
-                const int p = tid % BJ_BS, q = tid / BJ_BS;
-                unsigned vmask = 0;
-                for (int u = 0; u < BJ_W; ++u) vmask |= (s_iP[u] >= 0 ? 1u : 0u) << u;
-                E(*A)[BJ_W + 1] = L0;
-                E(*B)[BJ_W + 1] = L0b;
-                const bool across = s != 0;
-                const int inner_rounds = across ? BJ_BS : BJ_W - 1;
-                for (int r = 0; r < inner_rounds; ++r) {
-                    int ra, rb, ca, cb;
-                    if (across) {
-                        ra = p;
-                        rb = BJ_BS + ((p + r) & (BJ_BS - 1));
-                        ca = q;
-                        cb = BJ_BS + ((q + r) & (BJ_BS - 1));
-                    } else {
-                        rr_pair(r, p, BJ_W, ra, rb);
-                        rr_pair(r, q, BJ_W, ca, cb);
-                    }
-                    // accumulated-rotation entries first: their loads overlap the rotation math
-                    E va[2], vb[2];
+            // C tile = R_P^H T
+            E ov[NV];
+            int oa[NV], ob[NV];
+            block_product(L1, L0, true, ov);
 #pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        va[h] = L1[p + h * BJ_BS][ca];
-                        vb[h] = L1[p + h * BJ_BS][cb];
-                    }
-                    double cp, cq;
-                    E spe, spc, sqe, sqc;
-                    jrot<CPLX>(A[ra][rb], jre(A[ra][ra]), jre(A[rb][rb]), ((vmask >> ra) & (vmask >> rb) & 1u) != 0,
-                               cp, spe, spc);
-                    jrot<CPLX>(A[ca][cb], jre(A[ca][ca]), jre(A[cb][cb]), ((vmask >> ca) & (vmask >> cb) & 1u) != 0,
-                               cq, sqe, sqc);
-                    const E x00 = A[ra][ca], x01 = A[ra][cb], x10 = A[rb][ca], x11 = A[rb][cb];
-                    // M = X J_q,  J = [[c, s e^{i phi}], [-s e^{-i phi}, c]]
-                    const E m00 = jsub(jscale(x00, cq), jmul(sqc, x01));
-                    const E m01 = jadd(jmul(sqe, x00), jscale(x01, cq));
-                    const E m10 = jsub(jscale(x10, cq), jmul(sqc, x11));
-                    const E m11 = jadd(jmul(sqe, x10), jscale(x11, cq));
-                    // C' = J_p^H M
-                    E y00 = jsub(jscale(m00, cp), jmul(spe, m10));
-                    E y01 = jsub(jscale(m01, cp), jmul(spe, m11));
-                    E y10 = jadd(jmul(spc, m00), jscale(m10, cp));
-                    E y11 = jadd(jmul(spc, m01), jscale(m11, cp));
-                    if (p == q) {
-                        y01 = jzero<E>();
-                        y10 = jzero<E>();
-                        y00 = jreal<E>(jre(y00));
-                        y11 = jreal<E>(jre(y11));
-                    }
-                    B[ra][ca] = y00;
-                    B[ra][cb] = y01;
-                    B[rb][ca] = y10;
-                    B[rb][cb] = y11;
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const int x = p + h * BJ_BS;
-                        L1[x][ca] = jsub(jscale(va[h], cq), jmul(sqc, vb[h]));
-                        L1[x][cb] = jadd(jmul(sqe, va[h]), jscale(vb[h], cq));
-                    }
-                    __syncthreads();
-                    E(*T)[BJ_W + 1] = A;
-                    A = B;
-                    B = T;
-                }
-                // the rotated pair matrix is in A
-                if (A != L0)
-                    for (int e = tid; e < BJ_W * BJ_W; e += BJ_NT) L0[e % BJ_W][e / BJ_W] = A[e % BJ_W][e / BJ_W];
+            for (int r = 0; r < 4; ++r) {
+                oa[r] = bi16 + mfma16<double>::acc_row(lane, r);
+                ob[r] = bj16 + l16;
             }
-            __syncthreads();
-            E *R = Rcur + (long)P * BJ_W * BJ_W;
-            for (int e = tid; e < BJ_W * BJ_W; e += BJ_NT) {
-                const int a = e % BJ_W, b = e / BJ_W;
-                R[a + b * BJ_W] = L1[a][b];
+#pragma unroll
+            for (int u = 0; u < NV; ++u) {
+                E sum = ov[u];
+                const int ia = s_iP[oa[u]], ib = s_iQ[ob[u]];
+                if (ia >= 0 && ib >= 0) {
+                    if (ia == ib) sum = jreal<E>(jre(sum));
+                    Cnext[ia + (long)ib * ldc] = sum;
+                    if (P != Q) Cnext[ib + (long)ia * ldc] = jconj(sum);
+                    if (lastp && ia != ib) offacc += (P != Q ? 2.0 : 1.0) * jabs2(sum);
+                }
             }
-            E *DI = Dbuf + (long)I * BJ_BS * BJ_BS, *DJ = Dbuf + (long)J * BJ_BS * BJ_BS;
-            for (int e = tid; e < BJ_BS * BJ_BS; e += BJ_NT) {
-                const int a = e % BJ_BS, b = e / BJ_BS;
-                DI[a + b * BJ_BS] = L0[a][b];
-                DJ[a + b * BJ_BS] = L0[BJ_BS + a][BJ_BS + b];
+        } else {
+#pragma unroll
+            for (int u = 0; u < NV; ++u) {
+                const int ia = s_iP[ta[u]], ib = s_iQ[tb[u]];
+                if (ia >= 0 && ib >= 0) V[ia + (long)ib * ldv] = tv[u];
             }
-            __syncthreads();
-        }
-        // ---------------- phase 2 of round t-1: C_t = R^H C_{t-1} R, V_t = V_{t-1} R
-        const bool have2 = t > 0;
-        const int sp = have2 ? (t - 1) % rounds : 0;
-        const bool lastp = have2 && sp == rounds - 1;
-        double offacc = 0.0;
-        if (have2) {
-            E *Cnext = Cb[t & 1];
-            const int start = (bid + G - (npairs % G)) % G;
-            for (int it = start; it < nitems; it += G) {
-                const bool is_c = it < n_ctiles;
-                int P = 0, Q = 0, rc = 0;
-                if (is_c) {
-                    Q = (int)((sqrt(8.0 * it + 1.0) - 1.0) * 0.5);
-                    while ((Q + 1) * (Q + 2) / 2 <= it) ++Q;
-                    while (Q * (Q + 1) / 2 > it) --Q;
-                    P = it - Q * (Q + 1) / 2;
-                } else {
-                    Q = (it - n_ctiles) / nrc;
-                    rc = (it - n_ctiles) % nrc;
-                }
-                pair_idx(sp, Q, s_iQ);
-                if (is_c) pair_idx(sp, P, s_iP);
-                else
-                    for (int u = tid; u < BJ_W; u += BJ_NT) s_iP[u] = (rc * BJ_W + u < n) ? rc * BJ_W + u : -1;
-                __syncthreads();
-                const E *RQ = Rprev + (long)Q * BJ_W * BJ_W;
-                const E *src = is_c ? Cprev : V;
-                const long lds = is_c ? ldc : ldv;
-                for (int e = tid; e < BJ_W * BJ_W; e += BJ_NT) {
-                    const int a = e % BJ_W, b = e / BJ_W;
-                    const int ia = s_iP[a], ib = s_iQ[b];
-                    L0[a][b] = (ia >= 0 && ib >= 0) ? src[ia + (long)ib * lds] : jzero<E>();
-                    L1[a][b] = RQ[a + b * BJ_W];
-                }
-                __syncthreads();
-                // T = X R_Q: each of the 4 waves forms one 16 x 16 block of T
-                // with FP64 matrix-core steps (lane l holds rows acc_row(l, r)
-                // and column l % 16 of its block; a complex product takes four
-                // real ones).  (ta, tb) = tile position of tv.
-                constexpr int NV = BJ_W * BJ_W / BJ_NT;
-                static_assert(NV == 4 && BJ_W == 32 && BJ_NT == 256, "one 16 x 16 block per wave");
-                E tv[NV];
-                int ta[NV], tb[NV];
-                const int wv = tid >> 6, bi16 = (wv & 1) * 16, bj16 = (wv >> 1) * 16, l16 = lane & 15, l4 = lane >> 4;
-                // 16 x 16 block (bi16, bj16) of op(Lx) Ly over the 32-deep tile:
-                // op = identity, Lx[row][k]; or op = ^H, conj(Lx[k][row])
-                auto block_product = [&](E (*Lx)[BJ_W + 1], E (*Ly)[BJ_W + 1], bool adj, E *outv) {
-                    if constexpr (!CPLX) {
-                        f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                        for (int kk = 0; kk < BJ_W / 4; ++kk) {
-                            const double xa = adj ? Lx[kk * 4 + l4][bi16 + l16] : Lx[bi16 + l16][kk * 4 + l4];
-                            acc = mfma16<double>::step(xa, Ly[kk * 4 + l4][bj16 + l16], acc);
-                        }
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) outv[r] = acc[r];
-                    } else {
-                        f64x4 re = {0.0, 0.0, 0.0, 0.0}, im = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                        for (int kk = 0; kk < BJ_W / 4; ++kk) {
-                            double2 xa = adj ? Lx[kk * 4 + l4][bi16 + l16] : Lx[bi16 + l16][kk * 4 + l4];
-                            if (adj) xa.y = -xa.y;
-                            const double2 yb = Ly[kk * 4 + l4][bj16 + l16];
-                            re = mfma16<double>::step(xa.x, yb.x, re);
-                            re = mfma16<double>::step(-xa.y, yb.y, re);
-                            im = mfma16<double>::step(xa.x, yb.y, im);
-                            im = mfma16<double>::step(xa.y, yb.x, im);
-                        }
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) outv[r] = make_double2(re[r], im[r]);
-                    }
-                };
-                block_product(L0, L1, false, tv);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    ta[r] = bi16 + mfma16<double>::acc_row(lane, r);
-                    tb[r] = bj16 + l16;
-                }
-                __syncthreads();
-                if (is_c) {
-                    const E *RP = Rprev + (long)P * BJ_W * BJ_W;
-#pragma unroll
-                    for (int u = 0; u < NV; ++u) L0[ta[u]][tb[u]] = tv[u];
-                    for (int e = tid; e < BJ_W * BJ_W; e += BJ_NT) {
-                        const int a = e % BJ_W, b = e / BJ_W;
-                        L1[a][b] = RP[a + b * BJ_W];
-                    }
-                    __syncthreads();
-                    // C tile = R_P^H T
-                    E ov[NV];
-                    int oa[NV], ob[NV];
-                    block_product(L1, L0, true, ov);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        oa[r] = bi16 + mfma16<double>::acc_row(lane, r);
-                        ob[r] = bj16 + l16;
-                    }
-#pragma unroll
-                    for (int u = 0; u < NV; ++u) {
-                        E sum = ov[u];
-                        const int ia = s_iP[oa[u]], ib = s_iQ[ob[u]];
-                        if (ia >= 0 && ib >= 0) {
-                            if (ia == ib) sum = jreal<E>(jre(sum));
-                            Cnext[ia + (long)ib * ldc] = sum;
-                            if (P != Q) Cnext[ib + (long)ia * ldc] = jconj(sum);
-                            if (lastp && ia != ib) offacc += (P != Q ? 2.0 : 1.0) * jabs2(sum);
-                        }
-                    }
-                } else {
-#pragma unroll
-                    for (int u = 0; u < NV; ++u) {
-                        const int ia = s_iP[ta[u]], ib = s_iQ[tb[u]];
-                        if (ia >= 0 && ib >= 0) V[ia + (long)ib * ldv] = tv[u];
-                    }
-                }
-                __syncthreads();
-            }
-        }
-        if (lastp) {
-            const double b2 = block_reduce(offacc);
-            if (tid == 0) partial[(sweep & 1) * G + bid] = b2;
-        }
-        gs.sync();
-        if (lastp) {
-            // C_t is the matrix after a whole sweep
-            double off2 = 0.0;
-            for (int q = 0; q < G; ++q) off2 += partial[(sweep & 1) * G + q];
-            const double off = sqrt(off2);
-            if (gtid == 0 && sweep < 64) hist[sweep] = fro > 0.0 ? off / fro : 0.0;
-            ++sweep;
-            // Stop once the off-diagonal norm is below tol * ||C||_F (a Ritz
-            // vector error of size off mixes only pairs whose eigenvalues differ
-            // by about off / error, so its residual contribution is ~off), or
-            // once rounding noise stops the decrease.
-            if (off <= tol * fro || fro == 0.0) conv = 1;
-            else if (off <= 1e-11 * fro && off >= 0.5 * off_prev) conv = 1;
-            off_prev = off;
-            if (conv || sweep >= max_sweeps) break;
         }
     }
-    const E *Cfin = Cb[t & 1];
-    for (long i = gtid; i < n; i += gthreads) dout[i] = jre(Cfin[i + i * ldc]);
-    if (gtid == 0) {
-        status[0] = conv ? 0 : -1;
-        status[1] = sweep;
+    if (!lastp) return;
+    // C_t is the matrix after a whole sweep: off-norm partial of this tile,
+    // and the stopping decision by the last tile workgroup to finish
+    offacc = wave_sum(offacc);
+    if (lane == 0) s_red[tid >> 6] = offacc;
+    __syncthreads();
+    if (tid != 0) return;
+    double b2 = 0.0;
+    for (int q = 0; q < BJ_NT / 64; ++q) b2 += s_red[q];
+    partial[it] = b2;
+    if (!jac_last_arrival(&st->count, (unsigned)nitems)) return;
+    double off2 = 0.0;
+    for (int q = 0; q < nitems; ++q) off2 += __hip_atomic_load(partial + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const double off = sqrt(off2), fro = st->fro, off_prev = st->off_prev;
+    const int sweep = st->sweep;
+    if (sweep < 64) hist[sweep] = fro > 0.0 ? off / fro : 0.0;
+    // Stop once the off-diagonal norm is below tol * ||C||_F (a Ritz vector
+    // error of size off mixes only pairs whose eigenvalues differ by about
+    // off / error, so its residual contribution is ~off), or once rounding
+    // noise stops the decrease.
+    int conv = 0;
+    if (off <= tol * fro || fro == 0.0) conv = 1;
+    else if (off <= 1e-11 * fro && off >= 0.5 * off_prev) conv = 1;
+    st->off_prev = off;
+    st->sweep = sweep + 1;
+    st->conv = conv;
+    st->t_final = t;
+    if (conv || sweep + 1 >= max_sweeps) st->stop = 1;
+}
+
+// Eigenvalue estimates (the diagonal of the final C) and the status words
+// {0 converged / -1 sweep limit, sweeps}.
+template <bool CPLX>
+__global__ void jacobi_final_kernel(int n, const typename jelem<CPLX>::type *C0, const typename jelem<CPLX>::type *C1,
+                                    long ldc, const jac_state *st, double *dout, int *status)
+{
+    const typename jelem<CPLX>::type *Cfin = (st->t_final & 1) ? C1 : C0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        dout[i] = jre(Cfin[i + (long)i * ldc]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        status[0] = st->conv ? 0 : -1;
+        status[1] = st->sweep;
     }
 }
 

@@ -2,13 +2,17 @@
 
     python tests/golden/make_oracle_fixtures.py realgen_n4096     # about 3 min on 8 cores
     python tests/golden/make_oracle_fixtures.py hermgen_n8192     # about 1 h on 8 cores
+    python tests/golden/make_oracle_fixtures.py --add-input-samples realgen_n4096
 
 Calls only the FP64 CPU oracle (oracle/) on inputs from the seeded generators
 (paper_1203_4031_amd/workloads.py, which hold none of the method's
 arithmetic).  Nothing here comes from the GPU library.  Each fixture holds:
 
-* the SHA-256 of the inputs (A, B, X0 bytes and the interval), so a test can
-  say whether it saw the same matrices;
+* the SHA-256 of the start subspace X0 (seeded random numbers only, so the
+  same to the bit on every machine) and A, B at 256 seeded positions: A and B
+  come out of LAPACK and BLAS calls whose last bits depend on the CPU, so a
+  test checks that its own A and B agree with these to rounding, and takes
+  the interval [Emin, Emax] from here;
 * info, M, the kept subspace size, loop and epsout;
 * E and res of every returned Ritz pair (in-interval ones first, ascending);
 * a projector sketch K = S2^T X_M X_M^H B S (16 x 16), with X_M the M
@@ -61,6 +65,37 @@ def input_sha256(p) -> str:
     return h.hexdigest()
 
 
+def x0_sha256(p) -> str:
+    return hashlib.sha256(np.asfortranarray(p.X0).tobytes(order="F")).hexdigest()
+
+
+SAMPLE_SEED, SAMPLES = 7003, 256
+
+
+def input_samples(p):
+    """A and B at 256 seeded (row, column) positions, real and imaginary parts."""
+    rng = np.random.Generator(np.random.PCG64(SAMPLE_SEED))
+    i = rng.integers(0, p.n, SAMPLES)
+    j = rng.integers(0, p.n, SAMPLES)
+    a, b = p.A[i, j], p.B[i, j]
+    return {"A_re": np.real(a).tolist(), "A_im": np.imag(a).tolist(),
+            "B_re": np.real(b).tolist(), "B_im": np.imag(b).tolist()}
+
+
+def inputs_match(p, ref, rtol=1e-12) -> bool:
+    """The generated A, B agree with the fixture's samples to rounding and X0
+    is the same to the bit."""
+    if x0_sha256(p) != ref["x0_sha256"]:
+        return False
+    smp = input_samples(p)
+    for key, mat in (("A", p.A), ("B", p.B)):
+        got = np.array(smp[key + "_re"]) + 1j * np.array(smp[key + "_im"])
+        want = np.array(ref["samples"][key + "_re"]) + 1j * np.array(ref["samples"][key + "_im"])
+        if np.max(np.abs(got - want)) > rtol * np.max(np.abs(mat)):
+            return False
+    return True
+
+
 def sketch_blocks(n: int):
     return [W.start_subspace(n, SKETCH_COLS, seed=s) for s in SKETCH_SEEDS]
 
@@ -82,7 +117,29 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
+def add_input_samples(name: str):
+    """Add the X0 hash and the A, B samples to an existing fixture, from the
+    generator alone (the oracle's results in it are left as they are); the
+    input SHA-256 must still match, so the samples describe the inputs the
+    oracle saw."""
+    path = os.path.join(HERE, f"oracle_{name}.json")
+    with open(path) as f:
+        out = json.load(f)
+    p = workload(name)
+    if out["input_sha256"] != input_sha256(p):
+        raise SystemExit("inputs differ from the ones the oracle ran on: rerun the oracle")
+    out["x0_sha256"] = x0_sha256(p)
+    out["samples"] = input_samples(p)
+    with open(path, "w") as f:
+        json.dump(out, f, indent=0)
+        f.write("\n")
+    print(f"updated {path}", flush=True)
+
+
 def main():
+    if sys.argv[1] == "--add-input-samples":
+        add_input_samples(sys.argv[2])
+        return
     name = sys.argv[1]
     t0 = time.perf_counter()
     p = workload(name)
@@ -100,6 +157,7 @@ def main():
         "n": p.n, "m0": p.m0, "ne": p.ne, "tol": p.tol, "hermitian": bool(p.hermitian),
         "emin": p.emin, "emax": p.emax, "meta": p.meta,
         "input_sha256": input_sha256(p),
+        "x0_sha256": x0_sha256(p), "samples": input_samples(p),
         "info": r.info, "M": r.M, "m0_out": r.m0, "loop": r.loop, "epsout": r.epsout,
         "E": [float(x) for x in r.E], "res": [float(x) for x in r.res],
         "sketch_cols": SKETCH_COLS, "sketch_seeds": list(SKETCH_SEEDS),
