@@ -139,6 +139,29 @@ int feast_solve_z_dev(int N, const feast_z *dA, int lda, const feast_z *dB, int 
                       double Emax, int *M0, const feast_opts *opts, double *E, feast_z *dX, int ldx,
                       int *M, double *res, int *loop, double *epsout, void *stream);
 
+/* ---- no-allocation form of feast_solve_d_dev, for callers that cannot
+ * allocate device memory during the call (code running under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  The same
+ * arguments, results and info codes as feast_solve_d_dev, but every device
+ * buffer of the solve comes from a static scratch array of
+ * FEASTX_NOALLOC_SCRATCH_BYTES on each device (held from the library's load
+ * until the process ends) and the call allocates nothing: no hipMalloc,
+ * hipFree, pinned host memory, stream or event.
+ *   Limit: a problem whose workspace (Ne factors and their solve form, solve
+ *   panels, subspace blocks) exceeds the scratch returns -1 at once with a
+ *   message on stderr, before any GPU work: with Ne = 8, N up to about 700 in
+ *   mixed precision and about 512 in FP64 for M0 of a few dozen.
+ *   Scratch contents persist between calls: the solve initialises every
+ *   buffer it reads.  Calls on one device share its scratch and take turns
+ *   (a lock per device); work the caller queues on `stream` after the call
+ *   may overlap nothing of it, because the call returns after the solve has
+ *   finished.  The stream may be NULL (the null stream).  The stage timers of
+ *   feast_stats stay 0. */
+#define FEASTX_NOALLOC_SCRATCH_BYTES (128ull << 20)
+int feast_solve_d_dev_noalloc(int N, const double *dA, int lda, const double *dB, int ldb, double Emin,
+                              double Emax, int *M0, const feast_opts *opts, double *E, double *dX, int ldx,
+                              int *M, double *res, int *loop, double *epsout, void *stream);
+
 /* ---- non-Hermitian FEAST (guide: the variant for non-Hermitian pencils,
  * with dual subspaces Q and Q-hat for the right and left eigenvectors, a full
  * contour around a two-dimensional search region, Table "tab_fpm" fpm(8),

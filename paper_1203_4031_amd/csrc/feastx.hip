@@ -74,8 +74,35 @@ struct Workspace {
     int device = -1;
     int num_cu = 0;
 
+    // Fixed-arena mode (the no-allocation entry point): get() carves the
+    // named buffers out of [arena, arena + arena_cap) in request order and
+    // pinned() out of a static host block, so neither allocates; the solve
+    // runs on the caller's stream with no stream or event of its own.
+    bool noalloc = false;
+    unsigned char *arena = nullptr, *host_arena = nullptr;
+    size_t arena_cap = 0, arena_used = 0, host_cap = 0, host_used = 0;
+    static void *carve(std::map<std::string, std::pair<void *, size_t>> &m, const std::string &name, size_t bytes,
+                       unsigned char *base, size_t cap, size_t &used)
+    {
+        auto it = m.find(name);
+        if (it != m.end() && it->second.second >= bytes) return it->second.first;
+        const size_t off = (used + 255) & ~size_t(255);
+        if (off > cap || bytes > cap - off) throw alloc_error{};
+        used = off + bytes;
+        m[name] = {base + off, bytes};
+        return base + off;
+    }
+    // forget the carved buffers (the start of every no-allocation call)
+    void reset_arena()
+    {
+        dev.clear();
+        host.clear();
+        arena_used = host_used = 0;
+    }
+
     void *get(const std::string &name, size_t bytes)
     {
+        if (noalloc) return carve(dev, name, bytes, arena, arena_cap, arena_used);
         auto &e = dev[name];
         if (e.second < bytes) {
             if (e.first) FX_CHECK(hipFree(e.first));
@@ -92,6 +119,7 @@ struct Workspace {
     }
     void *pinned(const std::string &name, size_t bytes)
     {
+        if (noalloc) return carve(host, name, bytes, host_arena, host_cap, host_used);
         auto &e = host[name];
         if (e.second < bytes) {
             if (e.first) FX_CHECK(hipHostFree(e.first));
@@ -107,7 +135,7 @@ struct Workspace {
     }
     void init()
     {
-        if (stream) return;
+        if (noalloc || stream) return;
         FX_CHECK(hipGetDevice(&device));
         FX_CHECK(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
         FX_CHECK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
@@ -167,6 +195,7 @@ struct Workspace {
     // free the device buffers
     void trim()
     {
+        if (noalloc) return;
         for (auto &kv : dev)
             if (kv.second.first) {
                 (void)hipFree(kv.second.first);
@@ -176,6 +205,10 @@ struct Workspace {
     }
     void release()
     {
+        if (noalloc) {
+            reset_arena();
+            return;
+        }
         for (auto &kv : dev)
             if (kv.second.first) (void)hipFree(kv.second.first);
         for (auto &kv : host)
@@ -313,17 +346,20 @@ static Contour custom_contour(const feast_z *zne, const feast_z *wne, int ne)
 // ------------------------------------------------------------ timing
 struct StageTimer {
     hipStream_t s;
+    bool on;   // off: no events at all (the no-allocation entry point)
     std::vector<std::pair<hipEvent_t, double *>> marks;
     hipEvent_t last = nullptr;
-    explicit StageTimer(hipStream_t st) : s(st) {}
+    StageTimer(hipStream_t st, bool enabled) : s(st), on(enabled) {}
     void start()
     {
+        if (!on) return;
         FX_CHECK(hipEventCreate(&last));
         FX_CHECK(hipEventRecord(last, s));
         marks.push_back({last, nullptr});
     }
     void mark(double *acc)
     {
+        if (!on) return;
         hipEvent_t e;
         FX_CHECK(hipEventCreate(&e));
         FX_CHECK(hipEventRecord(e, s));
@@ -487,6 +523,12 @@ static void device_eigh(Workspace &ws, hipStream_t s, int m, F64<CPLX> *C, F64<C
         }
         FX_LAUNCH_CHECK();
         FX_CHECK(hipMemcpyAsync(h_stop + sw, &jst->stop, sizeof(int), hipMemcpyDeviceToHost, s));
+        if (!ws.ev_j[0]) {
+            // no events (the no-allocation entry point): read each decision at once
+            FX_CHECK(hipStreamSynchronize(s));
+            if (h_stop[sw]) break;
+            continue;
+        }
         FX_CHECK(hipEventRecord(ws.ev_j[sw & 1], s));
         if (sw >= 2) {
             FX_CHECK(hipEventSynchronize(ws.ev_j[(sw - 1) & 1]));
@@ -630,7 +672,7 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
     const bool mixed = std::is_same<T, float>::value;
     const size_t nm = (size_t)n * m0, mm = (size_t)m0 * m0;
     feast_stats st{};
-    StageTimer tm(s);
+    StageTimer tm(s, !ws.noalloc);
     tm.start();
 
     Contour ct = o.Zne ? custom_contour(o.Zne, o.Wne, ne)
@@ -1089,7 +1131,7 @@ static int run_general(const GProblem &pb, const feast_opts &o, hipStream_t s, W
     const double alpha = std::hypot(pb.emid.x, pb.emid.y) + pb.r;
     const size_t nm = (size_t)n * m0, mm = (size_t)m0 * m0;
     feast_stats st{};
-    StageTimer tm(s);
+    StageTimer tm(s, !ws.noalloc);
     tm.start();
 
     Contour ct = make_full_contour(pb.emid, pb.r, ne, o.integration_full, o.ellipse, o.angle);
@@ -1429,8 +1471,8 @@ static int dispatch(bool cplx_in, const Problem &pb, const feast_opts &o, hipStr
     GemmTimer gt;
     try {
         ws.init();
-        if (!s) s = ws.stream;
-        g_gemm_timer = g_timing ? &gt : nullptr;
+        if (!s && !ws.noalloc) s = ws.stream;
+        g_gemm_timer = (g_timing && !ws.noalloc) ? &gt : nullptr;
         int info;
         if (o.precision == 1)
             info = cplx_in ? run<float, true>(pb, o, s, ws, out, st) : run<float, false>(pb, o, s, ws, out, st);
@@ -1558,6 +1600,22 @@ static double footprint_bytes(bool cplx, int n, int m0, const feast_opts &o, boo
     return b;
 }
 
+}  // namespace fx
+
+namespace fx {
+// Device scratch of the no-allocation entry point: one copy per device,
+// held until the process ends.  Host code never uses the name itself (a
+// host-side stand-in); it takes the device address from
+// hipGetSymbolAddress at each device's set-up.
+static __device__ __align__(256) unsigned char scratch[FEASTX_NOALLOC_SCRATCH_BYTES];
+constexpr int NOALLOC_MAX_DEVICES = 16;
+struct NoAllocDevice {
+    std::mutex mu;              // calls on one device take turns (they share its scratch)
+    void *ptr = nullptr;        // device address of this device's scratch
+    Workspace ws;               // fixed-arena workspace over it
+    alignas(256) unsigned char host[1 << 18];   // read-back staging (plain host memory)
+};
+static NoAllocDevice g_noalloc[NOALLOC_MAX_DEVICES];
 }  // namespace fx
 
 // Per-launch timing hook of the complex64 matrix product (feast_set_timing).
@@ -1877,6 +1935,74 @@ int feast_solve_z_dev(int N, const feast_z *dA, int lda, const feast_z *dB, int 
 {
     return solve_single(true, 1, N, dA, lda, dB, ldb, Emin, Emax, M0, opts, E, dX, ldx, M, res, loop, epsout,
                         stream);
+}
+
+// ---- the no-allocation variant of feast_solve_d_dev: every device buffer of
+// the solve is carved out of `scratch`, a static array on each device, and
+// host read-backs go through a static host block per device.
+static int solve_d_dev_noalloc(int N, const double *dA, int lda, const double *dB, int ldb, double Emin,
+                               double Emax, int *M0, const feast_opts *opts, double *E, double *dX, int ldx, int *M,
+                               double *res, int *loop, double *epsout, void *stream)
+{
+    if (!M0) return -108;
+    feast_opts o;
+    if (opts) o = *opts;
+    else feast_default_opts(&o);
+    int v = check_args(N, *M0, Emin, Emax, o, dA, lda, dB, ldb, dX, ldx, E, res, M);
+    if (v) return v;
+    const double need = fx::footprint_bytes(false, N, *M0, o, false);
+    if (need > (double)FEASTX_NOALLOC_SCRATCH_BYTES) {
+        std::fprintf(stderr,
+                     "feastx: feast_solve_d_dev_noalloc: N=%d, M0=%d, ne=%d needs about %.0f MiB of device "
+                     "workspace; its fixed scratch holds %llu MiB (use feast_solve_d_dev)\n",
+                     N, *M0, o.ne, need / (1 << 20), (unsigned long long)(FEASTX_NOALLOC_SCRATCH_BYTES >> 20));
+        return -1;
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= fx::NOALLOC_MAX_DEVICES) return -4;
+    fx::NoAllocDevice &d = fx::g_noalloc[dev];
+    std::lock_guard<std::mutex> lk(d.mu);
+    if (!d.ptr) {
+        // set-up on this device (current): the device address of its copy of
+        // the scratch array; the array's name is a host-side stand-in
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(fx::scratch));
+        if (e != hipSuccess || !p) {
+            std::fprintf(stderr, "feastx: hipGetSymbolAddress(scratch) failed on device %d: %s\n", dev,
+                         hipGetErrorString(e));
+            return -4;
+        }
+        d.ptr = p;
+        d.ws.noalloc = true;
+        d.ws.device = dev;
+        d.ws.arena = static_cast<unsigned char *>(p);
+        d.ws.arena_cap = FEASTX_NOALLOC_SCRATCH_BYTES;
+        d.ws.host_arena = d.host;
+        d.ws.host_cap = sizeof(d.host);
+    }
+    d.ws.reset_arena();
+    fx::SolveArgs a{false, N, dA, lda, dB, ldb, Emin, Emax, *M0, dX, ldx, E, res, 1,
+                    static_cast<hipStream_t>(stream)};
+    fx::SolveOut so;
+    fx::solve_in(d.ws, o, a, so);
+    fx::t_stats = so.st;
+    if (so.info == -1)
+        std::fprintf(stderr, "feastx: feast_solve_d_dev_noalloc: the fixed scratch (%llu MiB) ran out\n",
+                     (unsigned long long)(FEASTX_NOALLOC_SCRATCH_BYTES >> 20));
+    if (so.info == 0 || so.info == 1 || so.info == 2 || so.info == 3 || so.info == 4 || so.info == 5) {
+        *M = so.M;
+        *M0 = so.m0;
+        if (loop) *loop = so.loop;
+        if (epsout) *epsout = so.epsout;
+    }
+    return so.info;
+}
+
+int feast_solve_d_dev_noalloc(int N, const double *dA, int lda, const double *dB, int ldb, double Emin, double Emax,
+                              int *M0, const feast_opts *opts, double *E, double *dX, int ldx, int *M, double *res,
+                              int *loop, double *epsout, void *stream)
+{
+    return solve_d_dev_noalloc(N, dA, lda, dB, ldb, Emin, Emax, M0, opts, E, dX, ldx, M, res, loop, epsout, stream);
 }
 
 int feast_solve_d_ex(int N, const double *A, int lda, const double *B, int ldb, double Emin, double Emax, int *M0,

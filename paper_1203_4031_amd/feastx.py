@@ -87,7 +87,7 @@ def lib():
             f = getattr(L, name)
             f.argtypes = [C.c_int, vp, C.c_int, vp, C.c_int, C.c_double, C.c_double, ip, op, dp, vp,
                           C.c_int, ip, dp, ip, dp]
-        for name in ("feast_solve_d_dev", "feast_solve_z_dev"):
+        for name in ("feast_solve_d_dev", "feast_solve_z_dev", "feast_solve_d_dev_noalloc"):
             f = getattr(L, name)
             f.argtypes = [C.c_int, vp, C.c_int, vp, C.c_int, C.c_double, C.c_double, ip, op, dp, vp,
                           C.c_int, ip, dp, ip, dp, vp]
@@ -250,13 +250,15 @@ def _check_device_operands(A, B, X, xcols, dtypes):
             raise ValueError(f"{name} is on {t.device}, A on {A.device}")
 
 
-def solve_device(A, B, emin, emax, m0, X, stream=None, **kw) -> Result:
+def solve_device(A, B, emin, emax, m0, X, stream=None, noalloc=False, **kw) -> Result:
     """Device solve: A, B, X are column-major torch CUDA tensors (see
     fortran_tensor); X holds the start subspace if x0=True and receives the
-    eigenvectors.  Runs on `stream` (default: torch's current stream)."""
+    eigenvectors.  Runs on `stream` (default: torch's current stream).
+    noalloc=True calls feast_solve_d_dev_noalloc (real pencils only), whose
+    device workspace is the library's fixed scratch array."""
     import torch
 
-    _check_device_operands(A, B, X, m0, (torch.float64, torch.complex128))
+    _check_device_operands(A, B, X, m0, (torch.float64,) if noalloc else (torch.float64, torch.complex128))
     cplx = A.is_complex()
     n = A.shape[0]
     if stream is None:
@@ -268,7 +270,10 @@ def solve_device(A, B, emin, emax, m0, X, stream=None, **kw) -> Result:
     loop = C.c_int(0)
     eps = C.c_double(0)
     m0c = C.c_int(m0)
-    f = lib().feast_solve_z_dev if cplx else lib().feast_solve_d_dev
+    if noalloc:
+        f = lib().feast_solve_d_dev_noalloc
+    else:
+        f = lib().feast_solve_z_dev if cplx else lib().feast_solve_d_dev
     info = f(n, A.data_ptr(), A.stride(1), None if B is None else B.data_ptr(),
              n if B is None else B.stride(1), float(emin), float(emax), C.byref(m0c), C.byref(o),
              _dp(E), X.data_ptr(), X.stride(1), C.byref(M), _dp(res), C.byref(loop),
