@@ -106,6 +106,7 @@ typedef struct {
                                 LU itself (its trailing and panel-column updates) */
     double lu_update_flops;  /* algorithmic real flops of those launches */
     long long lu_update_launches;
+    int fp64_nodes;          /* mixed precision: contour nodes factored and solved in complex128 */
 } feast_stats;
 
 /* Defaults of the guide's feastinit (Table "tab_fpm"), with keep_factors = 1. */

@@ -242,6 +242,16 @@ static Workspace &thread_ws()
 static std::atomic<bool> g_timing{false};
 static const bool g_debug = std::getenv("FEASTX_DEBUG") != nullptr;
 static const bool g_no_lookahead = std::getenv("FEASTX_NO_LOOKAHEAD") != nullptr;   // tuning knob
+// Largest predicted per-loop contraction eta_j of a complex64 node
+// (fp64_nodes).  1e-3 keeps every node of the N = 4096 real pencil with
+// Ne = 8 in complex64 (largest eta about 5e-4) and moves the two end nodes of
+// the N = 8192 Hermitian pencil with Ne = 16 (eta about 1e-2) to complex128,
+// which takes that solve from 13 loops to 8.
+static double fp64_eta_max()
+{
+    const char *e = std::getenv("FEASTX_FP64_ETA");   // tuning knob
+    return e ? std::atof(e) : 1e-3;
+}
 
 // ------------------------------------------------------------ contour
 // Gauss-Legendre nodes on [-1, 1] by Newton iteration on P_n, evaluated with
@@ -660,6 +670,139 @@ static int bortho_eigen(Workspace &ws, hipStream_t s, int m0, F64<CPLX> *Bq, F64
 }
 
 
+// ---------------------------------------------------------------- node groups
+// The shifted matrices of a set of contour nodes in one factor precision
+// (complex<T>), with their solve form W, the inverted diagonal blocks and
+// the solve panels.  An FP64 solve has one group of all nodes.  A mixed
+// solve has a complex64 group and, for the nodes where complex64 error would
+// limit the outer iteration (fp64_nodes), a complex128 group.
+template <typename T, bool CPLX> struct NodeGroup {
+    using V = cplx<T>;
+    int n = 0, ne = 0;
+    std::vector<int> nodes;   // contour indices, in quadrature order
+    long ldf = 0, sF = 0, sI64 = 0, sInv = 0, sItmp = 0;
+    double2 *dz = nullptr;
+    V *F = nullptr, *L64 = nullptr, *U64 = nullptr, *Itmp = nullptr, *Wsv = nullptr, *Linv = nullptr,
+      *Uinv = nullptr, *Ytmp = nullptr, *Y = nullptr, *Yh = nullptr, *Yh2 = nullptr;
+    int *ipiv = nullptr, *perm = nullptr, *swapmap = nullptr, *dinfo = nullptr, *h_info = nullptr;
+
+    // buffers named with `tag` (distinct per group), the group's nodes uploaded on s
+    void setup(Workspace &ws, hipStream_t s, const std::string &tag, int n_, const std::vector<int> &nodes_,
+               const Contour &ct, size_t nm)
+    {
+        n = n_;
+        nodes = nodes_;
+        ne = (int)nodes.size();
+        if (ne == 0) return;
+        const std::string p = std::string(sizeof(T) == 4 ? "32" : "64") + tag;
+        ldf = n;
+        sF = (long)n * n;
+        std::vector<double2> zg(ne);
+        for (int j = 0; j < ne; ++j) zg[j] = ct.z[nodes[j]];
+        dz = static_cast<double2 *>(ws.get("z" + p, sizeof(double2) * ne));
+        FX_CHECK(hipMemcpyAsync(dz, zg.data(), sizeof(double2) * ne, hipMemcpyHostToDevice, s));
+        FX_CHECK(hipStreamSynchronize(s));   // zg goes out of scope
+        F = static_cast<V *>(ws.get("F" + p, sizeof(V) * (size_t)ne * sF));
+        ipiv = static_cast<int *>(ws.get("ipiv" + p, sizeof(int) * (size_t)ne * n));
+        perm = static_cast<int *>(ws.get("perm" + p, sizeof(int) * (size_t)ne * n));
+        swapmap = static_cast<int *>(ws.get("swapmap" + p, sizeof(int) * 2 * (size_t)ne * (1 + 4 * LU_NB)));
+        dinfo = static_cast<int *>(ws.get("info" + p, sizeof(int) * ne));
+        const bool compose = solve_nb<T>() > TRI_INV_NB;   // 128-row solve blocks from 64-row inverses
+        sI64 = compose ? tri_inv_stride(n) : 0;
+        sInv = solve_inv_stride<T>(n);
+        sItmp = compose ? (long)ceil_div(n, solve_nb<T>()) * 64 * 64 : 0;
+        L64 = compose ? static_cast<V *>(ws.get("L64inv" + p, sizeof(V) * (size_t)ne * sI64)) : nullptr;
+        U64 = compose ? static_cast<V *>(ws.get("U64inv" + p, sizeof(V) * (size_t)ne * sI64)) : nullptr;
+        Itmp = compose ? static_cast<V *>(ws.get("Invtmp" + p, sizeof(V) * (size_t)ne * sItmp)) : nullptr;
+        Wsv = static_cast<V *>(ws.get("Wsolve" + p, sizeof(V) * (size_t)ne * sF));
+        Linv = static_cast<V *>(ws.get("Linv" + p, sizeof(V) * (size_t)ne * sInv));
+        Uinv = static_cast<V *>(ws.get("Uinv" + p, sizeof(V) * (size_t)ne * sInv));
+        Ytmp = static_cast<V *>(ws.get("Yt" + p, sizeof(V) * (size_t)ne * nm));
+        Y = static_cast<V *>(ws.get("Y" + p, sizeof(V) * (size_t)ne * nm));
+        if (CPLX) {
+            Yh = static_cast<V *>(ws.get("Yh" + p, sizeof(V) * (size_t)ne * nm));
+            Yh2 = static_cast<V *>(ws.get("Yg" + p, sizeof(V) * (size_t)ne * nm));
+        }
+        h_info = static_cast<int *>(ws.pinned("h_info" + p, sizeof(int) * ne));
+    }
+
+    // shift, LU with partial pivoting, inverted diagonal blocks and W; throws
+    // solver_error{-2} on a zero or non-finite pivot
+    void factor(Workspace &ws, hipStream_t s, const Problem &pb, feast_stats &st)
+    {
+        if (ne == 0) return;
+        shift_build<T>(s, CPLX, n, pb.A, pb.lda, pb.B, pb.ldb, dz, ne, F, ldf, sF);
+        FX_CHECK(hipMemsetAsync(dinfo, 0, sizeof(int) * ne, s));
+        if (g_gemm_timer) g_gemm_timer->lu = true;
+        if (!g_no_lookahead && ws.lookahead && ws.split(ne)) {
+            FX_CHECK(hipEventRecord(ws.ev_c, s));
+            FX_CHECK(hipStreamWaitEvent(ws.fmain, ws.ev_c, 0));
+            getrf_batched<T>(ws.fmain, ws.fside, ws.ev_a, ws.ev_b, n, F, ldf, sF, ipiv, perm, n, swapmap, dinfo,
+                             ne);
+            FX_CHECK(hipEventRecord(ws.ev_d, ws.fmain));
+            FX_CHECK(hipStreamWaitEvent(s, ws.ev_d, 0));
+        } else {
+            getrf_batched<T>(s, (g_no_lookahead || !ws.lookahead) ? nullptr : ws.side, ws.ev_a, ws.ev_b, n, F, ldf,
+                             sF, ipiv, perm, n, swapmap, dinfo, ne);
+        }
+        if (g_gemm_timer) g_gemm_timer->lu = false;
+        solve_inverses<T>(s, n, F, ldf, sF, L64, U64, sI64, Linv, Uinv, sInv, Itmp, sItmp, ne);
+        build_w<T>(s, n, F, ldf, sF, Linv, Uinv, sInv, Wsv, ne);
+        FX_CHECK(hipMemcpyAsync(h_info, dinfo, sizeof(int) * ne, hipMemcpyDeviceToHost, s));
+        FX_CHECK(hipStreamSynchronize(s));
+        for (int j = 0; j < ne; ++j)
+            if (h_info[j] != 0) throw solver_error{-2};
+        st.factor_flops += ne * (8.0 / 3.0) * (double)n * n * n;
+    }
+
+    // Y_j = A_zj^{-1} R for the group's nodes; for Hermitian pencils also
+    // Yh2_j = A_zj^{-H} R (the same factors)
+    void solve(hipStream_t s, const double *R, int m0, feast_stats &st)
+    {
+        if (ne == 0) return;
+        const size_t cur_nm = (size_t)n * m0;
+        dim3 g((unsigned)((cur_nm + 255) / 256), ne);
+        hipLaunchKernelGGL((gather_rows_kernel<T, CPLX>), g, dim3(256), 0, s, n, m0, perm, (long)n, R, (long)n, Y,
+                           (long)n, (long)cur_nm);
+        FX_LAUNCH_CHECK();
+        getrs_batched<T>(s, false, n, m0, F, Wsv, ldf, sF, Linv, Uinv, sInv, Y, Ytmp, n, (long)cur_nm, ne);
+        if (CPLX) {
+            hipLaunchKernelGGL((copy_rhs_kernel<T, CPLX>), g, dim3(256), 0, s, n, m0, R, (long)n, Yh, (long)n,
+                               (long)cur_nm);
+            FX_LAUNCH_CHECK();
+            getrs_batched<T>(s, true, n, m0, F, Wsv, ldf, sF, Linv, Uinv, sInv, Yh, Ytmp, n, (long)cur_nm, ne);
+            hipLaunchKernelGGL((scatter_rows_kernel<T>), g, dim3(256), 0, s, n, m0, perm, (long)n, Yh, (long)n,
+                               (long)cur_nm, Yh2, (long)n, (long)cur_nm);
+            FX_LAUNCH_CHECK();
+        }
+        st.solve_flops += (CPLX ? 2.0 : 1.0) * ne * 8.0 * (double)n * n * m0;
+    }
+};
+
+// Contour nodes of a mixed-precision solve that are factored and solved in
+// complex128.  In the correction form, the complex64 backward error E_j of
+// the factors of z_j B - A (about u32 ||A_z||, u32 = 2^-24) reaches the next
+// subspace through w_j / (z_j - lambda) times (z_j B - A)^{-1} E_j (z_j B -
+// A)^{-1} R; for an unwanted direction near z_j each inverse amplifies by up
+// to 1 / Im(z_j) and R's components by up to (Emax - Emin) / Im(z_j), so the
+// unwanted components shrink each loop only by about
+//   eta_j = u32 (sA / sB + |z_j|) |w_j| (Emax - Emin) / Im(z_j)^3,
+// with sA, sB = ||A||_F, ||B||_F over sqrt(N) (scales of A and B).  Nodes
+// with eta_j above `eta_max` go to complex128; the others stay complex64.
+static std::vector<int> fp64_nodes(const Contour &ct, double sA, double sB, double emin, double emax,
+                                   double eta_max)
+{
+    std::vector<int> hi;
+    const double u32 = 5.9604644775390625e-08;
+    for (int j = 0; j < (int)ct.z.size(); ++j) {
+        const double im = std::fabs(ct.z[j].y);
+        const double zabs = std::hypot(ct.z[j].x, ct.z[j].y), wabs = std::hypot(ct.w[j].x, ct.w[j].y);
+        const double eta = im > 0 ? u32 * (sA / sB + zabs) * wabs * (emax - emin) / (im * im * im) : 1e300;
+        if (eta > eta_max) hi.push_back(j);
+    }
+    return hi;
+}
+
 template <typename T, bool CPLX>
 static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace &ws, Result &out,
                feast_stats &st_out)
@@ -677,8 +820,6 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
 
     Contour ct = o.Zne ? custom_contour(o.Zne, o.Wne, ne)
                        : make_contour(pb.emin, pb.emax, ne, o.integration, o.ellipse);
-    double2 *dz = static_cast<double2 *>(ws.get("z", sizeof(double2) * ne));
-    FX_CHECK(hipMemcpyAsync(dz, ct.z.data(), sizeof(double2) * ne, hipMemcpyHostToDevice, s));
 
     E *X = static_cast<E *>(ws.get("X", sizeof(E) * nm));
     E *R = static_cast<E *>(ws.get("R", sizeof(E) * nm));
@@ -701,32 +842,45 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
     double *rho = static_cast<double *>(ws.get("rho", sizeof(double) * m0));
     double2 *coef = static_cast<double2 *>(ws.get("coef", sizeof(double2) * ne * m0));
     int *sel = static_cast<int *>(ws.get("sel", sizeof(int) * m0));
-    const long ldf = n, sF = (long)n * n;
-    V *F = static_cast<V *>(ws.get(mixed ? "F32" : "F64", sizeof(V) * (size_t)ne * sF));
-    int *ipiv = static_cast<int *>(ws.get("ipiv", sizeof(int) * (size_t)ne * n));
-    int *perm = static_cast<int *>(ws.get("perm", sizeof(int) * (size_t)ne * n));
-    int *swapmap = static_cast<int *>(ws.get("swapmap", sizeof(int) * 2 * (size_t)ne * (1 + 4 * LU_NB)));
-    int *dinfo = static_cast<int *>(ws.get("info", sizeof(int) * ne));
-    const bool compose = solve_nb<T>() > TRI_INV_NB;   // 128-row solve blocks from 64-row inverses
-    const long sI64 = compose ? tri_inv_stride(n) : 0, sInv = solve_inv_stride<T>(n);
-    const long sItmp = compose ? (long)ceil_div(n, solve_nb<T>()) * 64 * 64 : 0;
-    V *L64 = compose ? static_cast<V *>(ws.get("L64inv", sizeof(V) * (size_t)ne * sI64)) : nullptr;
-    V *U64 = compose ? static_cast<V *>(ws.get("U64inv", sizeof(V) * (size_t)ne * sI64)) : nullptr;
-    V *Itmp = compose ? static_cast<V *>(ws.get("Invtmp", sizeof(V) * (size_t)ne * sItmp)) : nullptr;
-    V *Wsv = static_cast<V *>(ws.get(mixed ? "Wsolve32" : "Wsolve64", sizeof(V) * (size_t)ne * sF));
-    V *Linv = static_cast<V *>(ws.get(mixed ? "Linv32" : "Linv64", sizeof(V) * (size_t)ne * sInv));
-    V *Uinv = static_cast<V *>(ws.get(mixed ? "Uinv32" : "Uinv64", sizeof(V) * (size_t)ne * sInv));
-    V *Ytmp = static_cast<V *>(ws.get(mixed ? "Yt32" : "Yt64", sizeof(V) * (size_t)ne * nm));
-    V *Y = static_cast<V *>(ws.get(mixed ? "Y32" : "Y64", sizeof(V) * (size_t)ne * nm));
-    V *Yh = nullptr, *Yh2 = nullptr;
-    if (CPLX) {
-        Yh = static_cast<V *>(ws.get(mixed ? "Yh32" : "Yh64", sizeof(V) * (size_t)ne * nm));
-        Yh2 = static_cast<V *>(ws.get(mixed ? "Yg32" : "Yg64", sizeof(V) * (size_t)ne * nm));
+    // the contour's nodes in the factor precision T, except (mixed) those
+    // whose complex64 error would limit the outer iteration, in complex128
+    std::vector<int> lo_nodes, hi_nodes;
+    if (mixed && o.mode == 0) {
+        double *part = static_cast<double *>(ws.get("sumsq", sizeof(double) * 2 * SUMSQ_BLOCKS));
+        double *h_part = static_cast<double *>(ws.pinned("h_sumsq", sizeof(double) * 2 * SUMSQ_BLOCKS));
+        hipLaunchKernelGGL((sumsq_kernel<CPLX>), dim3(SUMSQ_BLOCKS), dim3(256), 0, s, n, pb.A, pb.lda, part);
+        if (pb.B)
+            hipLaunchKernelGGL((sumsq_kernel<CPLX>), dim3(SUMSQ_BLOCKS), dim3(256), 0, s, n, pb.B, pb.ldb,
+                               part + SUMSQ_BLOCKS);
+        FX_LAUNCH_CHECK();
+        FX_CHECK(hipMemcpyAsync(h_part, part, sizeof(double) * (pb.B ? 2 : 1) * SUMSQ_BLOCKS, hipMemcpyDeviceToHost,
+                                s));
+        FX_CHECK(hipStreamSynchronize(s));
+        double a2 = 0.0, b2 = 0.0;
+        for (int q = 0; q < SUMSQ_BLOCKS; ++q) {
+            a2 += h_part[q];
+            if (pb.B) b2 += h_part[SUMSQ_BLOCKS + q];
+        }
+        const double sA = std::sqrt(a2 / n), sB = pb.B ? std::sqrt(b2 / n) : 1.0;
+        hi_nodes = fp64_nodes(ct, sA, sB > 0 ? sB : 1.0, pb.emin, pb.emax, fp64_eta_max());
+        if (o.verbose) {
+            std::fprintf(stderr, "feastx: ||A||_F/sqrt(N) %.3e ||B||_F/sqrt(N) %.3e, complex128 nodes:", sA, sB);
+            for (int j : hi_nodes) std::fprintf(stderr, " %d", j);
+            std::fprintf(stderr, "\n");
+        }
     }
+    for (int j = 0; j < ne; ++j)
+        if (std::find(hi_nodes.begin(), hi_nodes.end(), j) == hi_nodes.end()) lo_nodes.push_back(j);
+    NodeGroup<T, CPLX> G0;
+    NodeGroup<double, CPLX> G1;
+    G0.setup(ws, s, "", n, lo_nodes, ct, nm);
+    G1.setup(ws, s, "h", n, hi_nodes, ct, nm);
+    st.fp64_nodes = mixed ? (int)hi_nodes.size() : 0;
+    double2 *coef1 = hi_nodes.empty() ? nullptr
+                                      : static_cast<double2 *>(ws.get("coef_h", sizeof(double2) * hi_nodes.size() * m0));
     double *h_beta = static_cast<double *>(ws.pinned("h_beta", sizeof(double) * m0));
     double *h_lam = static_cast<double *>(ws.pinned("h_lam", sizeof(double) * m0));
     double *h_res = static_cast<double *>(ws.pinned("h_res", sizeof(double) * m0));
-    int *h_info = static_cast<int *>(ws.pinned("h_info", sizeof(int) * ne));
 
     // start subspace
     if (o.x0) {
@@ -744,37 +898,17 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
     double prev_maxres = 1e300;     // largest residual in the interval at the previous loop
     double trace_prev = 0.0, epsout = 1.0;
     int info = 0, k = 0, M = 0;
-    std::vector<double2> hcoef((size_t)ne * m0);
+    std::vector<double2> hcoef((size_t)ne * m0), hcoef_g((size_t)ne * m0);
     std::vector<double> hrho(m0);
 
     for (k = 0; k <= o.maxloop; ++k) {
         const size_t cur_nm = (size_t)n * m0;
         // ---- factor every shifted matrix (once, fpm(10) = 1)
         if (k == 0 || !o.keep_factors) {
-            shift_build<T>(s, CPLX, n, pb.A, pb.lda, pb.B, pb.ldb, dz, ne, F, ldf, sF);
             tm.mark(&st.t_shift);
-            FX_CHECK(hipMemsetAsync(dinfo, 0, sizeof(int) * ne, s));
-            if (g_gemm_timer) g_gemm_timer->lu = true;
-            if (!g_no_lookahead && ws.lookahead && ws.split(ne)) {
-                FX_CHECK(hipEventRecord(ws.ev_c, s));
-                FX_CHECK(hipStreamWaitEvent(ws.fmain, ws.ev_c, 0));
-                getrf_batched<T>(ws.fmain, ws.fside, ws.ev_a, ws.ev_b, n, F, ldf, sF, ipiv, perm, n, swapmap,
-                                 dinfo, ne);
-                FX_CHECK(hipEventRecord(ws.ev_d, ws.fmain));
-                FX_CHECK(hipStreamWaitEvent(s, ws.ev_d, 0));
-            } else {
-                getrf_batched<T>(s, (g_no_lookahead || !ws.lookahead) ? nullptr : ws.side, ws.ev_a, ws.ev_b, n, F,
-                                 ldf, sF, ipiv, perm, n, swapmap, dinfo, ne);
-            }
-            if (g_gemm_timer) g_gemm_timer->lu = false;
-            solve_inverses<T>(s, n, F, ldf, sF, L64, U64, sI64, Linv, Uinv, sInv, Itmp, sItmp, ne);
-            build_w<T>(s, n, F, ldf, sF, Linv, Uinv, sInv, Wsv, ne);
+            G0.factor(ws, s, pb, st);
+            G1.factor(ws, s, pb, st);
             tm.mark(&st.t_factor);
-            FX_CHECK(hipMemcpyAsync(h_info, dinfo, sizeof(int) * ne, hipMemcpyDeviceToHost, s));
-            FX_CHECK(hipStreamSynchronize(s));
-            for (int j = 0; j < ne; ++j)
-                if (h_info[j] != 0) throw solver_error{-2};
-            st.factor_flops += ne * (8.0 / 3.0) * (double)n * n * n;
         }
         const bool corr = use_corr && k >= 1;
 
@@ -793,23 +927,8 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
         }
 
         // ---- solves at every node (and the adjoint solves for Hermitian pencils)
-        {
-            dim3 g((unsigned)((cur_nm + 255) / 256), ne);
-            hipLaunchKernelGGL((gather_rows_kernel<T, CPLX>), g, dim3(256), 0, s, n, m0, perm, (long)n,
-                               reinterpret_cast<const double *>(R), (long)n, Y, (long)n, (long)cur_nm);
-            FX_LAUNCH_CHECK();
-            getrs_batched<T>(s, false, n, m0, F, Wsv, ldf, sF, Linv, Uinv, sInv, Y, Ytmp, n, (long)cur_nm, ne);
-            if (CPLX) {
-                hipLaunchKernelGGL((copy_rhs_kernel<T, CPLX>), g, dim3(256), 0, s, n, m0,
-                                   reinterpret_cast<const double *>(R), (long)n, Yh, (long)n, (long)cur_nm);
-                FX_LAUNCH_CHECK();
-                getrs_batched<T>(s, true, n, m0, F, Wsv, ldf, sF, Linv, Uinv, sInv, Yh, Ytmp, n, (long)cur_nm, ne);
-                hipLaunchKernelGGL((scatter_rows_kernel<T>), g, dim3(256), 0, s, n, m0, perm, (long)n, Yh,
-                                   (long)n, (long)cur_nm, Yh2, (long)n, (long)cur_nm);
-                FX_LAUNCH_CHECK();
-            }
-            st.solve_flops += (CPLX ? 2.0 : 1.0) * ne * 8.0 * (double)n * n * m0;
-        }
+        G0.solve(s, reinterpret_cast<const double *>(R), m0, st);
+        G1.solve(s, reinterpret_cast<const double *>(R), m0, st);
         tm.mark(&st.t_solve);
 
         // ---- quadrature
@@ -830,10 +949,26 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
                 for (int j = 0; j < ne; ++j) r += hcoef[(size_t)j * m0 + c].x;
                 hrho[c] = r;
             }
-        FX_CHECK(hipMemcpyAsync(coef, hcoef.data(), sizeof(double2) * ne * m0, hipMemcpyHostToDevice, s));
+        // coefficients in each group's node order: complex64 (or FP64) group first
+        for (int g = 0; g < 2; ++g) {
+            const std::vector<int> &nodes = g == 0 ? lo_nodes : hi_nodes;
+            for (size_t q = 0; q < nodes.size(); ++q)
+                std::copy(hcoef.begin() + (size_t)nodes[q] * m0, hcoef.begin() + (size_t)(nodes[q] + 1) * m0,
+                          hcoef_g.begin() + (g == 0 ? 0 : lo_nodes.size() * m0) + q * m0);
+        }
+        FX_CHECK(hipMemcpyAsync(coef, hcoef_g.data(), sizeof(double2) * lo_nodes.size() * m0,
+                                hipMemcpyHostToDevice, s));
+        if (coef1)
+            FX_CHECK(hipMemcpyAsync(coef1, hcoef_g.data() + lo_nodes.size() * m0,
+                                    sizeof(double2) * hi_nodes.size() * m0, hipMemcpyHostToDevice, s));
         if (corr) FX_CHECK(hipMemcpyAsync(rho, hrho.data(), sizeof(double) * m0, hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL((accumulate_kernel<T, CPLX>), grid1(cur_nm), dim3(256), 0, s, n, m0, ne, Y, (long)n,
-                           (long)cur_nm, Yh2, coef, corr ? rho : nullptr, X, (long)n, Q, (long)n);
+        // Q = sum over the nodes (then X diag(rho) in the correction form), the
+        // complex128 group added last
+        hipLaunchKernelGGL((accumulate_kernel<T, CPLX>), grid1(cur_nm), dim3(256), 0, s, n, m0, G0.ne, G0.Y,
+                           (long)n, (long)cur_nm, G0.Yh2, coef, corr ? rho : nullptr, X, (long)n, Q, (long)n, 0);
+        if (G1.ne)
+            hipLaunchKernelGGL((accumulate_kernel<double, CPLX>), grid1(cur_nm), dim3(256), 0, s, n, m0, G1.ne, G1.Y,
+                               (long)n, (long)cur_nm, G1.Yh2, coef1, nullptr, X, (long)n, Q, (long)n, 1);
         FX_LAUNCH_CHECK();
         FX_CHECK(hipStreamSynchronize(s));   // host vectors above are reused next loop
         tm.mark(&st.t_accum);
@@ -1597,6 +1732,8 @@ static double footprint_bytes(bool cplx, int n, int m0, const feast_opts &o, boo
     b += o.ne * (double)n * 448.0 * vb;                   // inverted diagonal blocks (64 and 128 wide)
     b += 7.0 * nm * eb + 16.0 * mm * eb;                  // subspace blocks, reduced problem
     if (staged) b += 2.0 * nn * eb + nm * eb;             // copies of A, B, X
+    if (o.precision == 1)                                 // up to two nodes in complex128 (fp64_nodes)
+        b += 2.0 * (2.0 * nn * 16.0 + (double)n * 448.0 * 16.0 + nm * 16.0 * (cplx ? 4.0 : 2.0));
     return b;
 }
 

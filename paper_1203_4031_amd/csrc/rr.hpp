@@ -23,7 +23,7 @@ __global__ __launch_bounds__(256) void accumulate_kernel(int n, int ncols, int n
                                                          const double *__restrict__ rho,
                                                          const typename jelem<CPLX>::type *__restrict__ X,
                                                          long ldx, typename jelem<CPLX>::type *__restrict__ Q,
-                                                         long ldq)
+                                                         long ldq, int add)
 {
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long)n * ncols) return;
@@ -48,7 +48,38 @@ __global__ __launch_bounds__(256) void accumulate_kernel(int n, int ncols, int n
         qr += rho[c] * x.x;
         qi += rho[c] * x.y;
     }
+    if (add) {   // a second node group: Q += its sum
+        const double2 q0 = jload<CPLX>(Q, i + (long)c * ldq);
+        qr = q0.x + qr;
+        qi = q0.y + qi;
+    }
     jstore<CPLX>(Q, i + (long)c * ldq, make_double2(qr, qi));
+}
+
+// Per-block sums of |a_ij|^2 over an n x n matrix (SUMSQ_BLOCKS blocks,
+// summed on the host in block order).
+constexpr int SUMSQ_BLOCKS = 256;
+template <bool CPLX>
+__global__ __launch_bounds__(256) void sumsq_kernel(int n, const double *__restrict__ A, long lda,
+                                                    double *__restrict__ part)
+{
+    __shared__ double red[4];
+    double acc = 0.0;
+    const long nn = (long)n * n;
+    for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < nn; e += (long)gridDim.x * 256) {
+        const long i = e % n, j = e / n;
+        if constexpr (CPLX) {
+            const double2 a = reinterpret_cast<const double2 *>(A)[i + j * lda];
+            acc += a.x * a.x + a.y * a.y;
+        } else {
+            const double a = A[i + j * lda];
+            acc += a * a;
+        }
+    }
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
 // R = AX - BX diag(lambda)   (residual of the current Ritz pairs, FP64)

@@ -39,7 +39,8 @@ class feast_stats(C.Structure):
                 ("lu_gemm_flops", C.c_double), ("lu_gemm_launches", C.c_longlong),
                 ("factor_flops", C.c_double), ("solve_flops", C.c_double), ("loops", C.c_int),
                 ("m0_final", C.c_int), ("eig_calls", C.c_int), ("eig_sweeps", C.c_int),
-                ("t_lu_update", C.c_double), ("lu_update_flops", C.c_double), ("lu_update_launches", C.c_longlong)]
+                ("t_lu_update", C.c_double), ("lu_update_flops", C.c_double), ("lu_update_launches", C.c_longlong),
+                ("fp64_nodes", C.c_int)]
 
 
 class feast_job(C.Structure):

@@ -30,6 +30,10 @@ __all__ = [
     "dense_real_generalized",
     "dense_complex_hermitian",
     "batched_real_generalized",
+    "batched_specs",
+    "batched_problem",
+    "serving_pool_matrix",
+    "serving_requests",
     "start_subspace",
     "pick_interval",
 ]
@@ -253,19 +257,69 @@ def dense_complex_hermitian(n: int = 8192, count: int = 400, m0: int | None = No
                    {"seed": seed, "x0_seed": x0_seed, "count": count})
 
 
-def batched_real_generalized(nprob: int = 256, nmin: int = 256, nmax: int = 2048,
-                             ne: int = 8, tol: float = 1e-10, seed: int = 4000) -> list[Problem]:
-    """Many independent real symmetric generalized problems of uneven size:
-    N log-uniform on [nmin, nmax], each interval holding a fraction
-    f ~ U[0.05, 0.15] of its spectrum, M0 = ceil(1.5 count)."""
+def batched_specs(nprob: int = 256, nmin: int = 256, nmax: int = 2048, seed: int = 4000):
+    """Sizes and seeds of the batched problems, in order: (n, count, seed, x0_seed)
+    with N log-uniform on [nmin, nmax] and count = round(f N), f ~ U[0.05, 0.15]."""
     meta_rng = _rng(seed)
     out = []
     for i in range(nprob):
         n = int(round(math.exp(meta_rng.uniform(math.log(nmin), math.log(nmax)))))
         f = meta_rng.uniform(0.05, 0.15)
         count = max(1, int(round(f * n)))
-        out.append(dense_real_generalized(n, count, ne=ne, tol=tol, seed=seed + 1 + i,
-                                          x0_seed=seed + 100000 + i))
+        out.append((n, count, seed + 1 + i, seed + 100000 + i))
+    return out
+
+
+def batched_problem(spec, ne: int = 8, tol: float = 1e-10) -> Problem:
+    """One problem of batched_specs, built as the dense real generalized case."""
+    n, count, s, x0s = spec
+    return dense_real_generalized(n, count, ne=ne, tol=tol, seed=s, x0_seed=x0s)
+
+
+def batched_real_generalized(nprob: int = 256, nmin: int = 256, nmax: int = 2048,
+                             ne: int = 8, tol: float = 1e-10, seed: int = 4000) -> list[Problem]:
+    """Many independent real symmetric generalized problems of uneven size:
+    N log-uniform on [nmin, nmax], each interval holding a fraction
+    f ~ U[0.05, 0.15] of its spectrum, M0 = ceil(1.5 count)."""
+    return [batched_problem(sp, ne=ne, tol=tol) for sp in batched_specs(nprob, nmin, nmax, seed)]
+
+
+SERVING_SIZES = (512, 1024, 2048, 4096, 8192)
+
+
+def serving_pool_matrix(n: int, k: int, seed: int = 5000):
+    """Pool matrix k of size n for the request stream: a pencil built as the
+    dense complex Hermitian case (seed + 100 * log2(n) + k).  Returns
+    (A, B, sorted spectrum)."""
+    p = dense_complex_hermitian(n, min(50, n // 8), seed=seed + 100 * int(round(math.log2(n))) + k)
+    return p.A, p.B, p.spectrum
+
+
+def serving_requests(spectra: dict, nreq: int, per_size: int, seed: int = 5000, rate: float = 200.0,
+                     sizes=SERVING_SIZES, ne: int = 8, tol: float = 1e-10):
+    """The request stream: Poisson arrivals at `rate` per second; N drawn with
+    p(N) proportional to N^-2; a pool matrix k uniform in [0, per_size); the
+    interval holds count ~ U{50..300} eigenvalues (at most N/4) around a
+    uniformly drawn position of the spectrum (pick_interval); M0 = ceil(1.5
+    count).  `spectra[(n, k)]` holds the pool matrices' sorted spectra.
+    Returns dicts with t (arrival, seconds from the first), n, k, emin, emax,
+    count, m0, ne, tol and x0_seed."""
+    rng = _rng(seed + 7)
+    w = np.array([1.0 / (n * n) for n in sizes])
+    w /= w.sum()
+    t, out = 0.0, []
+    for i in range(nreq):
+        if i:
+            t += rng.exponential(1.0 / rate)
+        n = int(sizes[rng.choice(len(sizes), p=w)])
+        k = int(rng.integers(0, per_size))
+        count = min(int(rng.integers(50, 301)), n // 4)
+        spec = spectra[(n, k)]
+        half = count // 2 + max(1, int(round(0.05 * count))) + 1
+        centre = int(rng.integers(half, n - half))
+        emin, emax, _ = pick_interval(spec, count, centre)
+        out.append({"t": t, "n": n, "k": k, "emin": emin, "emax": emax, "count": count,
+                    "m0": int(math.ceil(1.5 * count)), "ne": ne, "tol": tol, "x0_seed": seed + 10000 + i})
     return out
 
 

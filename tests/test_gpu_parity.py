@@ -165,3 +165,20 @@ def test_spurious_pairs_in_a_spectral_gap(orc, precision):
             assert r.M == 0 and (r.res[ins] == -1.0).all()
         else:
             assert (r.res[ins] > 0.1).all()
+
+
+@pytest.mark.parametrize("eta", ["1e-9", "1e-4"])
+def test_mixed_with_complex128_nodes_matches_oracle(small_cases, monkeypatch, eta):
+    """Mixed precision with some contour nodes factored and solved in
+    complex128 (the library's FEASTX_FP64_ETA threshold lowered so that
+    most, or only the end, nodes qualify): the two node groups' solves are
+    summed into one quadrature, which must give the oracle's eigenpairs."""
+    p, ref = small_cases[3]
+    monkeypatch.setenv("FEASTX_FP64_ETA", eta)
+    print(f"case {p.name} mixed with FP64 nodes (eta {eta})", flush=True)
+    r = feastx.solve(p.A, p.B, p.emin, p.emax, p.m0, X0=p.X0, ne=p.ne, tol=p.tol, precision="mixed")
+    st = feastx.stats()
+    assert 0 < st.fp64_nodes <= p.ne, st.fp64_nodes
+    if eta == "1e-9":
+        assert st.fp64_nodes == p.ne
+    _check_pairs(p, r, ref)
