@@ -1884,7 +1884,8 @@ class Executor {
             solve_in(ws, j->opts, j->args, j->out);
             j->t_end = std::chrono::steady_clock::now();
             // keep a slot's workspace near the size of what it runs
-            if (ws.bytes() > 2.0 * j->footprint + 512.0 * (1 << 20)) ws.trim();
+            // (a freed buffer synchronises the device, so only a large excess is given back)
+            if (ws.bytes() > 2.0 * j->footprint + 4096.0 * (1 << 20)) ws.trim();
             {
                 std::lock_guard<std::mutex> lk(mu_);
                 in_use_ -= j->footprint;

@@ -295,10 +295,11 @@ def serving_pool_matrix(n: int, k: int, seed: int = 5000):
     return p.A, p.B, p.spectrum
 
 
-def serving_requests(spectra: dict, nreq: int, per_size: int, seed: int = 5000, rate: float = 200.0,
+def serving_requests(spectra: dict, nreq: int, per_size, seed: int = 5000, rate: float = 200.0,
                      sizes=SERVING_SIZES, ne: int = 8, tol: float = 1e-10):
     """The request stream: Poisson arrivals at `rate` per second; N drawn with
-    p(N) proportional to N^-2; a pool matrix k uniform in [0, per_size); the
+    p(N) proportional to N^-2; a pool matrix k uniform in [0, per_size) (an
+    int, or a dict of counts per N); the
     interval holds count ~ U{50..300} eigenvalues (at most N/4) around a
     uniformly drawn position of the spectrum (pick_interval); M0 = ceil(1.5
     count).  `spectra[(n, k)]` holds the pool matrices' sorted spectra.
@@ -312,12 +313,18 @@ def serving_requests(spectra: dict, nreq: int, per_size: int, seed: int = 5000, 
         if i:
             t += rng.exponential(1.0 / rate)
         n = int(sizes[rng.choice(len(sizes), p=w)])
-        k = int(rng.integers(0, per_size))
+        k = int(rng.integers(0, per_size[n] if isinstance(per_size, dict) else per_size))
         count = min(int(rng.integers(50, 301)), n // 4)
         spec = spectra[(n, k)]
         half = count // 2 + max(1, int(round(0.05 * count))) + 1
-        centre = int(rng.integers(half, n - half))
-        emin, emax, _ = pick_interval(spec, count, centre)
+        # the interval's end gaps at least a fifth of the median gap (no end
+        # inside a cluster), redrawing the position otherwise
+        gmed = float(np.median(np.diff(spec)))
+        for _ in range(100):
+            centre = int(rng.integers(half, n - half))
+            emin, emax, lo = pick_interval(spec, count, centre)
+            if min(spec[lo] - spec[lo - 1], spec[lo + count] - spec[lo + count - 1]) >= 0.2 * gmed:
+                break
         out.append({"t": t, "n": n, "k": k, "emin": emin, "emax": emax, "count": count,
                     "m0": int(math.ceil(1.5 * count)), "ne": ne, "tol": tol, "x0_seed": seed + 10000 + i})
     return out
