@@ -52,9 +52,9 @@ PEAK_FP64_MFMA = 78.6
 # kernel itself and every file that launches it (the FP64 reduced-problem
 # kernels in jacobi.hpp and bortho.hpp do not): `traffic` is null when they
 # differ.
-TRAFFIC = {
-    "hermgen_n8192": (None, ""),
-    "realgen_n4096": (None, ""),
+TRAFFIC = {   # profiles/hbm_traffic_hermgen_n8192_m0600.md, profiles/hbm_traffic_realgen_n4096_m0300.md
+    "hermgen_n8192": (3.414e+08, "dfbdfd70c84e4dea329fc24293641eb9325a2fe4eed2a67f200c26611f6ee5f1"),
+    "realgen_n4096": (1.196e+08, "dfbdfd70c84e4dea329fc24293641eb9325a2fe4eed2a67f200c26611f6ee5f1"),
 }
 
 
@@ -231,7 +231,8 @@ def measure_single(feastx, torch, p, steps, fp64_steps, warmup, roofline_steps, 
                                "matrix product on the FP32 matrix cores (LU trailing updates and "
                                "triangular-solve updates), every launch of the timed solves; products of at "
                                "most 32 columns use its 64x32 instance gemm_kernel<float, true, false, 64, 32, "
-                               "16, 32, 16, 4, true, true>, counted here too",
+                               "16, 32, 16, 4, true, true> and the adjoint solves of Hermitian pencils its "
+                               "A^H instance gemm_kernel<float, true, true, ...>, all counted here",
                      "bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA,
                      "traffic": (traffic_bytes if traffic_bytes and kernel_sources_sha256() == traffic_sha

@@ -1,7 +1,7 @@
 """Write the oracle's results on the full-size workloads as text fixtures.
 
     python tests/golden/make_oracle_fixtures.py realgen_n4096     # about 3 min on 8 cores
-    python tests/golden/make_oracle_fixtures.py hermgen_n8192     # about 1 h on 8 cores
+    python tests/golden/make_oracle_fixtures.py hermgen_n8192     # about 2.5 h on 6 cores
     python tests/golden/make_oracle_fixtures.py --add-input-samples realgen_n4096
 
 Calls only the FP64 CPU oracle (oracle/) on inputs from the seeded generators

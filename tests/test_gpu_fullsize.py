@@ -2,11 +2,11 @@
 generalized pencil, N = 4096, M0 = 300, Ne = 8, tol 1e-10, inputs resident in
 HBM, the same `feast_solve_d_dev` call and options as bench.py).
 
-The FP64 oracle's own run on this workload is stored in
-tests/golden/oracle_realgen_n4096.json (written by
-tests/golden/make_oracle_fixtures.py, which calls only the oracle): both
-precisions are compared with it element by element (eigenvalues) and through
-a sketch of the interval's eigenprojector.  The other checks are properties
+The FP64 oracle's own runs on this workload and on the N = 8192 complex
+Hermitian one are stored in tests/golden/oracle_{realgen_n4096,
+hermgen_n8192}.json (written by tests/golden/make_oracle_fixtures.py, which
+calls only the oracle): both precisions are compared with them element by
+element (eigenvalues) and through a sketch of the interval's eigenprojector.  The other checks are properties
 that hold at any size (guide: Table "tab_common" for E, X, res and M; Table
 "tab_info"):
 
@@ -101,27 +101,25 @@ def _fixture(name):
         return json.load(f)
 
 
-@pytest.mark.parametrize("prec", ["mixed", "fp64"])
-def test_matches_stored_oracle_run(bench_problem, solved, prec):
-    """Parity with the oracle at full size (reading R14).  Eigenvalues: the
-    1e-10 relative bar, element by element.  Eigenvectors: the sketch
-    K = S2^T X_M X_M^H B S of the interval's B-orthogonal eigenprojector, with
-    S, S2 seeded N x 16 blocks, does not depend on phases or rotations inside
-    clusters.  Its relative difference is bounded by the projectors'
-    distance, which the Davis-Kahan bound ||R|| / gap puts near 1e-7 at
-    residuals below 1e-10 and end gaps of about 2e-4; 1e-6 is the bar."""
+def _compare_with_oracle_run(p, name, r, X):
+    """Parity with the oracle's stored run on the same workload (reading
+    R14).  Eigenvalues: the 1e-10 relative bar, element by element.
+    Eigenvectors: the sketch K = S2^T X_M X_M^H B S of the interval's
+    B-orthogonal eigenprojector, with S, S2 seeded N x 16 blocks, does not
+    depend on phases or rotations inside clusters.  Its relative difference
+    is bounded by the projectors' distance, which the Davis-Kahan bound
+    ||R|| / gap puts near 1e-7 at residuals below 1e-10 and end gaps of about
+    2e-4; 1e-6 is the bar."""
     import sys
     import os
 
     sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
     import make_oracle_fixtures as F
 
-    p = bench_problem
-    ref = _fixture("realgen_n4096")
+    ref = _fixture(name)
     assert F.inputs_match(p, ref), "generator output differs from the oracle's inputs beyond rounding"
     assert abs(p.emin - ref["emin"]) <= 1e-12 and abs(p.emax - ref["emax"]) <= 1e-12
     assert ref["info"] == 0
-    r, X = solved[prec]
     assert r.info == 0 and r.M == ref["M"]
     alpha = max(abs(p.emin), abs(p.emax))
     e_ref = np.array(ref["E"][:ref["M"]])
@@ -133,6 +131,12 @@ def test_matches_stored_oracle_run(bench_problem, solved, prec):
     K_ref = np.array(ref["sketch_re"]) + 1j * np.array(ref["sketch_im"])
     rel = np.linalg.norm(K - K_ref) / np.linalg.norm(K_ref)
     assert rel <= 1e-6, rel
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_matches_stored_oracle_run(bench_problem, solved, prec):
+    r, X = solved[prec]
+    _compare_with_oracle_run(bench_problem, "realgen_n4096", r, X)
 
 
 def test_mixed_matches_fp64(bench_problem, solved):
@@ -202,8 +206,10 @@ def test_complex_hermitian_config_n8192():
 
     p = W.dense_complex_hermitian(8192, 400, m0=600, ne=16, tol=1e-10)
     for prec in ("mixed", "fp64"):
+        print(f"N=8192 complex Hermitian, {prec}", flush=True)
         r, X = _solve_hermitian(p, prec)
         _check_hermitian(p, r, X)
+        _compare_with_oracle_run(p, "hermgen_n8192", r, X)
 
 
 # ---------------------------------------------------------------------------
