@@ -394,13 +394,16 @@ struct StageTimer {
     }
 };
 
-// Per-launch timing of the complex64 products (enabled by feast_set_timing);
-// those issued by the shifted LU itself are also summed apart.
+// Per-launch timing of the complex products in the factor precision of the
+// solve (complex64 for mixed, complex128 for FP64; enabled by
+// feast_set_timing); those issued by the shifted LU itself are also summed
+// apart.
 struct GemmTimer {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
     std::vector<char> in_lu;
     double flops = 0, lu_flops = 0;
-    bool lu = false;   // launches being recorded belong to getrf_batched
+    bool lu = false;    // launches being recorded belong to getrf_batched
+    bool f64 = false;   // record the complex128 products (else complex64)
 };
 static thread_local GemmTimer *g_gemm_timer = nullptr;
 void gemm_timing_reset();
@@ -584,7 +587,7 @@ static int bortho_cholesky(Workspace &ws, hipStream_t s, int m, F64<CPLX> *Bq, F
     int *kidx = static_cast<int *>(ws.get("bo_kidx", sizeof(int) * m));
     int *keepf = static_cast<int *>(ws.get("bo_keep", sizeof(int) * m));
     E *Bt = static_cast<E *>(ws.get("bo_bt", sizeof(E) * mm));
-    E *L = static_cast<E *>(ws.get("bo_l", sizeof(E) * mm));
+    E *Pc = static_cast<E *>(ws.get("bo_p", sizeof(E) * (size_t)CHP_NB * m));
     E *Lk = static_cast<E *>(ws.get("bo_lk", sizeof(E) * mm));
     E *Ti = static_cast<E *>(ws.get("bo_ti", sizeof(E) * mm));
     E *Xi = static_cast<E *>(ws.get("bo_xi", sizeof(E) * mm));
@@ -607,14 +610,8 @@ static int bortho_cholesky(Workspace &ws, hipStream_t s, int m, F64<CPLX> *Bq, F
     FX_CHECK(hipMemcpyAsync(ord, order.data(), sizeof(int) * m, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL((sym_scale_kernel<CPLX>), grid1((long)mm), dim3(256), 0, s, m, Bq, (long)m, d, ord, Bt, (long)m);
     FX_LAUNCH_CHECK();
-    // one row per thread: a 512-thread launch up to m = 512 (wider column blocks fit its registers)
-    if (m <= 512)
-        hipLaunchKernelGGL((chol_drop_kernel<CPLX, 512>), dim3(1), dim3(512), 0, s, m, Bt, (long)m, L, (long)m, keepf,
-                           CHOL_DROP, INDEFINITE, status);
-    else
-        hipLaunchKernelGGL((chol_drop_kernel<CPLX, CHOL_MAXM>), dim3(1), dim3(CHOL_MAXM), 0, s, m, Bt, (long)m, L,
-                           (long)m, keepf, CHOL_DROP, INDEFINITE, status);
-    FX_LAUNCH_CHECK();
+    // blocked Cholesky in place on Bt: afterwards Bt's lower triangle is L
+    chol_drop_blocked<CPLX>(s, m, Bt, (long)m, Pc, keepf, CHOL_DROP, INDEFINITE, status);
     FX_CHECK(hipMemcpyAsync(h_i, status, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
     FX_CHECK(hipMemcpyAsync(h_i + 4, keepf, sizeof(int) * m, hipMemcpyDeviceToHost, s));
     FX_CHECK(hipStreamSynchronize(s));
@@ -633,8 +630,9 @@ static int bortho_cholesky(Workspace &ws, hipStream_t s, int m, F64<CPLX> *Bq, F
         }
     FX_CHECK(hipMemcpyAsync(kidx, h_kidx, sizeof(int) * r, hipMemcpyHostToDevice, s));
     FX_CHECK(hipMemcpyAsync(row_of, h_rowof, sizeof(int) * m, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL((gather_kk_kernel<CPLX>), grid1((long)r * r), dim3(256), 0, s, r, kidx, L, (long)m, Lk, (long)r);
-    hipLaunchKernelGGL((lower_block_inv_kernel<CPLX>), dim3(ceil_div(r, TRI_NB)), dim3(TRI_NB), 0, s, r, Lk, (long)r,
+    hipLaunchKernelGGL((gather_kk_kernel<CPLX>), grid1((long)r * r), dim3(256), 0, s, r, kidx, Bt, (long)m, Lk,
+                       (long)r);
+    hipLaunchKernelGGL((lower_block_inv_kernel<CPLX>), dim3(ceil_div(r, TRI_NB)), dim3(TRI_NT), 0, s, r, Lk, (long)r,
                        Dinv);
     hipLaunchKernelGGL((set_identity_kernel<CPLX>), grid1((long)r * r), dim3(256), 0, s, r, Xi, (long)r);
     FX_LAUNCH_CHECK();
@@ -1604,6 +1602,7 @@ static int dispatch(bool cplx_in, const Problem &pb, const feast_opts &o, hipStr
                     Result &out, feast_stats &st)
 {
     GemmTimer gt;
+    gt.f64 = o.precision != 1;
     try {
         ws.init();
         if (!s && !ws.noalloc) s = ws.stream;
@@ -1678,6 +1677,50 @@ static void copy_outputs(const Result &out, int info, const SolveArgs &a, SolveO
     }
 }
 
+// Copies of column blocks between pageable host memory (leading dimension
+// spitch / dpitch bytes) and a packed device buffer.  A pageable 2D copy
+// moves one column per transfer, so a contiguous block goes in one copy and a
+// strided one through a packed host buffer, up to 64 MiB at a time.  Both
+// return when the data has landed.
+static void upload_cols(void *dst, const void *src, size_t spitch, size_t rowbytes, long ncols)
+{
+    if (ncols <= 0 || rowbytes == 0) return;
+    if (spitch == rowbytes) {
+        FX_CHECK(hipMemcpy(dst, src, rowbytes * (size_t)ncols, hipMemcpyHostToDevice));
+        return;
+    }
+    const long per = std::max<long>(1, (long)((64ull << 20) / rowbytes));
+    std::vector<unsigned char> tmp(rowbytes * (size_t)std::min(per, ncols));
+    for (long j0 = 0; j0 < ncols; j0 += per) {
+        const long nc = std::min(per, ncols - j0);
+        for (long j = 0; j < nc; ++j)
+            std::memcpy(tmp.data() + j * rowbytes, static_cast<const unsigned char *>(src) + (j0 + j) * spitch,
+                        rowbytes);
+        FX_CHECK(hipMemcpy(static_cast<unsigned char *>(dst) + j0 * rowbytes, tmp.data(), nc * rowbytes,
+                           hipMemcpyHostToDevice));
+    }
+}
+
+// The reverse, after the work queued on stream s has finished.
+static void download_cols(void *dst, size_t dpitch, const void *src, size_t rowbytes, long ncols, hipStream_t s)
+{
+    FX_CHECK(hipStreamSynchronize(s));
+    if (ncols <= 0 || rowbytes == 0) return;
+    if (dpitch == rowbytes) {
+        FX_CHECK(hipMemcpy(dst, src, rowbytes * (size_t)ncols, hipMemcpyDeviceToHost));
+        return;
+    }
+    const long per = std::max<long>(1, (long)((64ull << 20) / rowbytes));
+    std::vector<unsigned char> tmp(rowbytes * (size_t)std::min(per, ncols));
+    for (long j0 = 0; j0 < ncols; j0 += per) {
+        const long nc = std::min(per, ncols - j0);
+        FX_CHECK(hipMemcpy(tmp.data(), static_cast<const unsigned char *>(src) + j0 * rowbytes, nc * rowbytes,
+                           hipMemcpyDeviceToHost));
+        for (long j = 0; j < nc; ++j)
+            std::memcpy(static_cast<unsigned char *>(dst) + (j0 + j) * dpitch, tmp.data() + j * rowbytes, rowbytes);
+    }
+}
+
 static void solve_in(Workspace &ws, const feast_opts &o, const SolveArgs &a, SolveOut &so)
 {
     Result out;
@@ -1700,16 +1743,15 @@ static void solve_in(Workspace &ws, const feast_opts &o, const SolveArgs &a, Sol
         // blocking uploads: each has landed before any kernel of the solve is
         // launched (an asynchronous copy from pageable memory was seen to be
         // overtaken by the stream's kernels under a profiler)
-        FX_CHECK(hipMemcpy2D(dA, es * N, a.A, es * a.lda, es * N, N, hipMemcpyHostToDevice));
-        if (a.B) FX_CHECK(hipMemcpy2D(dB, es * N, a.B, es * a.ldb, es * N, N, hipMemcpyHostToDevice));
-        if (o.x0) FX_CHECK(hipMemcpy2D(dX, es * N, a.X, es * a.ldx, es * N, a.m0, hipMemcpyHostToDevice));
+        upload_cols(dA, a.A, es * a.lda, es * N, N);
+        if (a.B) upload_cols(dB, a.B, es * a.ldb, es * N, N);
+        if (o.x0) upload_cols(dX, a.X, es * a.ldx, es * N, a.m0);
         Problem pb{N, static_cast<const double *>(dA), N, static_cast<const double *>(dB), N, a.emin, a.emax, a.m0,
                    static_cast<double *>(dX), N};
         info = dispatch(a.cplx, pb, o, s, ws, out, so.st);
         if (info == 0 || info == 1 || info == 2 || info == 3 || info == 4 || info == 5) {
             const int mo = (info == 4 || info == 5) ? a.m0 : out.m0;
-            FX_CHECK(hipMemcpy2DAsync(a.X, es * a.ldx, dX, es * N, es * N, mo, hipMemcpyDeviceToHost, s));
-            FX_CHECK(hipStreamSynchronize(s));
+            download_cols(a.X, es * a.ldx, dX, es * N, mo, s);
         }
     } catch (const alloc_error &) {
         info = -1;
@@ -1755,7 +1797,7 @@ struct NoAllocDevice {
 static NoAllocDevice g_noalloc[NOALLOC_MAX_DEVICES];
 }  // namespace fx
 
-// Per-launch timing hook of the complex64 matrix product (feast_set_timing).
+// Per-launch timing hook of the complex matrix products (feast_set_timing).
 // Events come from a pool created once per thread, so the hook only records.
 namespace fx {
 static thread_local std::vector<hipEvent_t> t_event_pool;
@@ -1769,15 +1811,15 @@ static hipEvent_t pooled_event()
     }
     return t_event_pool[t_event_next++];
 }
-void gemm_timing_begin(hipStream_t s, hipEvent_t *e)
+void gemm_timing_begin(hipStream_t s, hipEvent_t *e, bool f64)
 {
-    if (!g_gemm_timer) return;
+    if (!g_gemm_timer || f64 != g_gemm_timer->f64) return;
     *e = pooled_event();
     FX_CHECK(hipEventRecord(*e, s));
 }
-void gemm_timing_end(hipStream_t s, hipEvent_t e0, double flops)
+void gemm_timing_end(hipStream_t s, hipEvent_t e0, double flops, bool f64)
 {
-    if (!g_gemm_timer) return;
+    if (!g_gemm_timer || f64 != g_gemm_timer->f64) return;
     hipEvent_t e1 = pooled_event();
     FX_CHECK(hipEventRecord(e1, s));
     g_gemm_timer->ev.push_back({e0, e1});
@@ -2296,11 +2338,11 @@ static int gsolve(bool real_in, int N, const void *A, int lda, const void *B, in
                 FX_CHECK(hipMemcpy(dB, tmp.data(), es * nn, hipMemcpyHostToDevice));
             }
         } else {
-            FX_CHECK(hipMemcpy2D(dA, es * N, A, es * lda, es * N, N, hipMemcpyHostToDevice));
-            if (B) FX_CHECK(hipMemcpy2D(dB, es * N, B, es * ldb, es * N, N, hipMemcpyHostToDevice));
+            fx::upload_cols(dA, A, es * lda, es * N, N);
+            if (B) fx::upload_cols(dB, B, es * ldb, es * N, N);
         }
         // blocking upload, as in the Hermitian host path
-        if (o.x0) FX_CHECK(hipMemcpy2D(dX, es * N, X, es * ldx, es * N, 2 * m0, hipMemcpyHostToDevice));
+        if (o.x0) fx::upload_cols(dX, X, es * ldx, es * N, 2 * m0);
         fx::GProblem pb{N, dA, N, dB, N, emid, r, m0, dX, N};
         try {
             info = o.precision == 1 ? fx::run_general<float>(pb, o, s, ws, out, st)
@@ -2310,8 +2352,7 @@ static int gsolve(bool real_in, int N, const void *A, int lda, const void *B, in
             info = e.info;
         }
         if (info >= 0 && info <= 3) {
-            FX_CHECK(hipMemcpy2DAsync(X, es * ldx, dX, es * N, es * N, 2 * m0, hipMemcpyDeviceToHost, s));
-            FX_CHECK(hipStreamSynchronize(s));
+            fx::download_cols(X, es * ldx, dX, es * N, 2 * m0, s);
         }
         }
     } catch (const fx::alloc_error &) {
@@ -2407,11 +2448,11 @@ static int solve_slices(bool cplx, int N, const void *A, int lda, const void *B,
         const void *dA = A, *dB = B;
         if (!device) {
             void *a = st.get(es * (size_t)N * N);
-            FX_CHECK(hipMemcpy2D(a, es * N, A, es * lda, es * N, N, hipMemcpyHostToDevice));
+            fx::upload_cols(a, A, es * lda, es * N, N);
             dA = a;
             if (B) {
                 void *b = st.get(es * (size_t)N * N);
-                FX_CHECK(hipMemcpy2D(b, es * N, B, es * ldb, es * N, N, hipMemcpyHostToDevice));
+                fx::upload_cols(b, B, es * ldb, es * N, N);
                 dB = b;
             }
         }
@@ -2431,7 +2472,7 @@ static int solve_slices(bool cplx, int N, const void *A, int lda, const void *B,
             } else {
                 dX[s] = st.get(es * (size_t)N * cap[s]);
                 if (o.x0)
-                    FX_CHECK(hipMemcpy2D(dX[s], es * N, q.X, es * q.ldx, es * N, cap[s], hipMemcpyHostToDevice));
+                    fx::upload_cols(dX[s], q.X, es * q.ldx, es * N, cap[s]);
             }
             feast_job &j = jobs[s];
             j = q;
@@ -2509,7 +2550,7 @@ static int solve_slices(bool cplx, int N, const void *A, int lda, const void *B,
                 feast_job &q = slices[s];
                 const int i = q.info;
                 if (i == 0 || i == 1 || i == 2 || i == 3)
-                    FX_CHECK(hipMemcpy2D(q.X, es * q.ldx, dX[s], es * N, es * N, q.m0_out, hipMemcpyDeviceToHost));
+                    fx::download_cols(q.X, es * q.ldx, dX[s], es * N, q.m0_out, nullptr);
             }
         }
     } catch (const fx::alloc_error &) {

@@ -257,9 +257,10 @@ template <> struct gemm_cfg_narrow<float, true> {
     static constexpr bool DB = true, G3 = true;
 };
 
-// Optional per-launch timing of the complex64 product (defined by the driver).
-void gemm_timing_begin(hipStream_t s, hipEvent_t *e);
-void gemm_timing_end(hipStream_t s, hipEvent_t e0, double flops);
+// Optional per-launch timing of the complex products (defined by the driver;
+// f64 tells the element precision, the driver records one of the two).
+void gemm_timing_begin(hipStream_t s, hipEvent_t *e, bool f64);
+void gemm_timing_end(hipStream_t s, hipEvent_t e0, double flops, bool f64);
 
 // Two-level batch: entry (z, y), z < batch, y < batch2, at offsets
 // z * s? + y * s?2, with m + y * dm rows (dm may be negative; entries with
@@ -272,9 +273,10 @@ void gemm2(hipStream_t s, int m, int n, int k, T alpha, const typename elem<T, C
     const int mmax = std::max(m, m + (batch2 - 1) * dm);
     if (mmax <= 0 || n <= 0 || batch <= 0 || batch2 <= 0) return;
     if (alpha == T(0)) throw hip_error{hipErrorInvalidValue};   // the kernel scales C by beta / alpha
-    constexpr bool timed = std::is_same<T, float>::value && CPLX;
+    constexpr bool timed = CPLX;
+    constexpr bool f64 = std::is_same<T, double>::value;
     hipEvent_t e0 = nullptr;
-    if (timed) gemm_timing_begin(s, &e0);
+    if (timed) gemm_timing_begin(s, &e0, f64);
     // k <= 0: C = beta C (the k loop does not run)
     auto launch = [&](auto cfg_tag) {
         using cfg = decltype(cfg_tag);
@@ -285,7 +287,7 @@ void gemm2(hipStream_t s, int m, int n, int k, T alpha, const typename elem<T, C
                            grid, dim3(NT), 0, s, m, n, k, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, sA2, sB2,
                            sC2, dm);
     };
-    if constexpr (timed && !OPA_H) {
+    if constexpr (timed && !f64 && !OPA_H) {
         if (n <= 32) launch(gemm_cfg_narrow<T, CPLX>{});
         else launch(gemm_cfg<T, CPLX>{});
     } else {
@@ -294,7 +296,7 @@ void gemm2(hipStream_t s, int m, int n, int k, T alpha, const typename elem<T, C
     FX_LAUNCH_CHECK();
     double rows = 0;   // summed over the y entries
     for (int y = 0; y < batch2; ++y) rows += std::max(0, m + y * dm);
-    if (timed) gemm_timing_end(s, e0, 8.0 * rows * (double)n * (k > 0 ? k : 0) * batch);
+    if (timed) gemm_timing_end(s, e0, 8.0 * rows * (double)n * (k > 0 ? k : 0) * batch, f64);
 }
 
 template <typename T, bool CPLX, bool OPA_H>
