@@ -333,9 +333,39 @@ int feast_rationalx(const feast_z *Zne, const feast_z *Wne, int fpm2, const doub
 
 /* Statistics of the calling thread's last solve; 0 on success. */
 int feast_last_stats(feast_stats *stats);
-/* Enable (1) or disable (0) per-launch HIP-event timing of the complex64
- * matrix-product kernel (reported in feast_stats). */
+/* Enable (1) or disable (0) per-launch HIP-event timing of the complex
+ * matrix-product kernel in each solve's factor precision (reported in
+ * feast_stats). */
 void feast_set_timing(int on);
+
+/* ---- tile autotuner (spec batching: tile shapes chosen on the device).
+ * The complex products (LU updates, triangular-solve updates, Rayleigh-Ritz)
+ * have FEAST_TILE_VARIANTS tile shapes per precision; which one runs is read
+ * from a process-wide table indexed by precision (0 complex64, 1 complex128)
+ * and depth class (0: depth <= 64, the LU and Cholesky updates; 1: deeper,
+ * the solve updates and Rayleigh-Ritz products).  Variant 0 is the default.
+ * Every variant accumulates each output over the depth in the same order, so
+ * the table changes times, never results. */
+#define FEAST_TILE_VARIANTS 3
+typedef struct {
+    int choice[2][2];        /* [precision][class] -> variant, 0 .. FEAST_TILE_VARIANTS - 1 */
+    double tflops[2][2][FEAST_TILE_VARIANTS]; /* feast_autotune: measured rate of each variant
+                                (8 flops per complex multiply-add); 0 when not measured */
+} feast_tiles;
+/* Time every variant on the current device on the shapes of a solve of order
+ * n with m0 right-hand sides and ne contour nodes (capped at n = 4096 and
+ * ne = 8 to bound the scratch: one depth-64 trailing update of n - 64 rows
+ * and columns, one depth-256 solve update with m0 columns, batch ne), install
+ * the fastest per precision and class in the table (a variant replaces the
+ * default only when at least 5 % faster), and return both in *out (may be
+ * NULL).  Allocates and frees its own device scratch (up to about 2.2 GB).
+ * Not to be called while solves run on other threads.  Returns 0, 202 (n < 64),
+ * 201 (m0 < 1), 102 (ne < 1), -1 (device allocation failed), -4 (HIP error). */
+int feast_autotune(int n, int m0, int ne, feast_tiles *out);
+/* The current table (tflops zero). */
+void feast_get_tiles(feast_tiles *out);
+/* Install a table (choices only); 0, or -101 for NULL / an out-of-range entry. */
+int feast_set_tiles(const feast_tiles *tiles);
 /* Free the calling thread's context (device workspace and streams). */
 void feast_release(void);
 /* Library version string. */

@@ -1830,6 +1830,8 @@ void gemm_timing_end(hipStream_t s, hipEvent_t e0, double flops, bool f64)
 void gemm_timing_reset() { t_event_next = 0; }
 }  // namespace fx
 
+#include "tune.hpp"
+
 // ======================================================================
 //            concurrent executor: batched solves and the server
 // ======================================================================
@@ -2704,6 +2706,48 @@ int feast_last_stats(feast_stats *st)
 void feast_set_timing(int on)
 {
     fx::g_timing = on != 0;
+}
+
+int feast_autotune(int n, int m0, int ne, feast_tiles *out)
+{
+    if (n < 64) return 202;
+    if (m0 < 1) return 201;
+    if (ne < 1) return 102;
+    try {
+        fx::TileTimes tt = fx::autotune(n, m0, ne);
+        feast_tiles t{};
+        for (int p = 0; p < 2; ++p)
+            for (int c = 0; c < fx::GEMM_CLASSES; ++c) {
+                t.choice[p][c] = fx::g_tiles[p][c].load();
+                for (int v = 0; v < fx::GEMM_VARIANTS; ++v) t.tflops[p][c][v] = tt.tf[p][c][v];
+            }
+        if (out) *out = t;
+        return 0;
+    } catch (const fx::alloc_error &) {
+        return -1;
+    } catch (const fx::hip_error &e) {
+        std::fprintf(stderr, "feastx: HIP error %s in feast_autotune\n", hipGetErrorString(e.code));
+        return -4;
+    }
+}
+
+void feast_get_tiles(feast_tiles *out)
+{
+    if (!out) return;
+    *out = feast_tiles{};
+    for (int p = 0; p < 2; ++p)
+        for (int c = 0; c < fx::GEMM_CLASSES; ++c) out->choice[p][c] = fx::g_tiles[p][c].load();
+}
+
+int feast_set_tiles(const feast_tiles *t)
+{
+    if (!t) return -101;
+    for (int p = 0; p < 2; ++p)
+        for (int c = 0; c < fx::GEMM_CLASSES; ++c)
+            if (t->choice[p][c] < 0 || t->choice[p][c] >= fx::GEMM_VARIANTS) return -101;
+    for (int p = 0; p < 2; ++p)
+        for (int c = 0; c < fx::GEMM_CLASSES; ++c) fx::g_tiles[p][c].store(t->choice[p][c]);
+    return 0;
 }
 
 void feast_release(void)

@@ -229,14 +229,18 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, MINB) void gemm_kernel(
 // On random data the 64x64 four-product kernel gives 74-90 TF/s on the
 // depth-64 updates and 64-77 on the solve updates; double-buffered with the
 // three-product form, 96-109 and 81-90 (flops counted as 8 per complex
-// multiply-add).
+// multiply-add).  A depth sweep at N = 8192 over 16 matrices (random data,
+// depth-64 LU update / 600-column depth-256 solve update): BK 8 against 16
+// gives complex64 104 / 135 against 100 / 131 TF/s, and complex128, with
+// three workgroups per CU instead of two, 62 / 75 against 58 / 66; BK 32 and
+// 128x128 tiles are slower in both.
 template <typename T, bool CPLX> struct gemm_cfg;
 template <> struct gemm_cfg<float, true> {
-    static constexpr int BM = 64, BN = 64, BK = 16, WM = 32, WN = 32, MINB = 4;
+    static constexpr int BM = 64, BN = 64, BK = 8, WM = 32, WN = 32, MINB = 4;
     static constexpr bool DB = true, G3 = true;
 };
 template <> struct gemm_cfg<double, true> {
-    static constexpr int BM = 64, BN = 64, BK = 16, WM = 32, WN = 32, MINB = 2;
+    static constexpr int BM = 64, BN = 64, BK = 8, WM = 32, WN = 32, MINB = 3;
     static constexpr bool DB = true, G3 = true;
 };
 template <> struct gemm_cfg<double, false> {
@@ -256,6 +260,68 @@ template <> struct gemm_cfg_narrow<float, true> {
     static constexpr int BM = 64, BN = 32, BK = 16, WM = 32, WN = 16, MINB = 4;
     static constexpr bool DB = true, G3 = true;
 };
+
+// Tile variants of the complex products, chosen per precision and depth
+// class from a table that the autotuner (feast_autotune) fills; variant 0 is
+// the default.  Every variant accumulates each output over k in the same
+// order, four terms per matrix-core step, so the choice changes time, not
+// results.
+template <typename T, int V> struct gemm_var;
+template <> struct gemm_var<float, 0> : gemm_cfg<float, true> {};
+template <> struct gemm_var<float, 1> {   // eight waves, 128x64
+    static constexpr int BM = 128, BN = 64, BK = 8, WM = 32, WN = 32, MINB = 2;
+    static constexpr bool DB = true, G3 = true;
+};
+template <> struct gemm_var<float, 2> {   // deeper staging
+    static constexpr int BM = 64, BN = 64, BK = 16, WM = 32, WN = 32, MINB = 4;
+    static constexpr bool DB = true, G3 = true;
+};
+template <> struct gemm_var<double, 0> : gemm_cfg<double, true> {};
+template <> struct gemm_var<double, 1> {  // waves of 64x16
+    static constexpr int BM = 64, BN = 64, BK = 8, WM = 64, WN = 16, MINB = 3;
+    static constexpr bool DB = true, G3 = true;
+};
+template <> struct gemm_var<double, 2> {  // deeper staging, two per CU
+    static constexpr int BM = 64, BN = 64, BK = 16, WM = 32, WN = 32, MINB = 2;
+    static constexpr bool DB = true, G3 = true;
+};
+constexpr int GEMM_VARIANTS = 3;
+constexpr int GEMM_CLASSES = 2;   // 0: depth <= 64 (LU and Cholesky updates), 1: deeper (solves, Rayleigh-Ritz)
+inline int gemm_depth_class(int k) { return k <= 64 ? 0 : 1; }
+int gemm_tile_choice(bool f64, int cls);   // defined by the driver (the autotuner's table)
+
+template <typename T, bool CPLX, bool OPA_H, typename cfg>
+void gemm_launch_cfg(hipStream_t s, int m, int mmax, int n, int k, T alpha, const typename elem<T, CPLX>::type *A,
+                     long lda, long sA, long sA2, const typename elem<T, CPLX>::type *B, long ldb, long sB, long sB2,
+                     T beta, typename elem<T, CPLX>::type *C, long ldc, long sC, long sC2, int batch, int batch2,
+                     int dm)
+{
+    constexpr int NT = (cfg::BM / cfg::WM) * (cfg::BN / cfg::WN) * 64;
+    dim3 grid(ceil_div(mmax, cfg::BM) * ceil_div(n, cfg::BN), batch2, batch);
+    hipLaunchKernelGGL((gemm_kernel<T, CPLX, OPA_H, cfg::BM, cfg::BN, cfg::BK, cfg::WM, cfg::WN, cfg::MINB, cfg::DB,
+                                    cfg::G3>),
+                       grid, dim3(NT), 0, s, m, n, k, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, sA2, sB2, sC2,
+                       dm);
+}
+
+// One complex product C = alpha A B + beta C (batch of `batch`) with tile
+// variant v, no timing hook (the autotuner's launches).
+template <typename T>
+void gemm_variant(hipStream_t s, int v, int m, int n, int k, T alpha, const cplx<T> *A, long lda, long sA,
+                  const cplx<T> *B, long ldb, long sB, T beta, cplx<T> *C, long ldc, long sC, int batch)
+{
+    if (m <= 0 || n <= 0 || batch <= 0) return;
+    if (v == 1)
+        gemm_launch_cfg<T, true, false, gemm_var<T, 1>>(s, m, m, n, k, alpha, A, lda, sA, 0, B, ldb, sB, 0, beta, C,
+                                                        ldc, sC, 0, batch, 1, 0);
+    else if (v == 2)
+        gemm_launch_cfg<T, true, false, gemm_var<T, 2>>(s, m, m, n, k, alpha, A, lda, sA, 0, B, ldb, sB, 0, beta, C,
+                                                        ldc, sC, 0, batch, 1, 0);
+    else
+        gemm_launch_cfg<T, true, false, gemm_var<T, 0>>(s, m, m, n, k, alpha, A, lda, sA, 0, B, ldb, sB, 0, beta, C,
+                                                        ldc, sC, 0, batch, 1, 0);
+    FX_LAUNCH_CHECK();
+}
 
 // Optional per-launch timing of the complex products (defined by the driver;
 // f64 tells the element precision, the driver records one of the two).
@@ -280,16 +346,23 @@ void gemm2(hipStream_t s, int m, int n, int k, T alpha, const typename elem<T, C
     // k <= 0: C = beta C (the k loop does not run)
     auto launch = [&](auto cfg_tag) {
         using cfg = decltype(cfg_tag);
-        constexpr int NT = (cfg::BM / cfg::WM) * (cfg::BN / cfg::WN) * 64;
-        dim3 grid(ceil_div(mmax, cfg::BM) * ceil_div(n, cfg::BN), batch2, batch);
-        hipLaunchKernelGGL((gemm_kernel<T, CPLX, OPA_H, cfg::BM, cfg::BN, cfg::BK, cfg::WM, cfg::WN, cfg::MINB,
-                                        cfg::DB, cfg::G3>),
-                           grid, dim3(NT), 0, s, m, n, k, alpha, A, lda, sA, B, ldb, sB, beta, C, ldc, sC, sA2, sB2,
-                           sC2, dm);
+        gemm_launch_cfg<T, CPLX, OPA_H, cfg>(s, m, mmax, n, k, alpha, A, lda, sA, sA2, B, ldb, sB, sB2, beta, C, ldc,
+                                             sC, sC2, batch, batch2, dm);
     };
-    if constexpr (timed && !f64 && !OPA_H) {
-        if (n <= 32) launch(gemm_cfg_narrow<T, CPLX>{});
-        else launch(gemm_cfg<T, CPLX>{});
+    if constexpr (CPLX) {
+        bool done = false;
+        if constexpr (!f64 && !OPA_H) {
+            if (n <= 32) {
+                launch(gemm_cfg_narrow<T, CPLX>{});
+                done = true;
+            }
+        }
+        if (!done) {
+            const int v = gemm_tile_choice(f64, gemm_depth_class(k));
+            if (v == 1) launch(gemm_var<T, 1>{});
+            else if (v == 2) launch(gemm_var<T, 2>{});
+            else launch(gemm_var<T, 0>{});
+        }
     } else {
         launch(gemm_cfg<T, CPLX>{});
     }

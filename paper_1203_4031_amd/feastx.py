@@ -68,6 +68,13 @@ class feast_result(C.Structure):
                 ("latency_ms", C.c_double)]
 
 
+TILE_VARIANTS = 3
+
+
+class feast_tiles(C.Structure):
+    _fields_ = [("choice", (C.c_int * 2) * 2), ("tflops", ((C.c_double * TILE_VARIANTS) * 2) * 2)]
+
+
 def lib():
     """Load libfeastx.so; raises if it has not been built."""
     global _lib
@@ -100,6 +107,10 @@ def lib():
         L.feast_set_timing.restype = None
         L.feast_release.argtypes = []
         L.feast_release.restype = None
+        L.feast_autotune.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(feast_tiles)]
+        L.feast_get_tiles.argtypes = [C.POINTER(feast_tiles)]
+        L.feast_get_tiles.restype = None
+        L.feast_set_tiles.argtypes = [C.POINTER(feast_tiles)]
         L.feast_version.restype = C.c_char_p
         for name in ("feast_solve_batched_d", "feast_solve_batched_z"):
             f = getattr(L, name)
@@ -326,6 +337,45 @@ def set_timing(on: bool):
 
 def release():
     lib().feast_release()
+
+
+_PRECISIONS = ("complex64", "complex128")
+_CLASSES = ("depth<=64", "deeper")
+
+
+def _tiles_dict(t: feast_tiles) -> dict:
+    return {"choice": {p: {c: t.choice[i][j] for j, c in enumerate(_CLASSES)} for i, p in enumerate(_PRECISIONS)},
+            "tflops": {p: {c: [round(t.tflops[i][j][v], 2) for v in range(TILE_VARIANTS)]
+                           for j, c in enumerate(_CLASSES)} for i, p in enumerate(_PRECISIONS)}}
+
+
+def autotune(n: int, m0: int, ne: int) -> dict:
+    """feast_autotune: time the product kernel's tile variants on this
+    device for a solve of order n, m0 columns, ne nodes, install the fastest
+    and return {"choice": {precision: {class: variant}}, "tflops": ...}."""
+    t = feast_tiles()
+    info = lib().feast_autotune(int(n), int(m0), int(ne), C.byref(t))
+    if info != 0:
+        raise RuntimeError(f"feast_autotune: {info}")
+    return _tiles_dict(t)
+
+
+def tiles() -> dict:
+    """The installed tile table (choices)."""
+    t = feast_tiles()
+    lib().feast_get_tiles(C.byref(t))
+    return _tiles_dict(t)["choice"]
+
+
+def set_tiles(choice: dict) -> None:
+    """Install a table {precision: {class: variant}} as returned by tiles()."""
+    t = feast_tiles()
+    for i, p in enumerate(_PRECISIONS):
+        for j, c in enumerate(_CLASSES):
+            t.choice[i][j] = int(choice[p][c])
+    info = lib().feast_set_tiles(C.byref(t))
+    if info != 0:
+        raise ValueError(f"feast_set_tiles: {info}")
 
 
 def solve_batched(problems, concurrency=4, **kw) -> list[Result]:

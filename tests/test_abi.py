@@ -197,3 +197,26 @@ def test_device_gsolve_and_slices_check_operands():
         feastx.solve_slices(np.eye(n), None, [0.0, 1.0, 2.0], 3, X0=[np.zeros((n, 3))])
     with pytest.raises(ValueError, match=r"X0\[1\] has shape"):
         feastx.solve_slices(np.eye(n), None, [0.0, 1.0, 2.0], 3, X0=[np.zeros((n, 3)), np.zeros((n, 2))])
+
+
+def test_tile_table_host_logic():
+    """The tile table starts at the defaults, takes valid choices, refuses
+    out-of-range ones without changing, and the tuner checks its sizes
+    before touching the device."""
+    before = feastx.tiles()
+    try:
+        want = {"complex64": {"depth<=64": 1, "deeper": 2}, "complex128": {"depth<=64": 2, "deeper": 1}}
+        feastx.set_tiles(want)
+        assert feastx.tiles() == want
+        bad = {"complex64": {"depth<=64": feastx.TILE_VARIANTS, "deeper": 0},
+               "complex128": {"depth<=64": 0, "deeper": -1}}
+        with pytest.raises(ValueError):
+            feastx.set_tiles(bad)
+        assert feastx.tiles() == want
+        t = feastx.feast_tiles()
+        assert feastx.lib().feast_autotune(63, 10, 8, C.byref(t)) == 202
+        assert feastx.lib().feast_autotune(512, 0, 8, C.byref(t)) == 201
+        assert feastx.lib().feast_autotune(512, 10, 0, C.byref(t)) == 102
+        assert feastx.lib().feast_set_tiles(None) == -101
+    finally:
+        feastx.set_tiles(before)
