@@ -3,11 +3,12 @@
 Headline: the largest single-GPU workload, a dense complex Hermitian
 generalized problem A x = lambda B x with N = 8192 (A = U diag(lambda) U^H,
 Haar U, clustered spectrum; B = I + 0.1 H), M0 = 600, Ne = 16 Gauss-Legendre
-half-contour nodes, about 400 eigenvalues in the interval, tol 1e-10.  `value`
-is mixed-precision solves/s (complex64 factors and solves on the FP32 matrix
-cores, FP64 residual correction, complex128 for the contour nodes where
-complex64 error would limit the iteration); plain FP64 on the same GPU is
-reported beside it.
+half-contour nodes, about 400 eigenvalues in the interval, tol 1e-10.  Both
+precisions are timed the same way, K solves each: mixed (complex64 factors
+and solves on the FP32 matrix cores, FP64 residual correction, complex128 for
+the contour nodes where complex64 error would limit the iteration) and FP64
+(complex128 throughout).  `value` is the faster one's solves/s, `precision`
+names it and `dtype` is its arithmetic; both are reported in full.
 
 One step = one complete feast_solve call (all contour nodes: shift, LU,
 solves, quadrature, Rayleigh-Ritz, reduced eigensolve, residuals, every FEAST
@@ -48,13 +49,16 @@ PEAK_FP64_MFMA = 78.6
 # HBM bytes per launch of the roofline kernel (FETCH_SIZE + WRITE_SIZE, each
 # scaled by a 256 MiB copy's reading, averaged over the launches of one
 # solve), from the rocprofv3 counter passes summarised in profiles/, per
-# workload.  Each holds only for the sources it was measured on -- the
-# kernel itself and every file that launches it (the FP64 reduced-problem
-# kernels in jacobi.hpp and bortho.hpp do not): `traffic` is null when they
-# differ.
-TRAFFIC = {   # profiles/hbm_traffic_hermgen_n8192_m0600.md, profiles/hbm_traffic_realgen_n4096_m0300.md
-    "hermgen_n8192": (3.414e+08, "dfbdfd70c84e4dea329fc24293641eb9325a2fe4eed2a67f200c26611f6ee5f1"),
-    "realgen_n4096": (1.196e+08, "dfbdfd70c84e4dea329fc24293641eb9325a2fe4eed2a67f200c26611f6ee5f1"),
+# workload and precision, with the tile table they ran under.  Each holds only
+# for the sources it was measured on -- the kernel itself and every file that
+# launches it in a solve (the FP64 reduced-problem kernels in jacobi.hpp and
+# bortho.hpp and the tuner in tune.hpp do not) -- and for that table:
+# `traffic` is null otherwise.
+TRAFFIC = {   # profiles/hbm_traffic_hermgen_n8192_m0600_fp64.md, profiles/hbm_traffic_realgen_n4096_m0300.md
+    "hermgen_n8192_fp64": (1.9476e+09, "b9efbd3e4498fb5adbc5b9244a5b9811c14208aec1cef781d691ff6bef4c24f7",
+                           {"depth<=64": 0, "deeper": 0}),
+    "realgen_n4096_mixed": (1.1894e+08, "b9efbd3e4498fb5adbc5b9244a5b9811c14208aec1cef781d691ff6bef4c24f7",
+                            {"depth<=64": 0, "deeper": 0}),
 }
 
 
@@ -63,7 +67,7 @@ def kernel_sources_sha256():
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1203_4031_amd", "csrc")
     for name in sorted(os.listdir(d)):
-        if name.endswith((".hip", ".hpp", ".h")) and name not in ("jacobi.hpp", "bortho.hpp"):
+        if name.endswith((".hip", ".hpp", ".h")) and name not in ("jacobi.hpp", "bortho.hpp", "tune.hpp"):
             h.update(name.encode())
             with open(os.path.join(d, name), "rb") as f:
                 h.update(f.read())
@@ -180,81 +184,121 @@ def stage_ms(feastx):
     return d
 
 
-def measure_single(feastx, torch, p, steps, fp64_steps, warmup, roofline_steps, traffic_key):
+PRECISION_TEXT = {
+    "mixed": "mixed (complex64 factors and solves, complex128 for the nodes where complex64 error would limit "
+             "the iteration, FP64 residual correction)",
+    "fp64": "FP64 (complex128 factors and solves, FP64 Rayleigh-Ritz)",
+}
+
+# tile variants of the complex product kernel (the autotuner's table picks one
+# per precision and depth class)
+TILE_KERNELS = {
+    "complex64": ["gemm_kernel<float, true, false, 64, 64, 8, 32, 32, 4, true, true>",
+                  "gemm_kernel<float, true, false, 128, 64, 8, 32, 32, 2, true, true>",
+                  "gemm_kernel<float, true, false, 64, 64, 16, 32, 32, 4, true, true>"],
+    "complex128": ["gemm_kernel<double, true, false, 64, 64, 8, 32, 32, 3, true, true>",
+                   "gemm_kernel<double, true, false, 64, 64, 8, 64, 16, 3, true, true>",
+                   "gemm_kernel<double, true, false, 64, 64, 16, 32, 32, 2, true, true>"],
+}
+
+
+def roofline_kernel(feastx, best):
+    """Name, description and peak of the roofline kernel of precision `best`
+    under the installed tile table."""
+    prec = "complex64" if best == "mixed" else "complex128"
+    ch = feastx.tiles()[prec]
+    names = {cls: TILE_KERNELS[prec][v] for cls, v in ch.items()}
+    if best == "mixed":
+        what = ("complex64 matrix product on the FP32 matrix cores (LU trailing updates and triangular-solve "
+                "updates), every launch of the timed solves; products of at most 32 columns use the 64x32 "
+                "instance gemm_kernel<float, true, false, 64, 32, 16, 32, 16, 4, true, true> and the adjoint "
+                "solves of Hermitian pencils the A^H instances gemm_kernel<float, true, true, ...>, all counted")
+        peak = PEAK_FP32_MFMA
+    else:
+        what = ("complex128 matrix product on the FP64 matrix cores (LU trailing updates, triangular-solve "
+                "updates and, for complex pencils, the Rayleigh-Ritz and Ritz-vector products), every launch of "
+                "the timed solves; the adjoint solves of Hermitian pencils use the A^H instances "
+                "gemm_kernel<double, true, true, ...>, counted too")
+        peak = PEAK_FP64_MFMA
+    if names["depth<=64"] == names["deeper"]:
+        name = names["deeper"]
+    else:
+        name = f"{names['depth<=64']} (depth <= 64) and {names['deeper']} (deeper)"
+    return f"{name}: {what}", peak
+
+
+def time_precision(feastx, torch, A, B, X0, X, p, precision, steps, expected):
+    """`steps` solves back to back, bracketed by device synchronisations."""
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    times, res, _ = run_steps(feastx, torch, A, B, X0, X, p, precision, steps, False)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    stages = stage_ms(feastx)
+    check(res, p, expected)
+    loops = res[-1].loop + 1
+    log(f"{p.name} {precision}: {steps} solves in {wall:.3f}s, {loops} loops")
+    lat = np.array(times) * 1e3
+    return {"solves_per_s": steps / wall, "ms_per_solve": wall / steps * 1e3,
+            "eigenpairs_per_s": steps / wall * expected, "loops": loops,
+            "latency_ms_single_solves": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+            "stage_ms_last_solve": stages}
+
+
+def measure_single(feastx, torch, p, steps, warmup, roofline_steps, traffic_key, precisions=("mixed", "fp64")):
     """Mixed and FP64 solves of one workload with inputs in HBM: solves/s,
-    latency, stage times, and the complex64 product kernel's roofline."""
+    latency and stage times of each precision; the faster one is the
+    workload's figure, with the roofline of its complex product kernel."""
     expected = p.count_in_interval()
     A = feastx.fortran_tensor(p.A)
     B = feastx.fortran_tensor(p.B)
     X0 = feastx.fortran_tensor(p.X0.astype(np.complex128) if p.hermitian else p.X0)
     X = X0.clone(memory_format=torch.contiguous_format).t().contiguous().t()
-    run_steps(feastx, torch, A, B, X0, X, p, "mixed", warmup, False)
-    if warmup > 0 and fp64_steps > 0:
-        run_steps(feastx, torch, A, B, X0, X, p, "fp64", 1, False)
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    times, res_mixed, _ = run_steps(feastx, torch, A, B, X0, X, p, "mixed", steps, False)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
-    stages = stage_ms(feastx)
-    check(res_mixed, p, expected)
-    loops = res_mixed[-1].loop + 1
-    log(f"{p.name} mixed: {steps} solves in {wall:.3f}s, {loops} loops")
-    # the same solves with a HIP event pair around every launch of the
-    # complex64 product kernel (on the library's stream)
-    _, res_t, lu = run_steps(feastx, torch, A, B, X0, X, p, "mixed", roofline_steps, True)
+    for precision in precisions:
+        run_steps(feastx, torch, A, B, X0, X, p, precision, warmup, False)
+    per = {pr: time_precision(feastx, torch, A, B, X0, X, p, pr, steps, expected) for pr in precisions}
+    best = max(per, key=lambda pr: per[pr]["solves_per_s"])
+    # the same solves of the faster precision with a HIP event pair around
+    # every launch of its complex product kernel (on the library's stream)
+    _, res_t, lu = run_steps(feastx, torch, A, B, X0, X, p, best, roofline_steps, True)
     check(res_t, p, expected)
-    times64, loops64, stages64 = [float("nan")], None, None
-    if fp64_steps > 0:
-        times64, res64, _ = run_steps(feastx, torch, A, B, X0, X, p, "fp64", fp64_steps, False)
-        stages64 = stage_ms(feastx)
-        check(res64, p, expected)
-        loops64 = res64[-1].loop + 1
-        log(f"{p.name} fp64: {fp64_steps} solves, mean {np.mean(times64) * 1e3:.1f} ms, {loops64} loops")
+    kname, peak = roofline_kernel(feastx, best)
     achieved = lu[1] / (lu[0] * 1e-3) / 1e12 if lu[0] > 0 else 0.0
-    traffic_bytes, traffic_sha = TRAFFIC.get(traffic_key, (None, ""))
-    lat = np.array(times) * 1e3
+    traffic_bytes, traffic_sha, traffic_tiles = TRAFFIC.get(f"{traffic_key}_{best}", (None, "", None))
+    prec_name = "complex64" if best == "mixed" else "complex128"
+    traffic_ok = (traffic_bytes is not None and kernel_sources_sha256() == traffic_sha
+                  and feastx.tiles()[prec_name] == traffic_tiles)
     out = {
-        "solves_per_s": steps / wall,
-        "ms_per_solve": wall / steps * 1e3,
-        "eigenpairs_per_s": steps / wall * expected,
+        "precision": best,
+        "solves_per_s": per[best]["solves_per_s"],
+        "ms_per_solve": per[best]["ms_per_solve"],
+        "eigenpairs_per_s": per[best]["eigenpairs_per_s"],
         "count": expected,
-        "loops": loops,
-        "fp64_solves_per_s": 1.0 / float(np.mean(times64)),
-        "fp64_ms_per_solve": float(np.mean(times64)) * 1e3,
-        "fp64_loops": loops64,
-        "mixed_over_fp64": (steps / wall) * float(np.mean(times64)),
-        "latency_ms_single_solves": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
-        "stage_ms_last_mixed_solve": stages,
-        "stage_ms_last_fp64_solve": stages64,
-        "roofline": {"kernel": "gemm_kernel<float, true, false, 64, 64, 16, 32, 32, 4, true, true>: complex64 "
-                               "matrix product on the FP32 matrix cores (LU trailing updates and "
-                               "triangular-solve updates), every launch of the timed solves; products of at "
-                               "most 32 columns use its 64x32 instance gemm_kernel<float, true, false, 64, 32, "
-                               "16, 32, 16, 4, true, true> and the adjoint solves of Hermitian pencils its "
-                               "A^H instance gemm_kernel<float, true, true, ...>, all counted here",
-                     "bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA,
-                     "traffic": (traffic_bytes if traffic_bytes and kernel_sources_sha256() == traffic_sha
-                                 else None),
+        "loops": per[best]["loops"],
+        "mixed": per.get("mixed"),
+        "fp64": per.get("fp64"),
+        "mixed_over_fp64": (per["mixed"]["solves_per_s"] / per["fp64"]["solves_per_s"]
+                            if len(per) == 2 else None),
+        "roofline": {"kernel": kname, "bound": "mfma", "achieved": achieved, "peak": peak,
+                     "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": traffic_bytes if traffic_ok else None,
                      "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "flop_count": "algorithmic, 8 per complex multiply-add; the kernel's three-multiplication "
                                    "form issues 6 of them to the matrix cores (executed rate 0.75 x achieved)",
                      "launches": lu[2], "avg_launch_ms": lu[0] / max(lu[2], 1),
                      "flops_per_launch": lu[1] / max(lu[2], 1),
-                     "measured_over": f"{roofline_steps} extra mixed solves with per-launch HIP events"},
+                     "measured_over": f"{roofline_steps} extra {best} solves with per-launch HIP events"},
     }
     upd = lu[4] / (lu[3] * 1e-3) / 1e12 if lu[3] > 0 else 0.0
     fac = lu[7] / (lu[6] * 1e-3) / 1e12 if lu[6] > 0 else 0.0
-    out["shifted_lu"] = {"update_achieved": upd, "update_frac": upd / PEAK_FP32_MFMA,
-                         "update_launches": lu[5], "unit": "TFLOP/s", "peak": PEAK_FP32_MFMA,
+    out["shifted_lu"] = {"precision": best, "update_achieved": upd, "update_frac": upd / peak,
+                         "update_launches": lu[5], "unit": "TFLOP/s", "peak": peak,
                          "factor_ms": lu[6] / max(roofline_steps, 1),
-                         "factor_rate": fac, "factor_frac": fac / PEAK_FP32_MFMA,
-                         "note": "update_*: the LU's complex64 product launches alone (8 flops per complex "
+                         "factor_rate": fac, "factor_frac": fac / peak,
+                         "note": "update_*: the LU's own launches of the roofline kernel (8 flops per complex "
                                  "multiply-add); factor_*: the whole factor stage (shift, panels, interchanges, "
-                                 "products, solve form W) against (8/3) N^3 per node and the FP32 peak, timed "
-                                 "with per-launch events on (so slightly slow); nodes factored in complex128 "
-                                 "count in both time and flops"}
+                                 "products, solve form W) against (8/3) N^3 per node and the matrix-core peak "
+                                 "of the factor precision, timed with per-launch events on (so slightly slow)"}
     return out, (A, B, X0, X)
 
 
@@ -498,9 +542,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--roofline-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tiles", default=None,
+                    help="install this tile table instead of autotuning: c64 depth<=64, c64 deeper, c128 "
+                         "depth<=64, c128 deeper (e.g. 1,1,0,0)")
+    ap.add_argument("--precisions", default="mixed,fp64",
+                    help="precisions to time (profiler passes of one precision's kernels)")
     ap.add_argument("--only", choices=["nonhermitian", "hermgen", "realgen"], default=None,
                     help="run only this measurement and print its JSON object (profiler passes)")
     ap.add_argument("--no-extras", action="store_true",
@@ -515,6 +563,9 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device-to-device 5 times (reference for HBM byte counters)")
     args = ap.parse_args()
+    precisions = tuple(x for x in args.precisions.split(",") if x)
+    if not precisions or any(x not in ("mixed", "fp64") for x in precisions):
+        ap.error("--precisions takes mixed, fp64 or both")
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build measures the single-GPU path "
               "(multi-GPU sharding across contour nodes is a design note, not built).",
@@ -565,6 +616,17 @@ def main():
 
     feastx.lib()
     torch.cuda.set_device(0)
+    # tile shapes of the complex product kernel, timed on this device at the
+    # headline workload's shapes (capped by the tuner) before any solve, or
+    # installed as given (profiler passes repeat a measured table)
+    if args.tiles:
+        v = [int(x) for x in args.tiles.split(",")]
+        feastx.set_tiles({"complex64": {"depth<=64": v[0], "deeper": v[1]},
+                          "complex128": {"depth<=64": v[2], "deeper": v[3]}})
+        tune = {"choice": feastx.tiles(), "installed": "--tiles"}
+    else:
+        tune = feastx.autotune(8192, 600, 16)
+    log(f"tiles: {tune['choice']}")
     if args.only == "nonhermitian":
         print(json.dumps(nonhermitian(feastx, W, steps=max(args.steps, 1))), flush=True)
         feastx.release()
@@ -573,8 +635,8 @@ def main():
     result = {}
     # ---- the N = 4096 real generalized workload
     if args.only in (None, "realgen"):
-        r2, (A2, B2, _, _) = measure_single(feastx, torch, p2, max(args.steps, 5), max(args.fp64_steps, 2),
-                                            args.warmup, max(args.roofline_steps, 2), "realgen_n4096")
+        r2, (A2, B2, _, _) = measure_single(feastx, torch, p2, max(args.steps, 5), args.warmup,
+                                            max(args.roofline_steps, 2), "realgen_n4096", precisions)
         r2["config"] = {"workload": "dense real symmetric generalized A x = lambda B x, N=4096, M0=300, Ne=8, "
                                     "200 eigenvalues in the interval, tol 1e-10", "seed": 2001}
         if want_extras:
@@ -586,15 +648,17 @@ def main():
         feastx.release()
         torch.cuda.empty_cache()
         if args.only == "realgen":
+            r2["autotune"] = tune
             print(json.dumps(r2), flush=True)
             return
 
     # ---- headline: the N = 8192 complex Hermitian generalized workload
-    r3, _ = measure_single(feastx, torch, p3, args.steps, args.fp64_steps, args.warmup, args.roofline_steps,
-                           "hermgen_n8192")
+    r3, _ = measure_single(feastx, torch, p3, args.steps, args.warmup, args.roofline_steps, "hermgen_n8192",
+                           precisions)
     feastx.release()
     torch.cuda.empty_cache()
     if args.only == "hermgen":
+        r3["autotune"] = tune
         print(json.dumps(r3), flush=True)
         return
 
@@ -609,21 +673,19 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64+c128+f64",
+        "dtype": "c128+f64" if r3["precision"] == "fp64" else "c64+c128+f64",
         "data": "synthetic",
         "config": {"workload": "dense complex Hermitian generalized A x = lambda B x, N=8192 (Haar U, "
                                "clustered spectrum, B = I + 0.1 H), M0=600, Ne=16 Gauss-Legendre, ~400 "
                                "eigenvalues in the interval, tol 1e-10",
                    "n": 8192, "m0": 600, "ne": 16, "count": r3["count"], "tol": 1e-10, "seed": 3001,
-                   "precision": "mixed (complex64 factors and solves, complex128 for the nodes where "
-                                "complex64 error would limit the iteration, FP64 residual correction)",
+                   "precision": PRECISION_TEXT[r3["precision"]],
                    "parallelism": "single GPU"},
     }
-    for k in ("eigenpairs_per_s", "loops", "fp64_solves_per_s", "fp64_ms_per_solve", "fp64_loops",
-              "mixed_over_fp64", "latency_ms_single_solves", "stage_ms_last_mixed_solve",
-              "stage_ms_last_fp64_solve", "roofline", "shifted_lu"):
+    for k in ("precision", "eigenpairs_per_s", "loops", "mixed", "fp64", "mixed_over_fp64", "roofline",
+              "shifted_lu"):
         out[k] = r3[k]
-    out["faster_precision"] = "mixed" if r3["mixed_over_fp64"] >= 1.0 else "fp64"
+    out["autotune"] = tune
     out.update(result)
 
     if want_extras:
@@ -643,7 +705,8 @@ def main():
         del pool
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle LU and solves of one shifted N=8192 matrix")
-        out["cpu_baseline"] = cpu_baseline(p3, r3["fp64_loops"] or r3["loops"], r3["fp64_ms_per_solve"])
+        ref = r3["fp64"] or r3["mixed"]
+        out["cpu_baseline"] = cpu_baseline(p3, ref["loops"], ref["ms_per_solve"])
     print(json.dumps(out), flush=True)
     feastx.release()
 
