@@ -71,6 +71,7 @@ struct Workspace {
     hipStream_t fmain = nullptr, fside = nullptr;
     hipEvent_t ev_c = nullptr, ev_d = nullptr;
     hipEvent_t ev_j[2] = {nullptr, nullptr};   // reduced eigensolve: stop words read back per sweep
+    hipEvent_t ev_s[2] = {nullptr, nullptr};   // forward and adjoint solves on two streams
     int device = -1;
     int num_cu = 0;
 
@@ -146,6 +147,8 @@ struct Workspace {
         num_cu = prop.multiProcessorCount;
         FX_CHECK(hipEventCreateWithFlags(&ev_j[0], hipEventDisableTiming));
         FX_CHECK(hipEventCreateWithFlags(&ev_j[1], hipEventDisableTiming));
+        FX_CHECK(hipEventCreateWithFlags(&ev_s[0], hipEventDisableTiming));
+        FX_CHECK(hipEventCreateWithFlags(&ev_s[1], hipEventDisableTiming));
         FX_CHECK(hipDeviceSynchronize());
     }
     void drop_split()
@@ -221,10 +224,13 @@ struct Workspace {
         if (ev_b) (void)hipEventDestroy(ev_b);
         for (auto &e : ev_j)
             if (e) (void)hipEventDestroy(e);
+        for (auto &e : ev_s)
+            if (e) (void)hipEventDestroy(e);
         drop_split();
         stream = side = nullptr;
         ev_a = ev_b = nullptr;
         ev_j[0] = ev_j[1] = nullptr;
+        ev_s[0] = ev_s[1] = nullptr;
     }
 };
 
@@ -681,7 +687,7 @@ template <typename T, bool CPLX> struct NodeGroup {
     long ldf = 0, sF = 0, sI64 = 0, sInv = 0, sItmp = 0;
     double2 *dz = nullptr;
     V *F = nullptr, *L64 = nullptr, *U64 = nullptr, *Itmp = nullptr, *Wsv = nullptr, *Linv = nullptr,
-      *Uinv = nullptr, *Ytmp = nullptr, *Y = nullptr, *Yh = nullptr, *Yh2 = nullptr;
+      *Uinv = nullptr, *Ytmp = nullptr, *Ytmp2 = nullptr, *Y = nullptr, *Yh = nullptr, *Yh2 = nullptr;
     int *ipiv = nullptr, *perm = nullptr, *swapmap = nullptr, *dinfo = nullptr, *h_info = nullptr;
 
     // buffers named with `tag` (distinct per group), the group's nodes uploaded on s
@@ -720,6 +726,8 @@ template <typename T, bool CPLX> struct NodeGroup {
         if (CPLX) {
             Yh = static_cast<V *>(ws.get("Yh" + p, sizeof(V) * (size_t)ne * nm));
             Yh2 = static_cast<V *>(ws.get("Yg" + p, sizeof(V) * (size_t)ne * nm));
+            // the adjoint solves' own scratch when they run beside the forward ones
+            if (two_streams(ws)) Ytmp2 = static_cast<V *>(ws.get("Yt2" + p, sizeof(V) * (size_t)ne * nm));
         }
         h_info = static_cast<int *>(ws.pinned("h_info" + p, sizeof(int) * ne));
     }
@@ -755,23 +763,55 @@ template <typename T, bool CPLX> struct NodeGroup {
 
     // Y_j = A_zj^{-1} R for the group's nodes; for Hermitian pencils also
     // Yh2_j = A_zj^{-H} R (the same factors)
-    void solve(hipStream_t s, const double *R, int m0, feast_stats &st)
+    // Forward and adjoint solves of a Hermitian pencil are independent (same
+    // factors, separate outputs): in the single-solve path the adjoint ones
+    // run on the side stream with their own scratch, so that each chain's
+    // small in-group products fill the other's gaps.  Executor slots keep
+    // one in-order stream; per-launch timing keeps them in order too, so
+    // that each launch's events time that launch alone.
+    static bool two_streams(const Workspace &ws)
+    {
+        const bool off = std::getenv("FEASTX_SERIAL_SOLVES") != nullptr;   // measurement knob
+        return CPLX && !off && ws.lookahead && ws.side && !ws.noalloc;
+    }
+
+    void solve(Workspace &ws, hipStream_t s, const double *R, int m0, feast_stats &st)
     {
         if (ne == 0) return;
         const size_t cur_nm = (size_t)n * m0;
         dim3 g((unsigned)((cur_nm + 255) / 256), ne);
+        const bool two = two_streams(ws) && Ytmp2 && !g_gemm_timer;
+        hipStream_t sa = two ? ws.side : s;
+        if (two) {
+            FX_CHECK(hipEventRecord(ws.ev_s[0], s));
+            FX_CHECK(hipStreamWaitEvent(sa, ws.ev_s[0], 0));
+        }
+        if (CPLX) {
+            hipLaunchKernelGGL((copy_rhs_kernel<T, CPLX>), g, dim3(256), 0, sa, n, m0, R, (long)n, Yh, (long)n,
+                               (long)cur_nm);
+            FX_LAUNCH_CHECK();
+        }
         hipLaunchKernelGGL((gather_rows_kernel<T, CPLX>), g, dim3(256), 0, s, n, m0, perm, (long)n, R, (long)n, Y,
                            (long)n, (long)cur_nm);
         FX_LAUNCH_CHECK();
-        getrs_batched<T>(s, false, n, m0, F, Wsv, ldf, sF, Linv, Uinv, sInv, Y, Ytmp, n, (long)cur_nm, ne);
+        if (CPLX && two) {
+            // the adjoint chain is queued on the side stream first, then the
+            // forward chain on s; the two queues run at once
+            getrs_batched<T>(sa, true, n, m0, F, Wsv, ldf, sF, Linv, Uinv, sInv, Yh, Ytmp2, n, (long)cur_nm, ne);
+            getrs_batched<T>(s, false, n, m0, F, Wsv, ldf, sF, Linv, Uinv, sInv, Y, Ytmp, n, (long)cur_nm, ne);
+        } else {
+            getrs_batched<T>(s, false, n, m0, F, Wsv, ldf, sF, Linv, Uinv, sInv, Y, Ytmp, n, (long)cur_nm, ne);
+            if (CPLX)
+                getrs_batched<T>(s, true, n, m0, F, Wsv, ldf, sF, Linv, Uinv, sInv, Yh, Ytmp, n, (long)cur_nm, ne);
+        }
         if (CPLX) {
-            hipLaunchKernelGGL((copy_rhs_kernel<T, CPLX>), g, dim3(256), 0, s, n, m0, R, (long)n, Yh, (long)n,
-                               (long)cur_nm);
-            FX_LAUNCH_CHECK();
-            getrs_batched<T>(s, true, n, m0, F, Wsv, ldf, sF, Linv, Uinv, sInv, Yh, Ytmp, n, (long)cur_nm, ne);
-            hipLaunchKernelGGL((scatter_rows_kernel<T>), g, dim3(256), 0, s, n, m0, perm, (long)n, Yh, (long)n,
+            hipLaunchKernelGGL((scatter_rows_kernel<T>), g, dim3(256), 0, sa, n, m0, perm, (long)n, Yh, (long)n,
                                (long)cur_nm, Yh2, (long)n, (long)cur_nm);
             FX_LAUNCH_CHECK();
+        }
+        if (two) {
+            FX_CHECK(hipEventRecord(ws.ev_s[1], sa));
+            FX_CHECK(hipStreamWaitEvent(s, ws.ev_s[1], 0));
         }
         st.solve_flops += (CPLX ? 2.0 : 1.0) * ne * 8.0 * (double)n * n * m0;
     }
@@ -925,8 +965,8 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
         }
 
         // ---- solves at every node (and the adjoint solves for Hermitian pencils)
-        G0.solve(s, reinterpret_cast<const double *>(R), m0, st);
-        G1.solve(s, reinterpret_cast<const double *>(R), m0, st);
+        G0.solve(ws, s, reinterpret_cast<const double *>(R), m0, st);
+        G1.solve(ws, s, reinterpret_cast<const double *>(R), m0, st);
         tm.mark(&st.t_solve);
 
         // ---- quadrature
