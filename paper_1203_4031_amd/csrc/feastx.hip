@@ -151,9 +151,17 @@ struct Workspace {
         FX_CHECK(hipEventCreateWithFlags(&ev_j[1], hipEventDisableTiming));
         FX_CHECK(hipEventCreateWithFlags(&ev_s[0], hipEventDisableTiming));
         FX_CHECK(hipEventCreateWithFlags(&ev_s[1], hipEventDisableTiming));
-        FX_CHECK(hipStreamCreateWithFlags(&aux, hipStreamNonBlocking));
-        FX_CHECK(hipEventCreateWithFlags(&ev_g, hipEventDisableTiming));
         FX_CHECK(hipDeviceSynchronize());
+    }
+    // the aux stream and its event, created at first use (only the
+    // single-solve path asks for them)
+    hipStream_t aux_stream()
+    {
+        if (!aux && !noalloc) {
+            FX_CHECK(hipStreamCreateWithFlags(&aux, hipStreamNonBlocking));
+            FX_CHECK(hipEventCreateWithFlags(&ev_g, hipEventDisableTiming));
+        }
+        return aux;
     }
     void drop_split()
     {
@@ -961,8 +969,9 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
     // N = 8192, Ne = 16: 2 of 16 nodes, factor 433 -> 348 ms; with 5 or 8 of
     // them the groups only compete (the single-solve path only; per-launch
     // timing keeps them in order).
-    const bool groups_together = G0.ne > 0 && G1.ne > 0 && 4 * G1.ne <= G0.ne && ws.lookahead && ws.aux &&
-                                 !g_gemm_timer && std::getenv("FEASTX_SERIAL_GROUPS") == nullptr;
+    const bool groups_together = G0.ne > 0 && G1.ne > 0 && 4 * G1.ne <= G0.ne && ws.lookahead && !ws.noalloc &&
+                                 !g_gemm_timer && std::getenv("FEASTX_SERIAL_GROUPS") == nullptr &&
+                                 ws.aux_stream() != nullptr;
     std::vector<double> lam_prev;   // Ritz values of the previous loop (correction form)
     double prev_maxres = 1e300;     // largest residual in the interval at the previous loop
     double trace_prev = 0.0, epsout = 1.0;
