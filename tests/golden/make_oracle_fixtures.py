@@ -3,6 +3,7 @@
     python tests/golden/make_oracle_fixtures.py realgen_n4096     # about 3 min on 8 cores
     python tests/golden/make_oracle_fixtures.py hermgen_n8192     # about 2.5 h on 6 cores
     python tests/golden/make_oracle_fixtures.py --add-input-samples realgen_n4096
+    python tests/golden/make_oracle_fixtures.py batched_n256      # about 35 min on 8 cores
 
 Calls only the FP64 CPU oracle (oracle/) on inputs from the seeded generators
 (paper_1203_4031_amd/workloads.py, which hold none of the method's
@@ -136,9 +137,84 @@ def add_input_samples(name: str):
     print(f"updated {path}", flush=True)
 
 
+# ---- the batched workload: 256 real generalized problems of uneven N
+BATCHED_STORED_EVERY = 8      # E and res are stored for problems 0, 8, 16, ...
+BATCHED_SAMPLES = 8           # A, B samples per problem
+
+
+def batched_samples(p):
+    rng = np.random.Generator(np.random.PCG64(SAMPLE_SEED))
+    i = rng.integers(0, p.n, BATCHED_SAMPLES)
+    j = rng.integers(0, p.n, BATCHED_SAMPLES)
+    return {"A": p.A[i, j].tolist(), "B": p.B[i, j].tolist()}
+
+
+def batched_inputs_match(p, ref, rtol=1e-12) -> bool:
+    """The regenerated problem agrees with the fixture's entry: X0 to the bit,
+    A and B to rounding at the sampled positions."""
+    if x0_sha256(p) != ref["x0_sha256"] or p.n != ref["n"] or p.m0 != ref["m0"]:
+        return False
+    smp = batched_samples(p)
+    for key, mat in (("A", p.A), ("B", p.B)):
+        if np.max(np.abs(np.array(smp[key]) - np.array(ref["samples"][key]))) > rtol * np.max(np.abs(mat)):
+            return False
+    return True
+
+
+def _batched_one(idx_spec):
+    idx, spec = idx_spec
+    t0 = time.perf_counter()
+    p = W.batched_problem(spec)
+    t_gen = time.perf_counter() - t0
+    oracle._load()
+    t0 = time.perf_counter()
+    r = oracle.feast(p.A, p.B, p.emin, p.emax, p.m0, p.ne, p.tol, p.X0)
+    wall = time.perf_counter() - t0
+    out = {"i": idx, "n": p.n, "m0": p.m0, "count": spec[1], "seed": spec[2], "x0_seed": spec[3],
+           "emin": p.emin, "emax": p.emax, "x0_sha256": x0_sha256(p), "samples": batched_samples(p),
+           "info": r.info, "M": r.M, "loop": r.loop, "oracle_wall_s": wall, "generate_s": t_gen,
+           "max_res": float(np.max(r.res[:r.M])) if r.M > 0 else None}
+    if idx % BATCHED_STORED_EVERY == 0:
+        out["E"] = [float(x) for x in r.E[:r.M]]
+        out["res"] = [float(x) for x in r.res[:r.M]]
+    return out
+
+
+def batched(workers: int):
+    """The oracle on every problem of the batched workload, one problem per
+    single-threaded worker process at a time."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[k] = "1"
+    specs = W.batched_specs()
+    t0 = time.perf_counter()
+    results = []
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        for r in ex.map(_batched_one, list(enumerate(specs)), chunksize=1):
+            results.append(r)
+            print(f"problem {r['i']}: n {r['n']} M {r['M']} info {r['info']} loops {r['loop'] + 1} "
+                  f"{r['oracle_wall_s']:.1f} s", flush=True)
+    wall = time.perf_counter() - t0
+    out = {"workload": "batched_n256", "problems": len(specs), "ne": 8, "tol": 1e-10,
+           "stored_every": BATCHED_STORED_EVERY, "sample_seed": SAMPLE_SEED,
+           "oracle_cpu_s": sum(r["oracle_wall_s"] for r in results), "wall_s": wall,
+           "workers": workers, "threads_per_worker": 1, "nproc": os.cpu_count(), "cpu": cpu_model(),
+           "written": time.strftime("%Y-%m-%d"), "entries": results}
+    path = os.path.join(HERE, "oracle_batched_n256.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=0)
+        f.write("\n")
+    print(f"wrote {path}: {len(results)} problems, {wall:.0f} s wall on {workers} workers", flush=True)
+
+
 def main():
     if sys.argv[1] == "--add-input-samples":
         add_input_samples(sys.argv[2])
+        return
+    if sys.argv[1] == "batched_n256":
+        batched(int(sys.argv[2]) if len(sys.argv) > 2 else (os.cpu_count() or 1))
         return
     name = sys.argv[1]
     t0 = time.perf_counter()
