@@ -53,7 +53,7 @@ struct Workspace {
     std::map<std::string, std::pair<void *, size_t>> dev;
     std::map<std::string, std::pair<void *, size_t>> host;
     hipStream_t stream = nullptr;
-    hipStream_t side = nullptr;            // look-ahead panels of the LU
+    hipStream_t side = nullptr;            // look-ahead panels of the LU, adjoint solves (side_stream())
     hipEvent_t ev_a = nullptr, ev_b = nullptr;
     // Factorisation on a split of the CUs: the trailing updates on `fmain`,
     // the look-ahead panels on `fside`, which owns `fres` CUs per XCD that
@@ -141,7 +141,6 @@ struct Workspace {
         if (noalloc || stream) return;
         FX_CHECK(hipGetDevice(&device));
         FX_CHECK(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
-        FX_CHECK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
         FX_CHECK(hipEventCreateWithFlags(&ev_a, hipEventDisableTiming));
         FX_CHECK(hipEventCreateWithFlags(&ev_b, hipEventDisableTiming));
         hipDeviceProp_t prop;
@@ -153,8 +152,15 @@ struct Workspace {
         FX_CHECK(hipEventCreateWithFlags(&ev_s[1], hipEventDisableTiming));
         FX_CHECK(hipDeviceSynchronize());
     }
-    // the aux stream and its event, created at first use (only the
-    // single-solve path asks for them)
+    // The side and aux streams are created at first use: only the single-
+    // solve path asks for them.  An executor slot then owns one stream, so
+    // the slots' streams spread over the device's hardware queues instead
+    // of alternating with streams that are never used.
+    hipStream_t side_stream()
+    {
+        if (!side && !noalloc) FX_CHECK(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+        return side;
+    }
     hipStream_t aux_stream()
     {
         if (!aux && !noalloc) {
@@ -772,8 +778,8 @@ template <typename T, bool CPLX> struct NodeGroup {
             FX_CHECK(hipEventRecord(ws.ev_d, ws.fmain));
             FX_CHECK(hipStreamWaitEvent(s, ws.ev_d, 0));
         } else {
-            getrf_batched<T>(s, la ? ws.side : nullptr, ws.ev_a, ws.ev_b, n, F, ldf, sF, ipiv, perm, n, swapmap,
-                             dinfo, ne);
+            getrf_batched<T>(s, la ? ws.side_stream() : nullptr, ws.ev_a, ws.ev_b, n, F, ldf, sF, ipiv, perm, n,
+                             swapmap, dinfo, ne);
         }
         if (g_gemm_timer) g_gemm_timer->lu = false;
         solve_inverses<T>(s, n, F, ldf, sF, L64, U64, sI64, Linv, Uinv, sInv, Itmp, sItmp, ne);
@@ -802,7 +808,7 @@ template <typename T, bool CPLX> struct NodeGroup {
     static bool two_streams(const Workspace &ws)
     {
         const bool off = std::getenv("FEASTX_SERIAL_SOLVES") != nullptr;   // measurement knob
-        return CPLX && !off && ws.lookahead && ws.side && !ws.noalloc;
+        return CPLX && !off && ws.lookahead && !ws.noalloc;
     }
 
     void solve(Workspace &ws, hipStream_t s, const double *R, int m0, feast_stats &st)
@@ -811,7 +817,7 @@ template <typename T, bool CPLX> struct NodeGroup {
         const size_t cur_nm = (size_t)n * m0;
         dim3 g((unsigned)((cur_nm + 255) / 256), ne);
         const bool two = two_streams(ws) && Ytmp2 && !g_gemm_timer;
-        hipStream_t sa = two ? ws.side : s;
+        hipStream_t sa = two ? ws.side_stream() : s;
         if (two) {
             FX_CHECK(hipEventRecord(ws.ev_s[0], s));
             FX_CHECK(hipStreamWaitEvent(sa, ws.ev_s[0], 0));

@@ -72,7 +72,8 @@ static void time_variants(hipStream_t s, int nt, int mt, int batch, cplx<T> *F, 
 static TileTimes autotune(int n, int m0, int ne)
 {
     const int nt = std::min(n, 4096), mt = std::min(std::max(m0, 32), nt), batch = std::min(ne, 8);
-    const size_t bytes_f = sizeof(double2) * (size_t)nt * nt * batch, bytes_y = sizeof(double2) * (size_t)nt * mt * batch;
+    const size_t bytes_f = sizeof(double2) * (size_t)nt * nt * batch;
+    const size_t bytes_y = sizeof(double2) * (size_t)nt * mt * batch;
     void *F = nullptr, *Y = nullptr;
     hipStream_t s = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
