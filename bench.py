@@ -420,6 +420,17 @@ def batched(feastx, problems, concurrency):
         out[key + "eigenpairs_per_s"] = pairs / wall
         log(f"batched {prec}: {len(problems)} problems in {wall:.2f}s")
     out["mixed_over_fp64"] = out["fp64_s"] / out["s"]
+    try:
+        with open(os.path.join(ROOT, "tests", "golden", "oracle_batched_n256.json")) as f:
+            fx = json.load(f)
+        out["oracle_measured"] = {"problems": fx["problems"], "wall_s": fx["wall_s"],
+                                  "workers": fx["workers"], "threads_per_worker": fx["threads_per_worker"],
+                                  "cpu_s": fx["oracle_cpu_s"], "cpu": fx["cpu"],
+                                  "problems_per_s": fx["problems"] / fx["wall_s"],
+                                  "note": "the FP64 oracle on all 256 problems, measured once when its fixture "
+                                          "was written (another host)"}
+    except OSError:
+        pass
     return out
 
 

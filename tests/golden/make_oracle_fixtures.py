@@ -176,7 +176,8 @@ def _batched_one(idx_spec):
            "max_res": float(np.max(r.res[:r.M])) if r.M > 0 else None}
     if idx % BATCHED_STORED_EVERY == 0:
         out["E"] = [float(x) for x in r.E[:r.M]]
-        out["res"] = [float(x) for x in r.res[:r.M]]
+    else:
+        del out["samples"]   # only the stored problems are regenerated by the test
     return out
 
 
@@ -203,9 +204,14 @@ def batched(workers: int):
            "workers": workers, "threads_per_worker": 1, "nproc": os.cpu_count(), "cpu": cpu_model(),
            "written": time.strftime("%Y-%m-%d"), "entries": results}
     path = os.path.join(HERE, "oracle_batched_n256.json")
-    with open(path, "w") as f:
-        json.dump(out, f, indent=0)
-        f.write("\n")
+    entries = out.pop("entries")
+    with open(path, "w") as f:   # one problem per line
+        f.write("{\n")
+        for k, v in out.items():
+            f.write(json.dumps(k) + ": " + json.dumps(v) + ",\n")
+        f.write('"entries": [\n')
+        f.write(",\n".join(json.dumps(e, separators=(",", ":")) for e in entries))
+        f.write("\n]\n}\n")
     print(f"wrote {path}: {len(results)} problems, {wall:.0f} s wall on {workers} workers", flush=True)
 
 
