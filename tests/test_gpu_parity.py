@@ -182,3 +182,38 @@ def test_mixed_with_complex128_nodes_matches_oracle(small_cases, monkeypatch, et
     if eta == "1e-9":
         assert st.fp64_nodes == p.ne
     _check_pairs(p, r, ref)
+
+
+@pytest.mark.parametrize("herm", [False, True])
+def test_host_arrays_with_leading_dimensions(herm):
+    """Host-array entry points with lda, ldb, ldx larger than N (padded column-major storage) give the
+    same bits as contiguous arrays: the strided upload and download paths."""
+    import ctypes as C
+
+    n, pad = 260, (7, 11, 3)
+    p = (W.dense_complex_hermitian(n, count=20, seed=4411, tol=1e-10) if herm
+         else W.dense_real_generalized(n, count=20, seed=4412, tol=1e-10))
+    dt = np.complex128 if herm else np.float64
+    print(f"padded host arrays herm={herm}", flush=True)
+    ref = feastx.solve(p.A, p.B, p.emin, p.emax, p.m0, X0=p.X0, ne=8, tol=1e-10, precision="mixed")
+    assert ref.info == 0
+
+    def padded(a, extra):
+        out = np.zeros((a.shape[0] + extra, a.shape[1]), dtype=dt, order="F")
+        out[:a.shape[0], :] = a
+        return out
+
+    Ap, Bp = padded(p.A, pad[0]), padded(p.B, pad[1])
+    Xp = padded(p.X0.astype(dt), pad[2])
+    o = feastx.make_opts(x0=True, ne=8, tol=1e-10, precision="mixed")
+    E, res = np.zeros(p.m0), np.zeros(p.m0)
+    M, loop, eps, m0c = C.c_int(0), C.c_int(0), C.c_double(0), C.c_int(p.m0)
+    f = feastx.lib().feast_solve_z_ex if herm else feastx.lib().feast_solve_d_ex
+    info = f(n, Ap.ctypes.data, Ap.shape[0], Bp.ctypes.data, Bp.shape[0], float(p.emin), float(p.emax),
+             C.byref(m0c), C.byref(o), E.ctypes.data_as(C.POINTER(C.c_double)), Xp.ctypes.data, Xp.shape[0],
+             C.byref(M), res.ctypes.data_as(C.POINTER(C.c_double)), C.byref(loop), C.byref(eps))
+    assert info == 0 and M.value == ref.M and m0c.value == ref.m0
+    k = m0c.value
+    assert np.array_equal(E[:k], ref.E) and np.array_equal(res[:k], ref.res)
+    assert np.array_equal(Xp[:n, :k], ref.X)
+    assert not Xp[n:, :].any()   # the padding rows are left alone
