@@ -632,6 +632,8 @@ def main():
     # installed as given (profiler passes repeat a measured table)
     if args.tiles:
         v = [int(x) for x in args.tiles.split(",")]
+        if len(v) != 4:
+            raise SystemExit("--tiles takes four variants: c64 depth<=64, c64 deeper, c128 depth<=64, c128 deeper")
         feastx.set_tiles({"complex64": {"depth<=64": v[0], "deeper": v[1]},
                           "complex128": {"depth<=64": v[2], "deeper": v[3]}})
         tune = {"choice": feastx.tiles(), "installed": "--tiles"}
