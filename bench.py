@@ -638,7 +638,10 @@ def main():
                           "complex128": {"depth<=64": v[2], "deeper": v[3]}})
         tune = {"choice": feastx.tiles(), "installed": "--tiles"}
     else:
-        tune = feastx.autotune(8192, 600, 16)
+        try:
+            tune = feastx.autotune(8192, 600, 16)
+        except RuntimeError as e:   # the defaults stay installed
+            tune = {"choice": feastx.tiles(), "error": str(e)}
     log(f"tiles: {tune['choice']}")
     if args.only == "nonhermitian":
         print(json.dumps(nonhermitian(feastx, W, steps=max(args.steps, 1))), flush=True)
