@@ -4,6 +4,7 @@
     python tests/golden/make_oracle_fixtures.py hermgen_n8192     # about 2.5 h on 6 cores
     python tests/golden/make_oracle_fixtures.py --add-input-samples realgen_n4096
     python tests/golden/make_oracle_fixtures.py batched_n256      # about 35 min on 8 cores
+    python tests/golden/make_oracle_fixtures.py serving_sample    # about 25 min on 8 cores
 
 Calls only the FP64 CPU oracle (oracle/) on inputs from the seeded generators
 (paper_1203_4031_amd/workloads.py, which hold none of the method's
@@ -215,7 +216,103 @@ def batched(workers: int):
     print(f"wrote {path}: {len(results)} problems, {wall:.0f} s wall on {workers} workers", flush=True)
 
 
+# ---- the serving workload: a systematic sample of its request stream
+SERVING_POOL = {512: 2, 1024: 2, 2048: 2, 4096: 1, 8192: 1}   # the bench's pool sizes
+SERVING_EVERY, SERVING_STORED_EVERY, SERVING_MAX_N = 5, 50, 2048
+
+
+def serving_stream():
+    """The bench's 2000 requests (Poisson 200/s, p(N) ~ N^-2, seed 5000); the
+    N = 8192 pool matrix is the headline pencil."""
+    spectra = {}
+    for n, cnt in SERVING_POOL.items():
+        for k in range(cnt):
+            if n == 8192:
+                spectra[(n, k)] = W.dense_complex_hermitian(8192, 400, m0=600, ne=16, tol=1e-10,
+                                                            seed=3001).spectrum
+            else:
+                spectra[(n, k)] = W.serving_pool_matrix(n, k)[2]
+    return W.serving_requests(spectra, 2000, SERVING_POOL)
+
+
+_pool_cache = {}
+
+
+def _serving_one(idx_req):
+    idx, q = idx_req
+    key = (q["n"], q["k"])
+    if key not in _pool_cache:
+        _pool_cache[key] = W.serving_pool_matrix(*key)
+    A, B, _ = _pool_cache[key]
+    X0 = W.start_subspace(q["n"], q["m0"], q["x0_seed"])
+    oracle._load()
+    t0 = time.perf_counter()
+    r = oracle.feast(A, B, q["emin"], q["emax"], q["m0"], q["ne"], q["tol"], X0, hermitian=True)
+    wall = time.perf_counter() - t0
+    out = {"i": idx, "n": q["n"], "k": q["k"], "count": q["count"], "m0": q["m0"], "emin": q["emin"],
+           "emax": q["emax"], "x0_seed": q["x0_seed"], "info": r.info, "M": r.M, "loop": r.loop,
+           "oracle_wall_s": wall}
+    if idx % SERVING_STORED_EVERY == 0:
+        out["E"] = [float(x) for x in r.E[:r.M]]
+        rng = np.random.Generator(np.random.PCG64(SAMPLE_SEED))
+        i, j = rng.integers(0, q["n"], BATCHED_SAMPLES), rng.integers(0, q["n"], BATCHED_SAMPLES)
+        out["samples"] = {"A_re": np.real(A[i, j]).tolist(), "A_im": np.imag(A[i, j]).tolist(),
+                          "B_re": np.real(B[i, j]).tolist(), "B_im": np.imag(B[i, j]).tolist()}
+    return out
+
+
+def serving_sample_matches(A, B, ref, rtol=1e-12) -> bool:
+    """A regenerated pool matrix agrees with a stored request's samples to rounding."""
+    rng = np.random.Generator(np.random.PCG64(SAMPLE_SEED))
+    n = A.shape[0]
+    i, j = rng.integers(0, n, BATCHED_SAMPLES), rng.integers(0, n, BATCHED_SAMPLES)
+    for key, mat in (("A", A), ("B", B)):
+        want = np.array(ref["samples"][key + "_re"]) + 1j * np.array(ref["samples"][key + "_im"])
+        if np.max(np.abs(mat[i, j] - want)) > rtol * np.max(np.abs(mat)):
+            return False
+    return True
+
+
+def serving_sample(workers: int):
+    """The oracle on every fifth request of the serving stream with N <= 2048
+    (single-threaded workers), eigenvalues stored for every fiftieth."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+
+    reqs = serving_stream()
+    pick = [(i, q) for i, q in enumerate(reqs) if i % SERVING_EVERY == 0 and q["n"] <= SERVING_MAX_N]
+    print(f"{len(pick)} sampled requests of {len(reqs)}", flush=True)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[k] = "1"
+    t0 = time.perf_counter()
+    results = []
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        for r in ex.map(_serving_one, pick, chunksize=1):
+            results.append(r)
+            print(f"request {r['i']}: n {r['n']} M {r['M']} info {r['info']} loops {r['loop'] + 1} "
+                  f"{r['oracle_wall_s']:.1f} s", flush=True)
+    wall = time.perf_counter() - t0
+    out = {"workload": "serving_sample", "requests_in_stream": len(reqs), "sampled": len(results),
+           "every": SERVING_EVERY, "max_n": SERVING_MAX_N, "stored_every": SERVING_STORED_EVERY,
+           "pool": {str(n): c for n, c in SERVING_POOL.items()}, "sample_seed": SAMPLE_SEED,
+           "oracle_cpu_s": sum(r["oracle_wall_s"] for r in results), "wall_s": wall, "workers": workers,
+           "threads_per_worker": 1, "nproc": os.cpu_count(), "cpu": cpu_model(),
+           "written": time.strftime("%Y-%m-%d")}
+    path = os.path.join(HERE, "oracle_serving_sample.json")
+    with open(path, "w") as f:   # one request per line
+        f.write("{\n")
+        for k, v in out.items():
+            f.write(json.dumps(k) + ": " + json.dumps(v) + ",\n")
+        f.write('"entries": [\n')
+        f.write(",\n".join(json.dumps(e, separators=(",", ":")) for e in results))
+        f.write("\n]\n}\n")
+    print(f"wrote {path}: {len(results)} requests, {wall:.0f} s wall on {workers} workers", flush=True)
+
+
 def main():
+    if sys.argv[1] == "serving_sample":
+        serving_sample(int(sys.argv[2]) if len(sys.argv) > 2 else (os.cpu_count() or 1))
+        return
     if sys.argv[1] == "--add-input-samples":
         add_input_samples(sys.argv[2])
         return
