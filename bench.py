@@ -291,7 +291,11 @@ def measure_single(feastx, torch, p, steps, warmup, roofline_steps, traffic_key,
     }
     upd = lu[4] / (lu[3] * 1e-3) / 1e12 if lu[3] > 0 else 0.0
     fac = lu[7] / (lu[6] * 1e-3) / 1e12 if lu[6] > 0 else 0.0
-    out["shifted_lu"] = {"precision": best, "update_achieved": upd, "update_frac": upd / peak,
+    blocks = np.array_equal(feastx.lu_schedule(p.n, True), feastx.lu_schedule(p.n, True, "blocks"))
+    out["shifted_lu"] = {"precision": best,
+                         "schedule": ("blocks of four panels (depth-128 trailing products)" if blocks
+                                      else "panels in pairs (depth-64 trailing products)"),
+                         "update_achieved": upd, "update_frac": upd / peak,
                          "update_launches": lu[5], "unit": "TFLOP/s", "peak": peak,
                          "factor_ms": lu[6] / max(roofline_steps, 1),
                          "factor_rate": fac, "factor_frac": fac / peak,

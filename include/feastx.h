@@ -342,8 +342,9 @@ void feast_set_timing(int on);
  * The complex products (LU updates, triangular-solve updates, Rayleigh-Ritz)
  * have FEAST_TILE_VARIANTS tile shapes per precision; which one runs is read
  * from a process-wide table indexed by precision (0 complex64, 1 complex128)
- * and depth class (0: depth <= 64, the LU and Cholesky updates; 1: deeper,
- * the solve updates and Rayleigh-Ritz products).  Variant 0 is the default.
+ * and depth class (0: depth <= 64, the LU's panel-by-panel updates and the
+ * Cholesky updates; 1: deeper, the LU's 128-deep block updates, the solve
+ * updates and the Rayleigh-Ritz products).  Variant 0 is the default.
  * Every variant accumulates each output over the depth in the same order, so
  * the table changes times, never results. */
 #define FEAST_TILE_VARIANTS 3
@@ -354,9 +355,11 @@ typedef struct {
 } feast_tiles;
 /* Time every variant on the current device on the shapes of a solve of order
  * n with m0 right-hand sides and ne contour nodes (capped at n = 4096 and
- * ne = 8 to bound the scratch: one depth-64 trailing update of n - 64 rows
- * and columns, one depth-256 solve update with m0 columns, batch ne), install
- * the fastest per precision and class in the table (a variant replaces the
+ * ne = 8 to bound the scratch; class 0: one depth-64 trailing update of
+ * n - 64 rows and columns; class 1: one depth-128 trailing update of n - 128
+ * rows and columns together with one depth-256 solve update with m0 columns;
+ * batch ne), install the fastest per precision and class in the table (a
+ * variant replaces the
  * default only when at least 5 % faster), and return both in *out (may be
  * NULL).  Allocates and frees its own device scratch (up to about 2.2 GB).
  * Not to be called while solves run on other threads.  Returns 0, 202 (n < 64),
@@ -364,6 +367,35 @@ typedef struct {
 int feast_autotune(int n, int m0, int ne, feast_tiles *out);
 /* The current table (tflops zero). */
 void feast_get_tiles(feast_tiles *out);
+
+/* ---- the factorisation's launch schedule (host logic only; no device call).
+ * The shifted LU of every contour node (the factorisation step of the FEAST
+ * loop, "The FEAST Algorithm") is issued as a fixed list of steps that
+ * depends only on n, on whether a second (panel) stream is used and on the
+ * form.  form: -1 the schedule the library runs for this n (see
+ * feast_set_lu_form), 0 panels in pairs (depth-64
+ * trailing products), 1 panels in blocks of four (depth-128 trailing
+ * products).  This writes the first min(cap, count) steps into ops
+ * (FEAST_LU_OP_INTS ints each, caller-owned; ops may be NULL) and returns
+ * the count, or -1 for n < 1 or another form.  Step layout: kind (0 panel factorisation of columns k..k+nbw-1,
+ * 1 row interchanges / U rows, 2 trailing product, 3 event record, 4 stream
+ * wait), side (1: the panel stream), k, nbw, c0, c1, c2, c3 (kind 1: the
+ * column ranges [c0, c1) and [c2, c3); kind 2: rows [c0, c1), columns
+ * [c2, c3)), kc0, kc1 (kind 1: rows of the earlier panels' correction;
+ * kind 2: the product's depth range), mode (kind 1: 1 interchanges, 2 U
+ * rows, 4 correction), list (the move list written or read).  For tests
+ * that replay the schedule on the host. */
+#define FEAST_LU_OP_INTS 12
+int feast_lu_schedule(int n, int side, int form, int *ops, int cap);
+/* The schedule every later factorisation uses: -1 (the default) pairs below
+ * n = 6144 and blocks from there, 0 pairs, 1 blocks.  Both factor with
+ * partial pivoting and give the same factors up to rounding; the choice is
+ * one of speed (blocks: deeper trailing products; pairs: a shorter panel
+ * chain).  Returns 0, or -1 for another value (nothing changed).  Not to be
+ * changed while solves run on other threads. */
+int feast_set_lu_form(int form);
+/* The current setting (-1, 0 or 1). */
+int feast_get_lu_form(void);
 /* Install a table (choices only); 0, or -101 for NULL / an out-of-range entry. */
 int feast_set_tiles(const feast_tiles *tiles);
 /* Free the calling thread's context (device workspace and streams). */

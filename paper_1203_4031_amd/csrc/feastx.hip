@@ -730,7 +730,7 @@ template <typename T, bool CPLX> struct NodeGroup {
         F = static_cast<V *>(ws.get("F" + p, sizeof(V) * (size_t)ne * sF));
         ipiv = static_cast<int *>(ws.get("ipiv" + p, sizeof(int) * (size_t)ne * n));
         perm = static_cast<int *>(ws.get("perm" + p, sizeof(int) * (size_t)ne * n));
-        swapmap = static_cast<int *>(ws.get("swapmap" + p, sizeof(int) * 2 * (size_t)ne * (1 + 4 * LU_NB)));
+        swapmap = static_cast<int *>(ws.get("swapmap" + p, sizeof(int) * LU_LISTS * (size_t)ne * LU_LIST_INTS));
         dinfo = static_cast<int *>(ws.get("info" + p, sizeof(int) * ne));
         const bool compose = solve_nb<T>() > TRI_INV_NB;   // 128-row solve blocks from 64-row inverses
         sI64 = compose ? tri_inv_stride(n) : 0;
@@ -1390,7 +1390,7 @@ static int run_general(const GProblem &pb, const feast_opts &o, hipStream_t s, W
     V *F = static_cast<V *>(ws.get(mixed ? "F32" : "F64", sizeof(V) * (size_t)ne * sF));
     int *ipiv = static_cast<int *>(ws.get("ipiv", sizeof(int) * (size_t)ne * n));
     int *perm = static_cast<int *>(ws.get("perm", sizeof(int) * (size_t)ne * n));
-    int *swapmap = static_cast<int *>(ws.get("swapmap", sizeof(int) * 2 * (size_t)ne * (1 + 4 * LU_NB)));
+    int *swapmap = static_cast<int *>(ws.get("swapmap", sizeof(int) * LU_LISTS * (size_t)ne * LU_LIST_INTS));
     int *dinfo = static_cast<int *>(ws.get("info", sizeof(int) * ne));
     const bool compose = solve_nb<T>() > TRI_INV_NB;
     const long sI64 = compose ? tri_inv_stride(n) : 0, sInv = solve_inv_stride<T>(n);
@@ -2829,6 +2829,31 @@ int feast_autotune(int n, int m0, int ne, feast_tiles *out)
         std::fprintf(stderr, "feastx: HIP error %s in feast_autotune\n", hipGetErrorString(e.code));
         return -4;
     }
+}
+
+int feast_set_lu_form(int form)
+{
+    if (form < -1 || form > 1) return -1;
+    fx::g_lu_form.store(form);
+    return 0;
+}
+
+int feast_get_lu_form(void) { return fx::g_lu_form.load(); }
+
+int feast_lu_schedule(int n, int side, int form, int *ops, int cap)
+{
+    if (n < 1 || form < -1 || form > 1) return -1;
+    const std::vector<fx::LuOp> v = fx::lu_schedule(n, side != 0, form);
+    if (ops && cap > 0) {
+        const int m = std::min(cap, (int)v.size());
+        for (int i = 0; i < m; ++i) {
+            const fx::LuOp &o = v[i];
+            const int row[fx::LU_OP_INTS] = {o.kind, o.side, o.k, o.nbw, o.c0, o.c1,
+                                             o.c2,   o.c3,   o.kc0, o.kc1, o.mode, o.list};
+            std::copy(row, row + fx::LU_OP_INTS, ops + (size_t)i * fx::LU_OP_INTS);
+        }
+    }
+    return (int)v.size();
 }
 
 void feast_get_tiles(feast_tiles *out)

@@ -11,6 +11,10 @@
 // straight into the factor storage.
 #pragma once
 
+#include <algorithm>
+#include <atomic>
+#include <vector>
+
 #include "common.hpp"
 #include "gemm.hpp"
 
@@ -506,11 +510,12 @@ __global__ __launch_bounds__(256) void lu_swap_trsm_kernel(int n, cplx<T> *__res
         const int i = g + 4 * j;
         xr[j] = (colok && i < nbw) ? pc[i] : cmake<V>(0, 0);
     }
-    // correction rows of the solve column (rows kc0..kc1, final before this launch)
+    // correction rows of the solve column (rows kc0..kc1, final before this
+    // launch), NB at a time; the first NB are fetched here
     const int kw = (mode & 4) ? kc1 - kc0 : 0;
     V u0[CORR_MODE ? NB : 1];
+    const V *pu = a + (long)(colok ? col_of(soc) : 0) * ldf + kc0;
     if constexpr (CORR_MODE) {
-        const V *pu = a + (long)(colok ? col_of(soc) : 0) * ldf + kc0;
 #pragma unroll
         for (int q = 0; q < NB; ++q) u0[q] = (colok && q < kw) ? pu[q] : cmake<V>(0, 0);
     }
@@ -541,10 +546,11 @@ __global__ __launch_bounds__(256) void lu_swap_trsm_kernel(int n, cplx<T> *__res
     }
 
     // 4. U12 = L11^{-1} A12, column-oriented forward substitution, after
-    //    the correction of the top rows by an earlier panel when asked
-    //    (mode bit 2): rows k.. -= F[k.., kc0:kc1] F[kc0:kc1, col].  Those
-    //    L rows are read back after this launch's moves are stored, so
-    //    they may be columns of this launch, handled by this block.
+    //    the correction of the top rows by earlier panels when asked (mode
+    //    bit 2): rows k.. -= F[k.., kc0:kc1] F[kc0:kc1, col], up to three
+    //    panels deep, NB correction rows at a time.  Those L rows are read
+    //    back after this launch's moves are stored, so they may be columns
+    //    of this launch, handled by this block.
     if (right) {
 #pragma unroll
         for (int j = 0; j < NB / 4; ++j) {
@@ -555,11 +561,15 @@ __global__ __launch_bounds__(256) void lu_swap_trsm_kernel(int n, cplx<T> *__res
             }
         }
         if constexpr (CORR_MODE) {
-            if (kw > 0) {
-                __syncthreads();
+            for (int q0 = 0; q0 < kw; q0 += NB) {   // uniform
+                if (q0 > 0) {
+#pragma unroll
+                    for (int q = 0; q < NB; ++q) u0[q] = (colok && q0 + q < kw) ? pu[q0 + q] : cmake<V>(0, 0);
+                }
+                __syncthreads();   // the previous chunk's reads of Lc are done
                 for (int e = tid; e < NB * NB; e += 256) {
                     const int i = e % NB, q = e / NB;
-                    Lc[i][q] = (i < nbw && q < kw) ? a[(k + i) + (long)(kc0 + q) * ldf] : cmake<V>(0, 0);
+                    Lc[i][q] = (i < nbw && q0 + q < kw) ? a[(k + i) + (long)(kc0 + q0 + q) * ldf] : cmake<V>(0, 0);
                 }
                 __syncthreads();
 #pragma unroll
@@ -651,6 +661,10 @@ static void launch_panel_rows(hipStream_t s, int n, cplx<T> *F, long ldf, long s
 }
 
 constexpr int LU_SWAP = 1, LU_TRSM = 2, LU_CORR = 4;
+constexpr int LU_QB = 4;                     // panels per block of the blocked schedule
+constexpr int LU_CORR_MAX = (LU_QB - 1) * LU_NB;
+constexpr int LU_LISTS = 2 * LU_QB;          // move lists live at once (two blocks)
+constexpr int LU_LIST_INTS = 1 + 4 * LU_NB;  // one move list of one matrix
 
 // mode LU_CORR (with LU_TRSM): before the U-row solve, the top rows of the
 // solved columns get -= F[k:k+nbw, kc0:kc1] F[kc0:kc1, col].  When those L
@@ -664,7 +678,7 @@ static void swap_trsm(hipStream_t s, int n, cplx<T> *F, long ldf, long sF, int k
     dim3 grid(ceil_div(ncols, 64), batch);
     if (mode & LU_CORR) {
         const bool inside = (kc0 < c1 && kc1 > c0) || (kc0 < c3 && kc1 > c2);
-        if (!(mode & LU_TRSM) || kc1 - kc0 > LU_NB || kc1 < kc0 || kc1 > k || (inside && ncols > 64))
+        if (!(mode & LU_TRSM) || kc1 - kc0 > LU_CORR_MAX || kc1 < kc0 || kc1 > k || (inside && ncols > 64))
             throw hip_error{hipErrorInvalidValue};
         hipLaunchKernelGGL((lu_swap_trsm_kernel<T, LU_NB, true>), grid, dim3(256), 0, s, n, F, ldf, sF, k, nbw, c0,
                            c1, c2, c3, kc0, kc1, mode, swapmap);
@@ -685,97 +699,256 @@ static void lu_gemm(hipStream_t s, cplx<T> *F, long ldf, long sF, int r0, int r1
                          F + kc0 + (long)c0 * ldf, ldf, sF, T(1), F + r0 + (long)c0 * ldf, ldf, sF, batch);
 }
 
-// Factor `batch` matrices of order n (stride sF, leading dimension ldf) in
-// place.  ipiv/perm: n ints per matrix (stride sPiv).  swapmap: 2 (1 + 4 NB)
-// ints per matrix of scratch.  info: one int per matrix, 0 on success, else
-// 1 + the first zero/non-finite pivot index.
-//
-// Panels are NB = 32 columns wide and taken in pairs (k0, k1 = k0 + 32).
-// The far trailing update of a pair is one product of depth 64 instead of
-// two of depth 32, which halves the trailing-matrix traffic.  Per pair:
+// One step of the factorisation's launch schedule (host logic, no device
+// state): the executor below turns it into a launch, the host-side tests
+// replay it.  kind: LU_OP_PANEL factors columns k..k+nbw-1 (rows k..n-1)
+// and writes move list `list`; LU_OP_SWAP is swap_trsm() with that list;
+// LU_OP_GEMM is F[c0:c1, c2:c3] -= F[c0:c1, kc0:kc1] F[kc0:kc1, c2:c3] (c0,
+// c1 the row range); LU_OP_RECORD / LU_OP_WAIT order the two streams
+// (`side` records, the other stream waits).  side: 1 for the panel stream.
+enum { LU_OP_PANEL = 0, LU_OP_SWAP = 1, LU_OP_GEMM = 2, LU_OP_RECORD = 3, LU_OP_WAIT = 4 };
+struct LuOp {
+    int kind, side, k, nbw, c0, c1, c2, c3, kc0, kc1, mode, list;
+};
+constexpr int LU_OP_INTS = 12;
+
+// The blocked right-looking schedule.  Panels are NB = 32 columns wide and
+// grouped in blocks of QB = 4 (128 columns).  Each block updates most of the
+// trailing matrix with one product of depth 128, where a panel-by-panel
+// update would take four of depth 32.  For block B (columns b..e; f = e + NB
+// ends the next block's first panel):
+//   * N_j, after panel j of B: panel j's interchanges on B's columns left of
+//     it; on the columns right of it up to f, the interchanges, its U rows
+//     (swap_trsm) and the depth-32 update of the rows below.  This keeps B's
+//     next panel and the next block's first panel current (right-looking).
+//   * The previous block P (pb..b) finishes on the columns N_j of P did not
+//     reach, in three parts: beside B's panel 0, P's interchanges, U rows
+//     (corrected by P's earlier panels, mode LU_CORR) and depth-128 update
+//     on columns b + NB .. f (needed by B's N_0); after N_0, the same
+//     interchanges and U rows on the columns left of P and past f; then
+//     the depth-128 product past f in QB - 1 column chunks, one beside each
+//     of B's later panels.
+// Only the panels run on the panel stream; every other step is on the main
+// stream, so that the wide products keep the whole device.  A row
+// permutation commutes with a row-wise update as long as the update's L rows
+// get it too.  That is why a block's interchanges can reach the far columns
+// after later panels are factored: the far columns and the L columns of
+// earlier blocks get each block's interchanges in block order.  Move lists:
+// four per block, the two most recent blocks' live at once.  Without a panel
+// stream (side = false) the same steps run in the same order on one stream,
+// and the records and waits are left out.
+inline std::vector<LuOp> lu_schedule_blocks(int n, bool side)
+{
+    constexpr int NB = LU_NB, BW = LU_QB * LU_NB;
+    std::vector<LuOp> ops;
+    auto add = [&](LuOp o) { ops.push_back(o); };
+    auto record = [&](int sd) {
+        if (side) add({LU_OP_RECORD, sd, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0});
+    };
+    auto wait = [&](int sd) {
+        if (side) add({LU_OP_WAIT, sd, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0});
+    };
+    auto list_of = [](int B, int j) { return (B & 1) * LU_QB + j; };
+    auto panel = [&](int B, int j, int k) {   // on the panel stream, after the main stream's work so far
+        record(0);
+        wait(1);
+        add({LU_OP_PANEL, side ? 1 : 0, k, std::min(NB, n - k), 0, 0, 0, 0, 0, 0, 0, list_of(B, j)});
+        record(1);
+    };
+    auto swap = [&](int B, int j, int k, int nbw, int c0, int c1, int c2, int c3, int mode, int kc0) {
+        c1 = std::max(c0, c1);
+        c3 = std::max(c2, c3);
+        if (c1 - c0 + c3 - c2 <= 0) return;
+        if (!(mode & LU_TRSM) || kc0 >= k) mode &= ~LU_CORR;
+        add({LU_OP_SWAP, 0, k, nbw, c0, c1, c2, c3, (mode & LU_CORR) ? kc0 : 0, (mode & LU_CORR) ? k : 0, mode,
+             list_of(B, j)});
+    };
+    auto gemm = [&](int r0, int r1, int c0, int c1, int kc0, int kc1) {
+        if (r1 <= r0 || c1 <= c0 || kc1 <= kc0) return;
+        add({LU_OP_GEMM, 0, 0, 0, r0, r1, c0, c1, kc0, kc1, 0, 0});
+    };
+    const int nblk = ceil_div(n, BW);
+    for (int B = 0; B < nblk; ++B) {
+        const int b = B * BW, e = std::min(n, b + BW), f = std::min(n, e + NB);
+        const int np = ceil_div(e - b, NB);
+        panel(B, 0, b);
+        // the previous block P (pb..b, four full panels): its interchanges,
+        // U rows and depth-128 update of this block's columns past its first
+        // panel and of the next block's first panel (b + NB .. f), beside
+        // panel 0 of this block
+        const int pb = b - BW;
+        std::vector<int> chunk;   // column chunks of P's depth-128 product on its far columns f..n
+        if (B > 0) {
+            for (int j = 0; j < LU_QB; ++j)
+                swap(B - 1, j, pb + j * NB, NB, b + NB, f, 0, 0, LU_SWAP | LU_TRSM | LU_CORR, pb);
+            gemm(b, n, b + NB, f, pb, b);
+            const int nch = std::max(1, np - 1);
+            for (int c = 0; c <= nch; ++c) chunk.push_back(f + (int)((long)(n - f) * c / nch / 64 * 64));
+            chunk.back() = n;
+        }
+        // P's interchanges, U rows and update on the columns left of it and
+        // past f, after this block's N_0 so that they do not hold it up
+        auto far_of_previous = [&]() {
+            for (int j = 0; j < LU_QB; ++j)
+                swap(B - 1, j, pb + j * NB, NB, 0, pb, f, n, LU_SWAP | LU_TRSM | LU_CORR, pb);
+        };
+        for (int j = 0; j < np; ++j) {
+            const int kj = b + j * NB, wj = std::min(NB, e - kj);
+            wait(0);   // panel j
+            swap(B, j, kj, wj, b, kj, kj + wj, f, LU_SWAP | LU_TRSM, 0);
+            gemm(kj + wj, n, kj + wj, f, kj, kj + wj);
+            if (j + 1 < np) {
+                panel(B, j + 1, kj + wj);
+                if (B > 0) {
+                    if (j == 0) far_of_previous();
+                    gemm(b, n, chunk[j], chunk[j + 1], pb, b);
+                }
+            }
+        }
+        if (B > 0 && np == 1) {
+            far_of_previous();
+            gemm(b, n, chunk[0], chunk[1], pb, b);
+        }
+    }
+    // the last block's interchanges on the columns left of it
+    if (nblk > 0) {
+        const int B = nblk - 1, b = B * BW, np = ceil_div(n - b, NB);
+        for (int j = 0; j < np; ++j) {
+            const int kj = b + j * NB;
+            swap(B, j, kj, std::min(NB, n - kj), 0, b, 0, 0, LU_SWAP, 0);
+        }
+    }
+    return ops;
+}
+
+// The paired schedule: panels in pairs (k0, k1 = k0 + 32), whose far
+// trailing update is one product of depth 64.  Its chain is one interchange
+// step and one narrow product per panel, against the blocked schedule's
+// extra steps per block (the next columns' corrections by the previous
+// block), so it is the faster one where the panel chain, not the trailing
+// products, sets the time.  Per pair:
 //   1. panel k1's columns get panel k0's interchanges, U rows and update;
-//      panel k1 is factored on s2 (the look-ahead stream) while
-//   2. the far columns get the previous pair's deferred update (below),
-//      then panel k0's interchanges and U rows in one launch (the left
-//      columns, which hold the deferred update's L rows, get the
-//      interchanges in the same launch, after the update has read them);
-//   3. panel k2 = k1 + 32's columns get panel k1's interchanges (applied
-//      to panel k0's L too, so that its rows match), the depth-32
-//      correction of rows k1..k2 by panel k0, panel k1's U rows and the
-//      depth-64 update of rows k2.. by both panels; panel k2 is factored
-//      on s2 while
+//      panel k1 is factored on the panel stream while
+//   2. the far columns get the previous pair's deferred update, then panel
+//      k0's interchanges and U rows in one launch (the left columns, which
+//      hold the deferred update's L rows, get the interchanges in the same
+//      launch, after the update has read them);
+//   3. panel k2 = k1 + 32's columns get panel k1's interchanges (applied to
+//      panel k0's L too, so that its rows match), the depth-32 correction of
+//      rows k1..k2 by panel k0, panel k1's U rows and the depth-64 update of
+//      rows k2.. by both panels; panel k2 is factored on the panel stream
+//      while
 //   4. the far columns get the same as in 3, except that the depth-64
 //      update of the far half of them is deferred to step 2 of the next
 //      pair, so that both panels of a pair overlap a trailing product.
-// A row permutation commutes with a row-wise update, so applying a later
-// panel's interchanges before an earlier panel's update gives the same
-// matrix, as long as the update's L rows get them too.  The columns left
-// of a panel get its interchanges off the critical chain.  ev_a and ev_b
-// order the two streams; s2 == nullptr runs everything on s in the same
-// order.  The move lists alternate between two buffers.
-template <typename T>
-void getrf_batched(hipStream_t s, hipStream_t s2, hipEvent_t ev_a, hipEvent_t ev_b, int n, cplx<T> *F, long ldf,
-                   long sF, int *ipiv, int *perm, long sPiv, int *swapmap, int *info, int batch)
+// Move lists alternate between two buffers.
+inline std::vector<LuOp> lu_schedule_pairs(int n, bool side)
 {
     constexpr int NB = LU_NB;
-    const long smap = (long)batch * (1 + 4 * NB);   // one move list per matrix
-    auto sm = [&](int k) { return swapmap + ((k / NB) & 1) * smap; };
-    hipStream_t sp = s2 ? s2 : s;
+    std::vector<LuOp> ops;
+    auto add = [&](LuOp o) { ops.push_back(o); };
+    auto lst = [](int k) { return (k / NB) & 1; };
+    auto swap = [&](int k, int nbw, int c0, int c1, int c2, int c3, int mode, int kc0 = 0, int kc1 = 0) {
+        if ((c1 - c0) + (c3 - c2) <= 0) return;
+        add({LU_OP_SWAP, 0, k, nbw, c0, c1, c2, c3, kc0, kc1, mode, lst(k)});
+    };
+    auto gemm = [&](int r0, int r1, int c0, int c1, int kc0, int kc1) {
+        if (r1 <= r0 || c1 <= c0 || kc1 <= kc0) return;
+        add({LU_OP_GEMM, 0, 0, 0, r0, r1, c0, c1, kc0, kc1, 0, 0});
+    };
     auto panel_side = [&](int k) {
-        if (s2) {
-            FX_CHECK(hipEventRecord(ev_a, s));
-            FX_CHECK(hipStreamWaitEvent(s2, ev_a, 0));
+        if (side) {
+            add({LU_OP_RECORD, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0});
+            add({LU_OP_WAIT, 1, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0});
         }
-        launch_panel_rows<T>(sp, n, F, ldf, sF, k, ipiv, perm, sPiv, sm(k), info, batch);
-        if (s2) FX_CHECK(hipEventRecord(ev_b, s2));
+        add({LU_OP_PANEL, side ? 1 : 0, k, std::min(NB, n - k), 0, 0, 0, 0, 0, 0, 0, lst(k)});
+        if (side) add({LU_OP_RECORD, 1, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0});
     };
     auto join = [&]() {
-        if (s2) FX_CHECK(hipStreamWaitEvent(s, ev_b, 0));
+        if (side) add({LU_OP_WAIT, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0});
     };
-    // the deferred depth-64 update: F[pr0:, pc0:] -= F[pr0:, pk0:pk1] F[pk0:pk1, pc0:]
-    int pc0 = n, pr0 = n, pk0 = 0, pk1 = 0;
-    launch_panel_rows<T>(s, n, F, ldf, sF, 0, ipiv, perm, sPiv, sm(0), info, batch);
+    int pc0 = n, pr0 = n, pk0 = 0, pk1 = 0;   // the deferred update: F[pr0:, pc0:] -= F[pr0:, pk0:pk1] F[pk0:pk1, pc0:]
+    add({LU_OP_PANEL, 0, 0, std::min(NB, n), 0, 0, 0, 0, 0, 0, 0, 0});
     for (int k0 = 0; k0 < n; k0 += 2 * NB) {
         const int w0 = std::min(NB, n - k0), k1 = k0 + w0;
         if (k1 >= n) {   // a last panel on its own (no far columns, nothing deferred)
-            swap_trsm<T>(s, n, F, ldf, sF, k0, w0, 0, k0, 0, 0, LU_SWAP, sm(k0), batch);
+            swap(k0, w0, 0, k0, 0, 0, LU_SWAP);
             break;
         }
         const int w1 = std::min(NB, n - k1), k2 = k1 + w1;
-        // 1. panel k1's columns
-        swap_trsm<T>(s, n, F, ldf, sF, k0, w0, k1, k2, 0, 0, LU_SWAP | LU_TRSM, sm(k0), batch);
-        lu_gemm<T>(s, F, ldf, sF, k1, n, k1, k2, k0, k1, batch);
+        swap(k0, w0, k1, k2, 0, 0, LU_SWAP | LU_TRSM);   // 1.
+        gemm(k1, n, k1, k2, k0, k1);
         panel_side(k1);
-        // 2. far and left columns: the deferred update first, on rows and L
-        //    columns that panel k0's interchanges have not reached yet (the
-        //    two stay consistent), then panel k0's interchanges on the left
-        //    and far columns and its U rows on the far ones, in one launch
-        lu_gemm<T>(s, F, ldf, sF, pr0, n, pc0, n, pk0, pk1, batch);
+        gemm(pr0, n, pc0, n, pk0, pk1);   // 2.
         pc0 = n;
-        swap_trsm<T>(s, n, F, ldf, sF, k0, w0, 0, k0, k2, n, LU_SWAP | LU_TRSM, sm(k0), batch);
+        swap(k0, w0, 0, k0, k2, n, LU_SWAP | LU_TRSM);
         join();
         if (k2 >= n) {   // panel k1 was the last
-            swap_trsm<T>(s, n, F, ldf, sF, k1, w1, 0, k1, 0, 0, LU_SWAP, sm(k1), batch);
+            swap(k1, w1, 0, k1, 0, 0, LU_SWAP);
             break;
         }
         const int w2 = std::min(NB, n - k2), k3 = k2 + w2;
-        // 3. panel k2's columns: panel k1's interchanges (on panel k0's L
-        //    columns too), the depth-32 correction of rows k1..k2 by panel
-        //    k0 and panel k1's U rows in one launch, then the depth-64
-        //    update of rows k2.. by both panels
-        swap_trsm<T>(s, n, F, ldf, sF, k1, w1, k0, k1, k2, k3, LU_SWAP | LU_CORR | LU_TRSM, sm(k1), batch, k0, k1);
-        lu_gemm<T>(s, F, ldf, sF, k2, n, k2, k3, k0, k2, batch);
+        swap(k1, w1, k0, k1, k2, k3, LU_SWAP | LU_CORR | LU_TRSM, k0, k1);   // 3.
+        gemm(k2, n, k2, k3, k0, k2);
         panel_side(k2);
-        // 4. far and left columns; the far columns past `mid` wait for the
-        //    next pair's step 2 (panel k3 = k2 + 32's columns are before mid)
-        swap_trsm<T>(s, n, F, ldf, sF, k1, w1, 0, k0, k3, n, LU_SWAP | LU_CORR | LU_TRSM, sm(k1), batch, k0, k1);
+        swap(k1, w1, 0, k0, k3, n, LU_SWAP | LU_CORR | LU_TRSM, k0, k1);   // 4.
         const int mid = std::min(n, k3 + NB + ((n - k3 - NB) / 2 + 63) / 64 * 64);
-        lu_gemm<T>(s, F, ldf, sF, k2, n, k3, mid, k0, k2, batch);
+        gemm(k2, n, k3, mid, k0, k2);
         pc0 = mid;
         pr0 = k2;
         pk0 = k0;
         pk1 = k2;
         join();
+    }
+    return ops;
+}
+
+// Which schedule: the blocked one from this order up, where the trailing
+// products outweigh the panel chain (measured: at n = 4096 and 8 matrices
+// the paired schedule factors faster, at n = 8192 and 16 the blocked one).
+constexpr int LU_BLOCKS_MIN_N = 6144;
+enum { LU_FORM_AUTO = -1, LU_FORM_PAIRS = 0, LU_FORM_BLOCKS = 1 };
+// process-wide choice (LU_FORM_AUTO: by order); both give an LU with
+// partial pivoting, equal up to rounding
+static std::atomic<int> g_lu_form{LU_FORM_AUTO};
+inline std::vector<LuOp> lu_schedule(int n, bool side, int form = LU_FORM_AUTO)
+{
+    if (form == LU_FORM_AUTO) form = g_lu_form.load(std::memory_order_relaxed);
+    if (form == LU_FORM_AUTO) form = n >= LU_BLOCKS_MIN_N ? LU_FORM_BLOCKS : LU_FORM_PAIRS;
+    return form == LU_FORM_BLOCKS ? lu_schedule_blocks(n, side) : lu_schedule_pairs(n, side);
+}
+
+// Factor `batch` matrices of order n (stride sF, leading dimension ldf) in
+// place by the schedule lu_schedule picks.  ipiv/perm: n ints per matrix
+// (stride sPiv).  swapmap: LU_LISTS * LU_LIST_INTS ints per matrix of
+// scratch.  info: one int per matrix, 0 on success, else 1 + the first
+// zero/non-finite pivot index.  s2: the panel stream (nullptr: everything
+// on s); ev_a orders s2 after s, ev_b s after s2.
+template <typename T>
+void getrf_batched(hipStream_t s, hipStream_t s2, hipEvent_t ev_a, hipEvent_t ev_b, int n, cplx<T> *F, long ldf,
+                   long sF, int *ipiv, int *perm, long sPiv, int *swapmap, int *info, int batch)
+{
+    const long smap = (long)batch * LU_LIST_INTS;
+    for (const LuOp &o : lu_schedule(n, s2 != nullptr)) {
+        hipStream_t st = (o.side && s2) ? s2 : s;
+        int *sm = swapmap + o.list * smap;
+        switch (o.kind) {
+        case LU_OP_PANEL:
+            launch_panel_rows<T>(st, n, F, ldf, sF, o.k, ipiv, perm, sPiv, sm, info, batch);
+            break;
+        case LU_OP_SWAP:
+            swap_trsm<T>(st, n, F, ldf, sF, o.k, o.nbw, o.c0, o.c1, o.c2, o.c3, o.mode, sm, batch, o.kc0, o.kc1);
+            break;
+        case LU_OP_GEMM:
+            lu_gemm<T>(st, F, ldf, sF, o.c0, o.c1, o.c2, o.c3, o.kc0, o.kc1, batch);
+            break;
+        case LU_OP_RECORD:
+            FX_CHECK(hipEventRecord(o.side ? ev_b : ev_a, st));
+            break;
+        case LU_OP_WAIT:
+            FX_CHECK(hipStreamWaitEvent(st, o.side ? ev_a : ev_b, 0));
+            break;
+        }
     }
     hipLaunchKernelGGL((lu_finish_kernel<T>), dim3(batch), dim3(256), 0, s, n, F, ldf, sF, info);
     FX_LAUNCH_CHECK();

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <vector>
 
 #include "common.hpp"
 #include "feastx.h"
@@ -34,36 +35,52 @@ __global__ __launch_bounds__(256) void tune_fill_kernel(T *p, long cnt)
     }
 }
 
-// Rates of the variants of one precision on the two shapes; the buffers hold
-// F (batch matrices nt x nt) and Y (batch blocks nt x mt).
+// Rates of the variants of one precision per depth class; the buffers hold
+// F (batch matrices nt x nt) and Y (batch blocks nt x mt).  Class 0 is timed
+// on a depth-64 product of nt - 64 rows and columns (the LU's panel updates
+// and the Cholesky updates); class 1 on a depth-128 product of nt - 128 rows
+// and columns (the LU's block updates) together with a depth-256 product of
+// nt - 256 rows and mt columns (the solve updates), at the rate of the two
+// together.
 template <typename T>
 static void time_variants(hipStream_t s, int nt, int mt, int batch, cplx<T> *F, cplx<T> *Y, hipEvent_t e0,
                           hipEvent_t e1, double tf[GEMM_CLASSES][GEMM_VARIANTS])
 {
+    struct Shape {
+        int m, ncol, d;
+        const cplx<T> *A, *B;
+        cplx<T> *C;
+        long sB, sC;
+    };
     const long sF = (long)nt * nt, sY = (long)nt * mt;
+    auto square = [&](int d) { return Shape{nt - d, nt - d, d, F + d, F + (long)d * nt, F + d + (long)d * nt, sF, sF}; };
     for (int c = 0; c < GEMM_CLASSES; ++c) {
-        const int d = c == 0 ? 64 : 256;
-        if (nt <= d) continue;
-        const int m = nt - d, ncol = c == 0 ? nt - d : mt;
-        const cplx<T> *A = F + d, *B = c == 0 ? F + (long)d * nt : Y;
-        cplx<T> *C = c == 0 ? F + d + (long)d * nt : Y + d;
-        const long sB = c == 0 ? sF : sY, sC = c == 0 ? sF : sY;
+        std::vector<Shape> sh;
+        if (c == 0 && nt > 64) sh.push_back(square(64));
+        if (c == 1 && nt > 128) sh.push_back(square(128));
+        if (c == 1 && nt > 256) sh.push_back(Shape{nt - 256, mt, 256, F + 256, Y, Y + 256, sY, sY});
+        if (sh.empty()) continue;
+        double flops = 0;
+        for (const Shape &q : sh) flops += 8.0 * q.m * (double)q.ncol * q.d * batch;
+        auto run = [&](int v) {
+            for (const Shape &q : sh)
+                gemm_variant<T>(s, v, q.m, q.ncol, q.d, T(-1), q.A, nt, sF, q.B, nt, q.sB, T(1), q.C, nt, q.sC,
+                                batch);
+        };
         // one untimed launch of each variant, then rounds that visit the
         // variants in turn; each keeps its best round, so clock ramps and
         // other transients do not favour whichever variant runs later
-        for (int v = 0; v < GEMM_VARIANTS; ++v)
-            gemm_variant<T>(s, v, m, ncol, d, T(-1), A, nt, sF, B, nt, sB, T(1), C, nt, sC, batch);
+        for (int v = 0; v < GEMM_VARIANTS; ++v) run(v);
         constexpr int rounds = 3, reps = 3;
         for (int r = 0; r < rounds; ++r)
             for (int v = 0; v < GEMM_VARIANTS; ++v) {
                 FX_CHECK(hipEventRecord(e0, s));
-                for (int q = 0; q < reps; ++q)
-                    gemm_variant<T>(s, v, m, ncol, d, T(-1), A, nt, sF, B, nt, sB, T(1), C, nt, sC, batch);
+                for (int q = 0; q < reps; ++q) run(v);
                 FX_CHECK(hipEventRecord(e1, s));
                 FX_CHECK(hipEventSynchronize(e1));
                 float ms = 0;
                 FX_CHECK(hipEventElapsedTime(&ms, e0, e1));
-                const double rate = ms > 0 ? 8.0 * m * (double)ncol * d * batch * reps / (ms * 1e-3) / 1e12 : 0.0;
+                const double rate = ms > 0 ? flops * reps / (ms * 1e-3) / 1e12 : 0.0;
                 tf[c][v] = std::max(tf[c][v], rate);
             }
     }

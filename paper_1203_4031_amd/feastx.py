@@ -111,6 +111,9 @@ def lib():
         L.feast_get_tiles.argtypes = [C.POINTER(feast_tiles)]
         L.feast_get_tiles.restype = None
         L.feast_set_tiles.argtypes = [C.POINTER(feast_tiles)]
+        L.feast_lu_schedule.argtypes = [C.c_int, C.c_int, C.c_int, ip, C.c_int]
+        L.feast_set_lu_form.argtypes = [C.c_int]
+        L.feast_get_lu_form.argtypes = []
         L.feast_version.restype = C.c_char_p
         for name in ("feast_solve_batched_d", "feast_solve_batched_z"):
             f = getattr(L, name)
@@ -365,6 +368,40 @@ def tiles() -> dict:
     t = feast_tiles()
     lib().feast_get_tiles(C.byref(t))
     return _tiles_dict(t)["choice"]
+
+
+LU_OP_INTS = 12
+LU_OP_FIELDS = ("kind", "side", "k", "nbw", "c0", "c1", "c2", "c3", "kc0", "kc1", "mode", "list")
+
+
+LU_FORMS = {"auto": -1, "pairs": 0, "blocks": 1}
+
+
+def lu_schedule(n: int, side: bool, form: str = "auto") -> np.ndarray:
+    """feast_lu_schedule: the factorisation's launch steps for order n, one
+    row of LU_OP_FIELDS per step (host logic only, no device call).  form:
+    "auto" (what the library runs), "pairs" or "blocks"."""
+    f = LU_FORMS[form]
+    cnt = lib().feast_lu_schedule(int(n), int(bool(side)), f, None, 0)
+    if cnt < 0:
+        raise ValueError(f"feast_lu_schedule: {cnt}")
+    ops = np.zeros((cnt, LU_OP_INTS), dtype=np.int32)
+    got = lib().feast_lu_schedule(int(n), int(bool(side)), f, ops.ctypes.data_as(C.POINTER(C.c_int)), cnt)
+    assert got == cnt
+    return ops
+
+
+def set_lu_form(form: str) -> None:
+    """feast_set_lu_form: the factorisation schedule of later solves
+    ("auto", "pairs" or "blocks")."""
+    if lib().feast_set_lu_form(LU_FORMS[form]) != 0:
+        raise ValueError(f"feast_set_lu_form: {form}")
+
+
+def lu_form() -> str:
+    """The current factorisation schedule setting."""
+    v = lib().feast_get_lu_form()
+    return next(k for k, f in LU_FORMS.items() if f == v)
 
 
 def set_tiles(choice: dict) -> None:
