@@ -601,7 +601,12 @@ constexpr double CHOL_DROP = 1e-12;    // scaled Cholesky pivots at or below thi
 
 // B-orthonormal basis by diagonal scaling and Cholesky with column dropping
 // (columns visited in order of decreasing B-norm).  Returns the rank kept;
-// Tm (m x rank) receives T.
+// Tm (m x rank) receives T.  Returns -1 when a pivot comes out below
+// -INDEFINITE: visiting columns in a fixed order does not reveal rank, so a
+// nearly dependent column kept just above the drop threshold can amplify
+// rounding in the later pivots (seen with complex64 solves, whose noise puts
+// such columns near the threshold).  The caller then takes the
+// eigendecomposition, which decides definiteness from Bq's eigenvalues.
 template <bool CPLX>
 static int bortho_cholesky(Workspace &ws, hipStream_t s, int m, F64<CPLX> *Bq, F64<CPLX> *Tm)
 {
@@ -642,7 +647,7 @@ static int bortho_cholesky(Workspace &ws, hipStream_t s, int m, F64<CPLX> *Bq, F
     FX_CHECK(hipMemcpyAsync(h_i, status, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
     FX_CHECK(hipMemcpyAsync(h_i + 4, keepf, sizeof(int) * m, hipMemcpyDeviceToHost, s));
     FX_CHECK(hipStreamSynchronize(s));
-    if (h_i[0] != 0) throw solver_error{-3};
+    if (h_i[0] != 0) return -1;
     const int r = h_i[1];
     if (r < 1) throw solver_error{-3};
     // kept positions in Cholesky order -> original indices
@@ -1133,11 +1138,13 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
 
         // ---- reduced problem.  B-orthonormal basis T of the kept columns
         //      (T^H Bq T = I), then eig(T^H Aq T) = (lambda, V), Phi = T V.
-        int keep = 0;
-        if (m0 <= CHOL_MAXM)
-            keep = bortho_cholesky<CPLX>(ws, s, m0, Bq, Tm);
-        else
+        int keep = -1;
+        if (m0 <= CHOL_MAXM) keep = bortho_cholesky<CPLX>(ws, s, m0, Bq, Tm);
+        if (keep < 0) {
+            if (g_debug && m0 <= CHOL_MAXM)
+                std::fprintf(stderr, "feastx: loop %d: negative Cholesky pivot, Bq by eigendecomposition\n", k);
             keep = bortho_eigen<CPLX>(ws, s, m0, Bq, Wb, beta, Tm, st);
+        }
         dgemm<CPLX>(ws, s, false, m0, keep, m0, 1.0, Aq, m0, Tm, m0, 0.0, Tmp, m0);
         dgemm<CPLX>(ws, s, true, keep, keep, m0, 1.0, Tm, m0, Tmp, m0, 0.0, Cr, keep);
         hipLaunchKernelGGL((hermitian_part_kernel<CPLX>), grid1((long)keep * keep), dim3(256), 0, s, keep, Cr,
