@@ -55,9 +55,9 @@ PEAK_FP64_MFMA = 78.6
 # bortho.hpp and the tuner in tune.hpp do not) -- and for that table:
 # `traffic` is null otherwise.
 TRAFFIC = {   # profiles/hbm_traffic_hermgen_n8192_m0600_fp64.md, profiles/hbm_traffic_realgen_n4096_m0300.md
-    "hermgen_n8192_fp64": (1.9486e+09, "7c0126798c1c09d1a0b25605498c39c30cf7b0009d63fbdb51b86951c86725b6",
+    "hermgen_n8192_fp64": (1.5337e+09, "f11cd47c3fa8c00cc0aaefb19c75f2be139cd115e815f7fae901bb777bacc756",
                            {"depth<=64": 0, "deeper": 0}),
-    "realgen_n4096_mixed": (1.1894e+08, "7c0126798c1c09d1a0b25605498c39c30cf7b0009d63fbdb51b86951c86725b6",
+    "realgen_n4096_mixed": (1.1890e+08, "f11cd47c3fa8c00cc0aaefb19c75f2be139cd115e815f7fae901bb777bacc756",
                             {"depth<=64": 0, "deeper": 0}),
 }
 
