@@ -93,10 +93,11 @@ typedef struct {
 typedef struct {
     double t_total, t_shift, t_factor, t_solve, t_accum, t_rr, t_reduced, t_resid;
     double t_lu_gemm;        /* with feast_set_timing(1): time inside the complex matrix-product
-                                launches in the solve's factor precision (complex64 for mixed,
-                                complex128 for FP64): LU trailing updates, triangular-solve updates
-                                and, in FP64 solves of complex pencils, the loop's other complex128
-                                products (Rayleigh-Ritz, Ritz vectors) */
+                                launches of one precision: complex128 for FP64 and for mixed solves
+                                with at least half of their nodes in complex128 (fp64_nodes >=
+                                ne / 2), else complex64: LU trailing updates, triangular-solve
+                                updates and, for complex128 in complex pencils, the loop's other
+                                complex128 products (Rayleigh-Ritz, Ritz vectors) */
     double lu_gemm_flops;    /* algorithmic real flops of those launches (8 per complex multiply-add) */
     long long lu_gemm_launches;
     double factor_flops;     /* ne * (8/3) N^3 */

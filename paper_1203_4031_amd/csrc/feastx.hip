@@ -269,15 +269,21 @@ static Workspace &thread_ws()
 static std::atomic<bool> g_timing{false};
 static const bool g_debug = std::getenv("FEASTX_DEBUG") != nullptr;
 static const bool g_no_lookahead = std::getenv("FEASTX_NO_LOOKAHEAD") != nullptr;   // tuning knob
-// Largest predicted per-loop contraction eta_j of a complex64 node
-// (fp64_nodes).  1e-3 keeps every node of the N = 4096 real pencil with
-// Ne = 8 in complex64 (largest eta about 5e-4) and moves the two end nodes of
-// the N = 8192 Hermitian pencil with Ne = 16 (eta about 1e-2) to complex128,
-// which takes that solve from 13 loops to 8.
-static double fp64_eta_max()
+// Node precision from the predicted per-loop contraction eta_j of a
+// complex64 node (fp64_nodes).  When no node exceeds ETA_LIMIT every node
+// stays complex64: the N = 4096 real pencil with Ne = 8 (largest eta about
+// 5e-4) then converges in as many loops as FP64.  When some node does, the
+// complex64 nodes left set the contraction per loop, so a part-way promotion
+// does not pay: on the N = 8192 Hermitian pencil with Ne = 16, moving the 2
+// nodes above 1e-3 or the 5 above 1e-5 to complex128 took 7 and 10 loops,
+// while moving the 8 above ETA_FULL took 3, as FP64 does, in less time.  So
+// then every node above ETA_FULL goes to complex128.  FEASTX_FP64_ETA sets one
+// threshold for every node instead (tuning knob).
+constexpr double ETA_LIMIT = 1e-3, ETA_FULL = 1e-6;
+static double fp64_eta_env()
 {
-    const char *e = std::getenv("FEASTX_FP64_ETA");   // tuning knob
-    return e ? std::atof(e) : 1e-3;
+    const char *e = std::getenv("FEASTX_FP64_ETA");
+    return e ? std::atof(e) : -1.0;
 }
 
 // ------------------------------------------------------------ contour
@@ -941,7 +947,13 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
             if (pb.B) b2 += h_part[SUMSQ_BLOCKS + q];
         }
         const double sA = std::sqrt(a2 / n), sB = pb.B ? std::sqrt(b2 / n) : 1.0;
-        hi_nodes = fp64_nodes(ct, sA, sB > 0 ? sB : 1.0, pb.emin, pb.emax, fp64_eta_max());
+        const double sBn = sB > 0 ? sB : 1.0, eta_env = fp64_eta_env();
+        if (eta_env >= 0.0) {
+            hi_nodes = fp64_nodes(ct, sA, sBn, pb.emin, pb.emax, eta_env);
+        } else {
+            hi_nodes = fp64_nodes(ct, sA, sBn, pb.emin, pb.emax, ETA_LIMIT);
+            if (!hi_nodes.empty()) hi_nodes = fp64_nodes(ct, sA, sBn, pb.emin, pb.emax, ETA_FULL);
+        }
         if (o.verbose) {
             std::fprintf(stderr, "feastx: ||A||_F/sqrt(N) %.3e ||B||_F/sqrt(N) %.3e, complex128 nodes:", sA, sB);
             for (int j : hi_nodes) std::fprintf(stderr, " %d", j);
@@ -955,6 +967,10 @@ static int run(const Problem &pb, const feast_opts &o, hipStream_t s, Workspace 
     G0.setup(ws, s, "", n, lo_nodes, ct, nm);
     G1.setup(ws, s, "h", n, hi_nodes, ct, nm);
     st.fp64_nodes = mixed ? (int)hi_nodes.size() : 0;
+    // per-launch timing follows the products that take most of the solve's
+    // time: in a mixed solve with at least half of its nodes in complex128,
+    // those nodes' products (at half the complex64 rate) do
+    if (g_gemm_timer && mixed && 2 * (int)hi_nodes.size() >= ne) g_gemm_timer->f64 = true;
     double2 *coef1 = hi_nodes.empty() ? nullptr
                                       : static_cast<double2 *>(ws.get("coef_h", sizeof(double2) * hi_nodes.size() * m0));
     double *h_beta = static_cast<double *>(ws.pinned("h_beta", sizeof(double) * m0));
