@@ -54,8 +54,10 @@ PEAK_FP64_MFMA = 78.6
 # launches it in a solve (the FP64 reduced-problem kernels in jacobi.hpp and
 # bortho.hpp and the tuner in tune.hpp do not) -- and for that table:
 # `traffic` is null otherwise.
-TRAFFIC = {   # profiles/hbm_traffic_hermgen_n8192_m0600_mixed.md
+TRAFFIC = {   # profiles/hbm_traffic_hermgen_n8192_m0600_mixed.md, profiles/hbm_traffic_realgen_n4096_m0300.md
     "hermgen_n8192_mixed": (7.8826e+08, "8eb62fb1a654bb3796540844ed72d84486c0840249cd6c619d3dbdfdff99672e",
+                            {"depth<=64": 0, "deeper": 0}),
+    "realgen_n4096_mixed": (1.1890e+08, "8eb62fb1a654bb3796540844ed72d84486c0840249cd6c619d3dbdfdff99672e",
                             {"depth<=64": 0, "deeper": 0}),
 }
 
