@@ -447,6 +447,17 @@ def batched(feastx, problems, concurrency):
     return out
 
 
+def hbm_used_gb():
+    """Device memory in use on the current GPU (GB), or None if it cannot be read."""
+    try:
+        import torch
+
+        free, total = torch.cuda.mem_get_info()
+        return (total - free) / 1e9
+    except Exception:   # no device, or the query failed: the figure is left out
+        return None
+
+
 def serving(feastx, pool, reqs, per_size, slots, budget_gb):
     """Replays the request stream against the request loop, each request
     submitted at its arrival time (host arrays), mixed and FP64: completed
@@ -463,8 +474,14 @@ def serving(feastx, pool, reqs, per_size, slots, budget_gb):
     for prec in ("mixed", "fp64"):
         import queue
 
+        hbm = {"base": hbm_used_gb(), "max": None}
         srv = feastx.Server(slots=slots, hbm_budget_gb=budget_gb)
         pending, results = queue.Queue(), []
+
+        def sample_hbm():
+            used = hbm_used_gb()
+            if used is not None and (hbm["max"] is None or used > hbm["max"]):
+                hbm["max"] = used
 
         def collect():
             while True:
@@ -473,6 +490,8 @@ def serving(feastx, pool, reqs, per_size, slots, budget_gb):
                     return
                 rid, q, t_sub = item
                 results.append((srv.wait(rid), q, t_sub))
+                if len(results) % 25 == 0:
+                    sample_hbm()
 
         th = threading.Thread(target=collect, daemon=True)
         th.start()
@@ -488,6 +507,8 @@ def serving(feastx, pool, reqs, per_size, slots, budget_gb):
             rid = srv.submit(A, B, q["emin"], q["emax"], q["m0"], X0=x0[q["x0_seed"]], ne=8, tol=1e-10,
                              precision=prec)
             pending.put((rid, q, t_sub))
+            if i % 25 == 0:
+                sample_hbm()
         pending.put(None)
         th.join()
         wall = time.perf_counter() - t0
@@ -513,6 +534,11 @@ def serving(feastx, pool, reqs, per_size, slots, budget_gb):
         out[key + "latency_ms"] = {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                                    "max": float(lat.max())}
         out[key + "in_flight_max"] = inflight_max
+        # device memory in use (all of it, as the driver reports it), sampled every 25 submissions and
+        # completions: the request loop's workspaces on top of what was in use before it started
+        out[key + "hbm_gb"] = {"before": hbm["base"], "max_during": hbm["max"],
+                               "max_added": (hbm["max"] - hbm["base"]
+                                             if hbm["max"] is not None and hbm["base"] is not None else None)}
         out[key + "wall_s"] = wall
         log(f"serving {prec}: {len(reqs)} requests in {wall:.2f}s, p50 {out[key + 'latency_ms']['p50']:.1f} ms, "
             f"p99 {out[key + 'latency_ms']['p99']:.1f} ms")
