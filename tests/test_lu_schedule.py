@@ -164,7 +164,7 @@ def test_schedule_factors(n, side, form):
 
 
 @pytest.mark.parametrize("form", FORMS)
-@pytest.mark.parametrize("n", [100, 257, 385, 700, 1100])
+@pytest.mark.parametrize("n", [100, 257, 385, 700, 1100, 4096, 6144, 8192])
 def test_schedule_two_streams_race_free(n, form):
     ops = _ops(n, True, form)
     assert any(o["side"] for o in ops)
