@@ -24,7 +24,7 @@ PANEL, SWAP, GEMM, RECORD, WAIT = range(5)
 LU_NB = 32
 CORR_MAX = 3 * LU_NB
 
-SIZES = [1, 5, 31, 32, 33, 64, 100, 127, 128, 129, 200, 255, 256, 257, 300, 383, 384, 385, 512, 600, 700]
+SIZES = [1, 5, 31, 32, 33, 64, 100, 127, 128, 129, 200, 255, 256, 257, 300, 383, 384, 385, 512, 600, 700, 1100]
 
 
 FORMS = ["pairs", "blocks"]
